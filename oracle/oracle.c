@@ -1,0 +1,820 @@
+/*
+ * oracle.c -- plain, slow, FP64 CPU reference for the parabolic-operator
+ * advance of Caplan et al., "Advancing parabolic operators in thermodynamic
+ * MHD models II" (arXiv 2403.01004).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the library's GPU path includes,
+ * links or calls this file; only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg load it.  It shares no code, header or table
+ * with the GPU path.
+ *
+ * What it computes, step by step in the paper's order:
+ *   - the split parabolic operator F(u) of Eq. (par), in the two forms of
+ *     Eq. (visc)/(tc): an isotropic 7-point finite-volume Laplacian with a
+ *     cell coefficient c = scale * T0^expo (artificial viscosity; constant
+ *     coefficient when T0 is absent) and a field-aligned conduction operator
+ *     div(kappa bhat bhat . grad T) with lagged kappa = kappa0 T0^{5/2}.
+ *     The paper gives only the continuous operators; the discretisation is
+ *     this project's reading (finite volume on the spherical mesh; the
+ *     field-aligned term as L = G^T W K G over cell corners, with G the
+ *     corner gradient averaged over four cell-centre differences per
+ *     direction, K = kappa bhat bhat^T and W the corner dual volume),
+ *     which is symmetric positive semi-definite by construction;
+ *   - the explicit Euler limit dt_E = 2 / rho, rho a Gershgorin bound on
+ *     V^{-1} L (App. A uses dt_Euler without defining it);
+ *   - the practical time step limit of Eqs. (ptl)-(ptl3): the one-sided
+ *     ratio -(u_k - u_nb)/(F_k - F_nb) over the six face neighbours of the
+ *     cell k where |F| is largest (Sec. 2);
+ *   - dynamic cycling: the PTL re-evaluated after every cycle (Sec. 2, last
+ *     paragraph), reading "number of cycles" as n = ceil(t_rem / dt_PTL)
+ *     with the remaining time split equally, dt_c = t_rem / n;
+ *   - RKG2 (alpha = 3/2) super time stepping with the coefficients of
+ *     App. A, and RKL2 with the coefficients of Meyer, Balsara & Aslam
+ *     (2014), the paper's reference for RKL2 (Sec. 3.1); stage counts from
+ *     the App. A formula (RKG2) and its RKL2 analogue, with the odd-stage
+ *     rule of Sec. 3.1 / App. A;
+ *   - Backward Euler (Sec. 3.1) solved by textbook point-Jacobi
+ *     preconditioned conjugate gradients (PC1 of Sec. 3.1) on the
+ *     symmetric system (V + dt L) x = V u^n + dt h.
+ *
+ * Index conventions: cell (c,i,j,k) -> ((c*nr+i)*nt+j)*np+k, k fastest;
+ * corner (ic,jc,kc) with ic in [0,nr], jc in [0,nt], kc in [0,np) sits at
+ * (r_faces[ic], t_faces[jc], p_faces[kc]) and touches cells
+ * {ic-1,ic} x {jc-1,jc} x {kc-1,kc} (kc-1 taken periodically).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "oracle_api.h"
+
+#define OR_ISO7 0
+#define OR_ALIGNED 1
+#define OR_DIRICHLET 0
+#define OR_NOFLUX 1
+
+struct or_ctx {
+    int nr, nt, np, nc, op, bc_in, bc_out;
+    double *R, *TH, *PH;     /* faces */
+    double *rc, *tc, *pc;    /* centres */
+    double period;
+    double *coef;            /* cell coefficient c, [nr*nt*np] */
+    double *bhat;            /* corner unit field [3][(nr+1)(nt+1)np] */
+    double *ub_in, *ub_out;  /* [nc][nt][np] */
+    double *fbuf;            /* corner flux scratch [3][(nr+1)(nt+1)np] */
+};
+
+static size_t cell_ix(const or_ctx* o, int c, int i, int j, int k)
+{
+    return (((size_t)c * o->nr + i) * o->nt + j) * o->np + k;
+}
+static size_t corner_ix(const or_ctx* o, int ic, int jc, int kc)
+{
+    return ((size_t)ic * (o->nt + 1) + jc) * o->np + kc;
+}
+static size_t ncell(const or_ctx* o) { return (size_t)o->nr * o->nt * o->np; }
+static size_t ncorner(const or_ctx* o) { return (size_t)(o->nr + 1) * (o->nt + 1) * o->np; }
+
+/* ---------------------------------------------------------------- geometry */
+
+/* finite-volume cell volume: integral of r^2 sin(theta) dr dtheta dphi */
+double or_volume(const or_ctx* o, int i, int j, int k)
+{
+    const double* R = o->R;
+    return (R[i + 1] * R[i + 1] * R[i + 1] - R[i] * R[i] * R[i]) / 3.0 *
+           (cos(o->TH[j]) - cos(o->TH[j + 1])) * (o->PH[k + 1] - o->PH[k]);
+}
+
+/* distance in phi between the centres of cells k-1 and k (periodic) */
+static double dphi_centres(const or_ctx* o, int k)
+{
+    if (k == 0) return o->pc[0] + o->period - o->pc[o->np - 1];
+    return o->pc[k] - o->pc[k - 1];
+}
+
+/* Face transmissibilities A_f / d_f (coefficient not included).
+ * r-face "ir" lies at r_faces[ir], ir in [0,nr]. */
+static double trans_r(const or_ctx* o, int ir, int j, int k)
+{
+    const double area = o->R[ir] * o->R[ir] * (cos(o->TH[j]) - cos(o->TH[j + 1])) *
+                        (o->PH[k + 1] - o->PH[k]);
+    double d;
+    if (ir == 0) d = o->rc[0] - o->R[0];
+    else if (ir == o->nr) d = o->R[o->nr] - o->rc[o->nr - 1];
+    else d = o->rc[ir] - o->rc[ir - 1];
+    return area / d;
+}
+/* theta-face jt in [1,nt-1] between cells jt-1 and jt, at radius cell i */
+static double trans_t(const or_ctx* o, int i, int jt, int k)
+{
+    const double area = sin(o->TH[jt]) * 0.5 * (o->R[i + 1] * o->R[i + 1] - o->R[i] * o->R[i]) *
+                        (o->PH[k + 1] - o->PH[k]);
+    const double d = o->rc[i] * (o->tc[jt] - o->tc[jt - 1]);
+    return area / d;
+}
+/* phi-face between cells k-1 and k (periodic), at (i,j) */
+static double trans_p(const or_ctx* o, int i, int j, int k)
+{
+    const double area = 0.5 * (o->R[i + 1] * o->R[i + 1] - o->R[i] * o->R[i]) *
+                        (o->TH[j + 1] - o->TH[j]);
+    const double d = o->rc[i] * sin(o->tc[j]) * dphi_centres(o, k);
+    return area / d;
+}
+
+/* corner metric: centre-to-centre distances used by the corner gradient and
+ * the corner dual volume W (half the radial extent at the two radial
+ * boundaries, where one side of the corner is a mirror ghost cell). */
+static void corner_metric(const or_ctx* o, int ic, int jc, int kc, double* hr, double* ht,
+                          double* hp, double* W)
+{
+    double wr;
+    if (ic == 0) {
+        *hr = 2.0 * (o->rc[0] - o->R[0]);
+        wr = 0.5 * *hr;
+    } else if (ic == o->nr) {
+        *hr = 2.0 * (o->R[o->nr] - o->rc[o->nr - 1]);
+        wr = 0.5 * *hr;
+    } else {
+        *hr = o->rc[ic] - o->rc[ic - 1];
+        wr = *hr;
+    }
+    *ht = o->R[ic] * (o->tc[jc] - o->tc[jc - 1]);
+    *hp = o->R[ic] * sin(o->TH[jc]) * dphi_centres(o, kc);
+    *W = wr * *ht * *hp;
+}
+
+/* ------------------------------------------------------------- lifecycle */
+
+or_ctx* or_create(int nr, int nt, int np, int nc, const double* r_faces, const double* t_faces,
+                  const double* p_faces, int op, int bc_in, int bc_out)
+{
+    if (nr < 1 || nt < 2 || np < 3 || nc < 1) return NULL;
+    or_ctx* o = (or_ctx*)calloc(1, sizeof(or_ctx));
+    o->nr = nr; o->nt = nt; o->np = np; o->nc = nc; o->op = op;
+    o->bc_in = bc_in; o->bc_out = bc_out;
+    o->R = (double*)malloc(sizeof(double) * (nr + 1));
+    o->TH = (double*)malloc(sizeof(double) * (nt + 1));
+    o->PH = (double*)malloc(sizeof(double) * (np + 1));
+    memcpy(o->R, r_faces, sizeof(double) * (nr + 1));
+    memcpy(o->TH, t_faces, sizeof(double) * (nt + 1));
+    memcpy(o->PH, p_faces, sizeof(double) * (np + 1));
+    o->rc = (double*)malloc(sizeof(double) * nr);
+    o->tc = (double*)malloc(sizeof(double) * nt);
+    o->pc = (double*)malloc(sizeof(double) * np);
+    for (int i = 0; i < nr; ++i) o->rc[i] = 0.5 * (o->R[i] + o->R[i + 1]);
+    for (int j = 0; j < nt; ++j) o->tc[j] = 0.5 * (o->TH[j] + o->TH[j + 1]);
+    for (int k = 0; k < np; ++k) o->pc[k] = 0.5 * (o->PH[k] + o->PH[k + 1]);
+    o->period = o->PH[np] - o->PH[0];
+    o->coef = (double*)malloc(sizeof(double) * ncell(o));
+    for (size_t m = 0; m < ncell(o); ++m) o->coef[m] = 1.0;
+    o->ub_in = (double*)calloc((size_t)nc * nt * np, sizeof(double));
+    o->ub_out = (double*)calloc((size_t)nc * nt * np, sizeof(double));
+    if (op == OR_ALIGNED) {
+        o->bhat = (double*)calloc(3 * ncorner(o), sizeof(double));
+        o->fbuf = (double*)calloc(3 * ncorner(o), sizeof(double));
+    }
+    return o;
+}
+
+void or_destroy(or_ctx* o)
+{
+    if (!o) return;
+    free(o->R); free(o->TH); free(o->PH); free(o->rc); free(o->tc); free(o->pc);
+    free(o->coef); free(o->bhat); free(o->ub_in); free(o->ub_out); free(o->fbuf);
+    free(o);
+}
+
+/* Lagged diffusivity (Eq. tc, T0 = previous temperature): c = scale*T0^expo,
+ * or the constant `scale` when T0 is NULL.  B: corner field, normalised here
+ * to bhat = B/|B| (zero where |B| = 0).  Returns 0, or -1 on a non-finite
+ * or negative coefficient. */
+int or_set_coefficients(or_ctx* o, const double* T0, double scale, double expo, const double* B)
+{
+    const size_t n = ncell(o);
+    for (size_t m = 0; m < n; ++m) {
+        const double c = T0 ? scale * pow(T0[m], expo) : scale;
+        if (!isfinite(c) || c < 0.0) return -1;
+        o->coef[m] = c;
+    }
+    if (o->op == OR_ALIGNED) {
+        if (!B) return -1;
+        const size_t nn = ncorner(o);
+        for (size_t q = 0; q < nn; ++q) {
+            const double bx = B[q], by = B[nn + q], bz = B[2 * nn + q];
+            const double mag = sqrt(bx * bx + by * by + bz * bz);
+            if (!isfinite(mag)) return -1;
+            if (mag > 0.0) {
+                o->bhat[q] = bx / mag; o->bhat[nn + q] = by / mag; o->bhat[2 * nn + q] = bz / mag;
+            } else {
+                o->bhat[q] = o->bhat[nn + q] = o->bhat[2 * nn + q] = 0.0;
+            }
+        }
+    }
+    return 0;
+}
+
+void or_set_bc(or_ctx* o, const double* ub_in, const double* ub_out)
+{
+    const size_t n = (size_t)o->nc * o->nt * o->np;
+    if (ub_in) memcpy(o->ub_in, ub_in, n * sizeof(double));
+    if (ub_out) memcpy(o->ub_out, ub_out, n * sizeof(double));
+}
+
+/* --------------------------------------------------------------- operator */
+
+/* Isotropic operator, one component:  (L u)_m = sum_f c_f (A_f/d_f)(u_m - u_nb)
+ * with c_f the mean of the two cell coefficients; a Dirichlet radial face
+ * couples to the boundary value with the cell's own coefficient over the half
+ * cell distance; a no-flux face and the pole faces carry nothing.
+ * F = -(L u - h)/V, h the boundary-data part (absent when affine == 0). */
+static void apply_iso7(const or_ctx* o, int c, const double* u, double* F, int affine)
+{
+    const int nr = o->nr, nt = o->nt, np = o->np;
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < nr; ++i)
+        for (int j = 0; j < nt; ++j)
+            for (int k = 0; k < np; ++k) {
+                const size_t m = cell_ix(o, c, i, j, k);
+                const size_t mc = cell_ix(o, 0, i, j, k);
+                const double um = u[m], cm = o->coef[mc];
+                double Lu = 0.0;
+                /* radial faces */
+                if (i > 0) {
+                    const size_t nb = cell_ix(o, c, i - 1, j, k);
+                    Lu += 0.5 * (cm + o->coef[cell_ix(o, 0, i - 1, j, k)]) * trans_r(o, i, j, k) * (um - u[nb]);
+                } else if (o->bc_in == OR_DIRICHLET) {
+                    const double ub = affine ? o->ub_in[((size_t)c * nt + j) * np + k] : 0.0;
+                    Lu += cm * trans_r(o, 0, j, k) * (um - ub);
+                }
+                if (i < nr - 1) {
+                    const size_t nb = cell_ix(o, c, i + 1, j, k);
+                    Lu += 0.5 * (cm + o->coef[cell_ix(o, 0, i + 1, j, k)]) * trans_r(o, i + 1, j, k) * (um - u[nb]);
+                } else if (o->bc_out == OR_DIRICHLET) {
+                    const double ub = affine ? o->ub_out[((size_t)c * nt + j) * np + k] : 0.0;
+                    Lu += cm * trans_r(o, nr, j, k) * (um - ub);
+                }
+                /* colatitude faces (none across a pole) */
+                if (j > 0) {
+                    const size_t nb = cell_ix(o, c, i, j - 1, k);
+                    Lu += 0.5 * (cm + o->coef[cell_ix(o, 0, i, j - 1, k)]) * trans_t(o, i, j, k) * (um - u[nb]);
+                }
+                if (j < nt - 1) {
+                    const size_t nb = cell_ix(o, c, i, j + 1, k);
+                    Lu += 0.5 * (cm + o->coef[cell_ix(o, 0, i, j + 1, k)]) * trans_t(o, i, j + 1, k) * (um - u[nb]);
+                }
+                /* longitude faces (periodic) */
+                {
+                    const int km = (k + np - 1) % np, kp = (k + 1) % np;
+                    Lu += 0.5 * (cm + o->coef[cell_ix(o, 0, i, j, km)]) * trans_p(o, i, j, k) * (um - u[cell_ix(o, c, i, j, km)]);
+                    Lu += 0.5 * (cm + o->coef[cell_ix(o, 0, i, j, kp)]) * trans_p(o, i, j, kp) * (um - u[cell_ix(o, c, i, j, kp)]);
+                }
+                F[m] = -Lu / or_volume(o, i, j, k);
+            }
+}
+
+/* For corner (ic,jc,kc): the value seen at slot (a,b,e) in {0,1}^3 (a radial:
+ * 0 lower / 1 upper, b colatitude, e longitude).  Real cells give their
+ * value; the mirror ghost across a radial boundary gives 2 u_b - u
+ * (Dirichlet) or u (no flux), with u_b = 0 in linear mode. */
+static void corner_values(const or_ctx* o, int c, const double* u, int ic, int jc, int kc,
+                          int affine, double x[2][2][2])
+{
+    const int np = o->np, nt = o->nt;
+    const int ks[2] = {(kc + np - 1) % np, kc};
+    const int js[2] = {jc - 1, jc};
+    for (int b = 0; b < 2; ++b)
+        for (int e = 0; e < 2; ++e) {
+            for (int a = 0; a < 2; ++a) {
+                const int i = ic - 1 + a;
+                if (i >= 0 && i < o->nr) x[a][b][e] = u[cell_ix(o, c, i, js[b], ks[e])];
+            }
+            if (ic == 0) {
+                const double ur = x[1][b][e];
+                const double ub = affine ? o->ub_in[((size_t)c * nt + js[b]) * np + ks[e]] : 0.0;
+                x[0][b][e] = (o->bc_in == OR_DIRICHLET) ? 2.0 * ub - ur : ur;
+            } else if (ic == o->nr) {
+                const double ur = x[0][b][e];
+                const double ub = affine ? o->ub_out[((size_t)c * nt + js[b]) * np + ks[e]] : 0.0;
+                x[1][b][e] = (o->bc_out == OR_DIRICHLET) ? 2.0 * ub - ur : ur;
+            }
+        }
+}
+
+/* corner diffusivity: mean over the real cells touching the corner */
+static double corner_kappa(const or_ctx* o, int ic, int jc, int kc)
+{
+    const int np = o->np;
+    const int ks[2] = {(kc + np - 1) % np, kc};
+    double s = 0.0;
+    int n = 0;
+    for (int a = 0; a < 2; ++a) {
+        const int i = ic - 1 + a;
+        if (i < 0 || i >= o->nr) continue;
+        for (int b = 0; b < 2; ++b)
+            for (int e = 0; e < 2; ++e) { s += o->coef[cell_ix(o, 0, i, jc - 1 + b, ks[e])]; ++n; }
+    }
+    return s / n;
+}
+
+/* d g_d / d u for the real cell in slot (a,b,e) of corner (ic,...), including
+ * the chain rule through its mirror ghost at a radial boundary corner. */
+static void corner_dgdu(const or_ctx* o, int ic, int a, int b, int e, double hr, double ht,
+                        double hp, double dg[3])
+{
+    const double sr = a ? 1.0 : -1.0, st = b ? 1.0 : -1.0, sp = e ? 1.0 : -1.0;
+    dg[0] = 0.25 * sr / hr; dg[1] = 0.25 * st / ht; dg[2] = 0.25 * sp / hp;
+    int ghost = 0, bc = OR_NOFLUX;
+    if (ic == 0) { ghost = 1; bc = o->bc_in; }
+    if (ic == o->nr) { ghost = 1; bc = o->bc_out; }
+    if (ghost) {
+        const double s = (bc == OR_DIRICHLET) ? -1.0 : 1.0;   /* d u_ghost / d u */
+        dg[0] += s * 0.25 * (-sr) / hr;
+        dg[1] += s * 0.25 * st / ht;
+        dg[2] += s * 0.25 * sp / hp;
+    }
+}
+
+/* Field-aligned operator, one component.  Pass 1, per corner: the gradient
+ * g (average of four centre differences per direction), flux
+ * f = W kappa_c bhat (bhat . g).  Pass 2, per cell: (L u)_m = sum over the
+ * corners touching m of f . dg/du_m  (that is L = G^T W K G), and
+ * F = -(L u)/V.  Pole corners (jc = 0, nt) carry no flux. */
+static void apply_aligned(or_ctx* o, int c, const double* u, double* F, int affine)
+{
+    const int nr = o->nr, nt = o->nt, np = o->np;
+    const size_t nn = ncorner(o);
+    double* f = o->fbuf;
+#pragma omp parallel for schedule(static)
+    for (int ic = 0; ic <= nr; ++ic)
+        for (int jc = 0; jc <= nt; ++jc)
+            for (int kc = 0; kc < np; ++kc) {
+                const size_t q = corner_ix(o, ic, jc, kc);
+                if (jc == 0 || jc == nt) { f[q] = f[nn + q] = f[2 * nn + q] = 0.0; continue; }
+                double x[2][2][2], hr, ht, hp, W;
+                corner_values(o, c, u, ic, jc, kc, affine, x);
+                corner_metric(o, ic, jc, kc, &hr, &ht, &hp, &W);
+                double g[3] = {0.0, 0.0, 0.0};
+                for (int b = 0; b < 2; ++b)
+                    for (int e = 0; e < 2; ++e) g[0] += x[1][b][e] - x[0][b][e];
+                for (int a = 0; a < 2; ++a)
+                    for (int e = 0; e < 2; ++e) g[1] += x[a][1][e] - x[a][0][e];
+                for (int a = 0; a < 2; ++a)
+                    for (int b = 0; b < 2; ++b) g[2] += x[a][b][1] - x[a][b][0];
+                g[0] *= 0.25 / hr; g[1] *= 0.25 / ht; g[2] *= 0.25 / hp;
+                const double* bh = o->bhat;
+                const double b0 = bh[q], b1 = bh[nn + q], b2 = bh[2 * nn + q];
+                const double bg = b0 * g[0] + b1 * g[1] + b2 * g[2];
+                const double K = W * corner_kappa(o, ic, jc, kc);
+                f[q] = K * b0 * bg; f[nn + q] = K * b1 * bg; f[2 * nn + q] = K * b2 * bg;
+            }
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < nr; ++i)
+        for (int j = 0; j < nt; ++j)
+            for (int k = 0; k < np; ++k) {
+                double Lu = 0.0;
+                for (int a = 0; a < 2; ++a)          /* corner radial index ic = i + 1 - a */
+                    for (int b = 0; b < 2; ++b)
+                        for (int e = 0; e < 2; ++e) {
+                            const int ic = i + 1 - a, jc = j + 1 - b, kc = (k + 1 - e) % np;
+                            if (jc == 0 || jc == nt) continue;
+                            double hr, ht, hp, W, dg[3];
+                            corner_metric(o, ic, jc, kc, &hr, &ht, &hp, &W);
+                            /* the cell sits in slot (a,b,e) of that corner */
+                            corner_dgdu(o, ic, a, b, e, hr, ht, hp, dg);
+                            const size_t q = corner_ix(o, ic, jc, kc);
+                            Lu += f[q] * dg[0] + f[nn + q] * dg[1] + f[2 * nn + q] * dg[2];
+                        }
+                F[cell_ix(o, c, i, j, k)] = -Lu / or_volume(o, i, j, k);
+            }
+}
+
+void or_apply(or_ctx* o, const double* u, double* F, int affine)
+{
+    for (int c = 0; c < o->nc; ++c) {
+        if (o->op == OR_ISO7) apply_iso7(o, c, u, F, affine);
+        else apply_aligned(o, c, u, F, affine);
+    }
+}
+
+/* ------------------------------------------- diagonal and Euler limit */
+
+/* Row data of L for cell (i,j,k): diag = L_mm and abs_row = a Gershgorin
+ * bound on sum_n |L_mn| (exact for the 7-point operator; for the corner
+ * operator the sum over corners of the row sums of each corner's rank-one
+ * block, which bounds the exact row sum from above). */
+static void row_bounds(const or_ctx* o, int i, int j, int k, double* diag, double* absrow)
+{
+    const int nr = o->nr, nt = o->nt, np = o->np;
+    double d = 0.0, s = 0.0;
+    if (o->op == OR_ISO7) {
+        const double cm = o->coef[cell_ix(o, 0, i, j, k)];
+        double off = 0.0, C;
+        if (i > 0) { C = 0.5 * (cm + o->coef[cell_ix(o, 0, i - 1, j, k)]) * trans_r(o, i, j, k); d += C; off += C; }
+        else if (o->bc_in == OR_DIRICHLET) d += cm * trans_r(o, 0, j, k);
+        if (i < nr - 1) { C = 0.5 * (cm + o->coef[cell_ix(o, 0, i + 1, j, k)]) * trans_r(o, i + 1, j, k); d += C; off += C; }
+        else if (o->bc_out == OR_DIRICHLET) d += cm * trans_r(o, nr, j, k);
+        if (j > 0) { C = 0.5 * (cm + o->coef[cell_ix(o, 0, i, j - 1, k)]) * trans_t(o, i, j, k); d += C; off += C; }
+        if (j < nt - 1) { C = 0.5 * (cm + o->coef[cell_ix(o, 0, i, j + 1, k)]) * trans_t(o, i, j + 1, k); d += C; off += C; }
+        const int km = (k + np - 1) % np, kp = (k + 1) % np;
+        C = 0.5 * (cm + o->coef[cell_ix(o, 0, i, j, km)]) * trans_p(o, i, j, k); d += C; off += C;
+        C = 0.5 * (cm + o->coef[cell_ix(o, 0, i, j, kp)]) * trans_p(o, i, j, kp); d += C; off += C;
+        s = d + off;
+    } else {
+        const size_t nn = ncorner(o);
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b)
+                for (int e = 0; e < 2; ++e) {
+                    const int ic = i + 1 - a, jc = j + 1 - b, kc = (k + 1 - e) % np;
+                    if (jc == 0 || jc == nt) continue;
+                    double hr, ht, hp, W, dg[3];
+                    corner_metric(o, ic, jc, kc, &hr, &ht, &hp, &W);
+                    const size_t q = corner_ix(o, ic, jc, kc);
+                    const double b0 = o->bhat[q], b1 = o->bhat[nn + q], b2 = o->bhat[2 * nn + q];
+                    const double K = W * corner_kappa(o, ic, jc, kc);
+                    corner_dgdu(o, ic, a, b, e, hr, ht, hp, dg);
+                    const double vm = b0 * dg[0] + b1 * dg[1] + b2 * dg[2];
+                    /* sum over the real cells n of this corner of |bhat . dg_n| */
+                    double vsum = 0.0;
+                    const int alo = (ic == 0) ? 1 : 0, ahi = (ic == nr) ? 0 : 1;
+                    for (int a2 = alo; a2 <= ahi; ++a2)
+                        for (int b2i = 0; b2i < 2; ++b2i)
+                            for (int e2 = 0; e2 < 2; ++e2) {
+                                double dn[3];
+                                corner_dgdu(o, ic, a2, b2i, e2, hr, ht, hp, dn);
+                                vsum += fabs(b0 * dn[0] + b1 * dn[1] + b2 * dn[2]);
+                            }
+                    d += K * vm * vm;
+                    s += K * fabs(vm) * vsum;
+                }
+    }
+    *diag = d;
+    *absrow = s;
+}
+
+/* diag(L) into out[nr*nt*np] (same for every component) */
+void or_diag(const or_ctx* o, double* out)
+{
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < o->nr; ++i)
+        for (int j = 0; j < o->nt; ++j)
+            for (int k = 0; k < o->np; ++k) {
+                double d, s;
+                row_bounds(o, i, j, k, &d, &s);
+                out[cell_ix(o, 0, i, j, k)] = d;
+            }
+}
+
+/* Explicit Euler limit dt_E = 2 / max_m (sum_n |L_mn|) / V_m. */
+double or_dt_explicit(const or_ctx* o)
+{
+    double rho = 0.0;
+    for (int i = 0; i < o->nr; ++i) {
+        double rp = 0.0;
+#pragma omp parallel for reduction(max : rp) schedule(static)
+        for (int j = 0; j < o->nt; ++j)
+            for (int k = 0; k < o->np; ++k) {
+                double d, s;
+                row_bounds(o, i, j, k, &d, &s);
+                const double v = s / or_volume(o, i, j, k);
+                if (v > rp) rp = v;
+            }
+        if (rp > rho) rho = rp;
+    }
+    return rho > 0.0 ? 2.0 / rho : INFINITY;
+}
+
+/* ------------------------------------------------------ time step limit */
+
+/* Eq. (ptl3): at the cell k of largest |F| (over components and cells, ties
+ * to the lowest linear index), the minimum over the six face neighbours nb of
+ * -(u_k - u_nb)/(F_k - F_nb), taken only where du != 0, dF != 0 and
+ * du*dF < 0 (Eq. ptl2).  Neighbours: periodic in phi, none across a pole or
+ * a radial boundary.  +inf when no neighbour constrains. */
+double or_ptl_from(int nc, int nr, int nt, int np, const double* u, const double* F,
+                   int64_t* kmax)
+{
+    const size_t n = (size_t)nc * nr * nt * np;
+    size_t best = 0;
+    double fbest = -1.0;
+    for (size_t m = 0; m < n; ++m) {
+        const double a = fabs(F[m]);
+        if (a > fbest) { fbest = a; best = m; }
+    }
+    if (kmax) *kmax = (int64_t)best;
+    const int k = (int)(best % np);
+    const int j = (int)((best / np) % nt);
+    const int i = (int)((best / ((size_t)np * nt)) % nr);
+    const size_t base = best - ((size_t)i * nt + j) * np - k;   /* start of this component */
+    size_t nb[6];
+    int nnb = 0;
+    if (i > 0) nb[nnb++] = base + ((size_t)(i - 1) * nt + j) * np + k;
+    if (i < nr - 1) nb[nnb++] = base + ((size_t)(i + 1) * nt + j) * np + k;
+    if (j > 0) nb[nnb++] = base + ((size_t)i * nt + j - 1) * np + k;
+    if (j < nt - 1) nb[nnb++] = base + ((size_t)i * nt + j + 1) * np + k;
+    nb[nnb++] = base + ((size_t)i * nt + j) * np + (k + np - 1) % np;
+    nb[nnb++] = base + ((size_t)i * nt + j) * np + (k + 1) % np;
+    double dt = INFINITY;
+    for (int q = 0; q < nnb; ++q) {
+        const double du = u[best] - u[nb[q]];
+        const double dF = F[best] - F[nb[q]];
+        if (du != 0.0 && dF != 0.0 && du * dF < 0.0) {
+            const double cand = -du / dF;
+            if (cand < dt) dt = cand;
+        }
+    }
+    return dt;
+}
+
+/* Eq. (ptl2) minimised over every cell and every face direction (the
+ * full-grid form the paper mentions before adopting the F_max shortcut). */
+double or_ptl_fullgrid(int nc, int nr, int nt, int np, const double* u, const double* F)
+{
+    double dt = INFINITY;
+    for (int c = 0; c < nc; ++c)
+        for (int i = 0; i < nr; ++i)
+            for (int j = 0; j < nt; ++j)
+                for (int k = 0; k < np; ++k) {
+                    const size_t m = (((size_t)c * nr + i) * nt + j) * np + k;
+                    size_t nb[6];
+                    int nnb = 0;
+                    if (i > 0) nb[nnb++] = m - (size_t)nt * np;
+                    if (i < nr - 1) nb[nnb++] = m + (size_t)nt * np;
+                    if (j > 0) nb[nnb++] = m - np;
+                    if (j < nt - 1) nb[nnb++] = m + np;
+                    nb[nnb++] = m - k + (k + np - 1) % np;
+                    nb[nnb++] = m - k + (k + 1) % np;
+                    for (int q = 0; q < nnb; ++q) {
+                        const double du = u[m] - u[nb[q]], dF = F[m] - F[nb[q]];
+                        if (du != 0.0 && dF != 0.0 && du * dF < 0.0 && -du / dF < dt) dt = -du / dF;
+                    }
+                }
+    return dt;
+}
+
+double or_ptl(or_ctx* o, const double* u, int64_t* kmax)
+{
+    const size_t n = (size_t)o->nc * ncell(o);
+    double* F = (double*)malloc(n * sizeof(double));
+    or_apply(o, u, F, 1);
+    const double dt = or_ptl_from(o->nc, o->nr, o->nt, o->np, u, F, kmax);
+    free(F);
+    return dt;
+}
+
+/* ---------------------------------------------------------- STS tables */
+
+/* Fills mu[k], nu[k], mut[k], gam[k] for k = 1..s (index 0 unused; at k=1
+ * only mut[1] is used).  kind 0: RKL2 (Meyer, Balsara & Aslam 2014);
+ * kind 1: RKG2 with alpha = 3/2 (App. A).  Returns -1 for s < 2. */
+int or_sts_coeffs(int kind, int s, double* mu, double* nu, double* mut, double* gam)
+{
+    if (s < 2) return -1;
+    double* b = (double*)malloc(sizeof(double) * (s + 1));
+    for (int k = 0; k <= s; ++k) mu[k] = nu[k] = mut[k] = gam[k] = 0.0;
+    if (kind == 0) {
+        const double w1 = 4.0 / ((double)s * s + s - 2.0);
+        for (int j = 0; j <= s; ++j)
+            b[j] = (j <= 2) ? 1.0 / 3.0 : ((double)j * j + j - 2.0) / (2.0 * j * (j + 1.0));
+        mut[1] = b[1] * w1;
+        for (int j = 2; j <= s; ++j) {
+            mu[j] = (2.0 * j - 1.0) / j * b[j] / b[j - 1];
+            nu[j] = -(j - 1.0) / j * b[j] / b[j - 2];
+            mut[j] = mu[j] * w1;
+            gam[j] = -(1.0 - b[j - 1]) * mut[j];
+        }
+    } else {
+        const double w = 6.0 / ((s + 4.0) * (s - 1.0));
+        b[0] = 1.0;
+        b[1] = 1.0 / 3.0;
+        b[2] = 1.0 / 15.0;
+        for (int k = 3; k <= s; ++k)
+            b[k] = 4.0 * (k - 1.0) * (k + 4.0) / (3.0 * k * (k + 1.0) * (k + 2.0) * (k + 3.0));
+        mu[1] = 1.0;
+        mut[1] = w;
+        mu[2] = 0.5;
+        nu[2] = -0.1;
+        mut[2] = mu[2] * w;
+        gam[2] = 0.0;
+        for (int k = 3; k <= s; ++k) {
+            mu[k] = (2.0 + 1.0 / k) * b[k] / b[k - 1];
+            nu[k] = -(1.0 / k + 1.0) * b[k] / b[k - 2];
+            mut[k] = mu[k] * w;
+            gam[k] = (k * (k + 1.0) / 2.0 * b[k - 1] - 1.0) * mut[k];
+        }
+    }
+    free(b);
+    return 0;
+}
+
+/* Stage count for ratio = dt / dt_E: RKG2 from App. A,
+ * s = ceil(sqrt(25 + 24 ratio)/2 - 3/2); RKL2 from its stability bound
+ * dt <= dt_E (s^2 + s - 2)/4, s = ceil((sqrt(9 + 16 ratio) - 1)/2).
+ * At least 2; one more when even and force_odd (Sec. 3.1 / App. A). */
+int or_sts_stages(int kind, double ratio, int force_odd)
+{
+    double x = (kind == 0) ? 0.5 * (sqrt(9.0 + 16.0 * ratio) - 1.0)
+                           : 0.5 * sqrt(25.0 + 24.0 * ratio) - 1.5;
+    int s = (int)ceil(x);
+    if (s < 2) s = 2;
+    if (force_odd && (s % 2 == 0)) s += 1;
+    return s;
+}
+
+/* One STS cycle (App. A recurrence) of length dt with s stages, in place. */
+static void sts_cycle(or_ctx* o, double* u, double dt, int kind, int s)
+{
+    const size_t n = (size_t)o->nc * ncell(o);
+    double *mu = (double*)malloc(sizeof(double) * (s + 1)), *nu = (double*)malloc(sizeof(double) * (s + 1));
+    double *mut = (double*)malloc(sizeof(double) * (s + 1)), *gam = (double*)malloc(sizeof(double) * (s + 1));
+    or_sts_coeffs(kind, s, mu, nu, mut, gam);
+    double* u0 = (double*)malloc(n * sizeof(double));
+    double* y0 = (double*)malloc(n * sizeof(double));
+    double* ukm2 = (double*)malloc(n * sizeof(double));
+    double* ukm1 = (double*)malloc(n * sizeof(double));
+    double* uk = (double*)malloc(n * sizeof(double));
+    double* Fk = (double*)malloc(n * sizeof(double));
+    memcpy(u0, u, n * sizeof(double));
+    or_apply(o, u0, y0, 1);                                   /* y0 = F(u0) */
+    for (size_t m = 0; m < n; ++m) ukm1[m] = u0[m] + mut[1] * dt * y0[m];   /* u1 */
+    memcpy(ukm2, u0, n * sizeof(double));
+    for (int k = 2; k <= s; ++k) {
+        or_apply(o, ukm1, Fk, 1);
+        for (size_t m = 0; m < n; ++m)
+            uk[m] = mu[k] * ukm1[m] + nu[k] * ukm2[m] + (1.0 - mu[k] - nu[k]) * u0[m] +
+                    mut[k] * dt * Fk[m] + gam[k] * dt * y0[m];
+        double* t = ukm2; ukm2 = ukm1; ukm1 = uk; uk = t;
+    }
+    memcpy(u, ukm1, n * sizeof(double));
+    free(mu); free(nu); free(mut); free(gam);
+    free(u0); free(y0); free(ukm2); free(ukm1); free(uk); free(Fk);
+}
+
+/* ------------------------------------------------------------ BE + PCG */
+
+static double dot(const double* a, const double* b, size_t n)
+{
+    /* fixed-order sum so that the oracle is reproducible */
+    double s = 0.0;
+    for (size_t m = 0; m < n; ++m) s += a[m] * b[m];
+    return s;
+}
+
+/* y = M x = V x + dt L x, with L x = -V F_lin(x) */
+static void be_matvec(or_ctx* o, const double* x, double* y, double dt, double* tmp)
+{
+    or_apply(o, x, tmp, 0);
+    const size_t N = ncell(o);
+    for (int c = 0; c < o->nc; ++c)
+        for (int i = 0; i < o->nr; ++i)
+            for (int j = 0; j < o->nt; ++j)
+                for (int k = 0; k < o->np; ++k) {
+                    const size_t m = c * N + cell_ix(o, 0, i, j, k);
+                    const double V = or_volume(o, i, j, k);
+                    y[m] = V * x[m] + dt * (-V * tmp[m]);
+                }
+}
+
+/* Backward Euler step (I - dt V^{-1}(h - L.))u^{n+1} = u^n written as the
+ * SPD system (V + dt L) x = V u^n + dt h, solved by point-Jacobi PCG from
+ * x0 = u^n, stopping when ||r||_2 <= tol ||b||_2 (or after exactly
+ * force_iters iterations when > 0).  Returns 0, 4 (no convergence),
+ * 5 (breakdown: <p,Mp> <= 0 or not finite). */
+static int be_solve(or_ctx* o, double* u, double dt, double tol, int max_iter, int force_iters,
+                    int* iters, double* relres)
+{
+    const size_t N = ncell(o), n = (size_t)o->nc * N;
+    double* b = (double*)malloc(n * sizeof(double));
+    double* x = (double*)malloc(n * sizeof(double));
+    double* r = (double*)malloc(n * sizeof(double));
+    double* z = (double*)malloc(n * sizeof(double));
+    double* p = (double*)malloc(n * sizeof(double));
+    double* q = (double*)malloc(n * sizeof(double));
+    double* tmp = (double*)malloc(n * sizeof(double));
+    double* zero = (double*)calloc(n, sizeof(double));
+    double* Ld = (double*)malloc(N * sizeof(double));
+    double* D = (double*)malloc(N * sizeof(double));
+    or_diag(o, Ld);
+    for (int i = 0; i < o->nr; ++i)
+        for (int j = 0; j < o->nt; ++j)
+            for (int k = 0; k < o->np; ++k) {
+                const size_t m = cell_ix(o, 0, i, j, k);
+                D[m] = or_volume(o, i, j, k) + dt * Ld[m];
+            }
+    /* b = V u^n + dt h, with h = V F(0) the boundary-data part of F */
+    or_apply(o, zero, tmp, 1);
+    for (int c = 0; c < o->nc; ++c)
+        for (int i = 0; i < o->nr; ++i)
+            for (int j = 0; j < o->nt; ++j)
+                for (int k = 0; k < o->np; ++k) {
+                    const size_t m = c * N + cell_ix(o, 0, i, j, k);
+                    const double V = or_volume(o, i, j, k);
+                    b[m] = V * u[m] + dt * V * tmp[m];
+                }
+    memcpy(x, u, n * sizeof(double));
+    be_matvec(o, x, q, dt, tmp);
+    for (size_t m = 0; m < n; ++m) r[m] = b[m] - q[m];
+    for (size_t m = 0; m < n; ++m) z[m] = r[m] / D[m % N];
+    memcpy(p, z, n * sizeof(double));
+    double rho = dot(r, z, n);
+    const double bnorm = sqrt(dot(b, b, n));
+    double rnorm = sqrt(dot(r, r, n));
+    int it = 0, status = 0;
+    const int limit = force_iters > 0 ? force_iters : max_iter;
+    if (!(force_iters > 0) && rnorm <= tol * bnorm) goto done;
+    for (it = 1; it <= limit; ++it) {
+        be_matvec(o, p, q, dt, tmp);
+        const double pq = dot(p, q, n);
+        if (!(pq > 0.0) || !isfinite(pq)) { status = 5; break; }
+        const double alpha = rho / pq;
+        for (size_t m = 0; m < n; ++m) x[m] += alpha * p[m];
+        for (size_t m = 0; m < n; ++m) r[m] -= alpha * q[m];
+        rnorm = sqrt(dot(r, r, n));
+        if (force_iters > 0) { if (it == force_iters) break; }
+        else if (rnorm <= tol * bnorm) break;
+        for (size_t m = 0; m < n; ++m) z[m] = r[m] / D[m % N];
+        const double rho1 = dot(r, z, n);
+        const double beta = rho1 / rho;
+        for (size_t m = 0; m < n; ++m) p[m] = z[m] + beta * p[m];
+        rho = rho1;
+    }
+    if (it > limit) { it = limit; status = 4; }
+done:
+    memcpy(u, x, n * sizeof(double));
+    *iters = it;
+    *relres = bnorm > 0.0 ? rnorm / bnorm : rnorm;
+    free(b); free(x); free(r); free(z); free(p); free(q); free(tmp); free(zero); free(Ld); free(D);
+    return status;
+}
+
+/* ------------------------------------------------------- cycle control */
+
+/* Advance u over dt.  scheme 0: STS (sts_kind 0 RKL2 / 1 RKG2); scheme 1:
+ * BE + PCG.  cycles > 0: that many equal cycles, no PTL.  cycles == 0:
+ * dynamic PTL cycling -- at each cycle the PTL of the current u gives
+ * n = ceil(t_rem / dt_PTL) and the cycle length t_rem / n (Sec. 2).
+ * replay_n > 0: use the given cycle lengths instead (parity replays).
+ * ptl_floor: the limit used is max(dt_PTL, ptl_floor * dt_E).  The paper sets
+ * no lower bound; without one the limit can collapse towards zero once a
+ * cycle has flattened the limiting pair (the difference in Eq. ptl2 is then
+ * ~0 while dF is not), and a Backward Euler cycle that is then too short to
+ * move the iterate leaves it there for good.  0 disables the floor.
+ * Returns 0 or an error code (4 no convergence, 5 breakdown, 6 non-finite
+ * PTL, 8 more than max_cycles cycles). */
+int or_advance(or_ctx* o, double* u, double dt, int cycles, int scheme, int sts_kind,
+               int force_odd, int s_override, double tol, int max_iter, int force_iters,
+               int max_cycles, double ptl_floor, const double* replay_dt, int replay_n,
+               or_stats* st)
+{
+    memset(st, 0, sizeof(*st));
+    st->dt_ptl_first = st->dt_ptl_min = INFINITY;
+    const double dtE = or_dt_explicit(o);
+    st->dt_explicit = dtE;
+    double t_rem = dt;
+    int ncyc = 0, status = 0;
+    while (1) {
+        double dtc;
+        int last = 0;
+        if (replay_n > 0) {
+            dtc = replay_dt[ncyc];
+            last = (ncyc + 1 == replay_n);
+        } else if (cycles > 0) {
+            dtc = dt / cycles;
+            last = (ncyc + 1 == cycles);
+        } else {
+            int64_t km;
+            const double ptl = or_ptl(o, u, &km);
+            if (isnan(ptl) || ptl <= 0.0) { status = 6; break; }
+            if (ncyc == 0) { st->dt_ptl_first = ptl; st->k_first = km; }
+            if (ptl < st->dt_ptl_min) st->dt_ptl_min = ptl;
+            double lim = ptl;
+            if (lim < ptl_floor * dtE) { lim = ptl_floor * dtE; st->floored += 1; }
+            const double nreq = ceil(t_rem / lim);
+            if (!(nreq > 1.0)) { dtc = t_rem; last = 1; }
+            else dtc = t_rem / nreq;
+        }
+        if (ncyc >= max_cycles) { status = 8; break; }
+        if (ncyc < OR_MAX_LOG) st->dt_cycle[ncyc] = dtc;
+        if (scheme == 0) {
+            const int s = s_override > 0 ? s_override : or_sts_stages(sts_kind, dtc / dtE, force_odd);
+            if (ncyc < OR_MAX_LOG) st->s_cycle[ncyc] = s;
+            st->s_total += s;
+            if (s > st->s_max) st->s_max = s;
+            sts_cycle(o, u, dtc, sts_kind, s);
+        } else {
+            int its;
+            double rr;
+            status = be_solve(o, u, dtc, tol, max_iter, force_iters, &its, &rr);
+            if (ncyc < OR_MAX_LOG) st->s_cycle[ncyc] = its;
+            st->iters_total += its;
+            if (its > st->iters_max) st->iters_max = its;
+            st->rel_residual = rr;
+        }
+        ++ncyc;
+        if (status) break;
+        if (last) break;
+        t_rem -= dtc;
+    }
+    st->cycles = ncyc;
+    return status;
+}
