@@ -1,0 +1,187 @@
+/*
+ * paradv.h -- C ABI of the MI355X (gfx950) parabolic-operator advance library.
+ *
+ * The library advances one operator-split parabolic term du/dt = F(u)
+ * (Caplan et al., arXiv 2403.01004, Sec. 2, Eq. par) on a spherical
+ * (r, theta, phi) shell over a time step dt, with
+ *   - F the artificial-viscosity operator div(c grad u) per component or the
+ *     field-aligned Spitzer conduction operator div(kappa bhat bhat . grad T)
+ *     with lagged diffusivity kappa = kappa0 T0^{5/2} (Eqs. visc, tc);
+ *   - RKL2 or RKG2 super time stepping (Sec. 3.1, App. A), or Backward Euler
+ *     solved by point-Jacobi preconditioned CG (Sec. 3.1, PC1);
+ *   - cycling at the practical time step limit of Eqs. (ptl)-(ptl3),
+ *     re-evaluated after every cycle (Sec. 2).
+ *
+ * Discretisation (the paper gives only the continuous operators): finite
+ * volume on a mesh given by its cell faces; the isotropic operator is a
+ * 7-point stencil with face coefficients the mean of the two cell values;
+ * the field-aligned operator is a symmetric corner scheme L = G^T W K G
+ * (corner gradients averaged over four cell-centre differences, K = kappa
+ * bhat bhat^T at cell corners, W the corner dual volume).  Radial
+ * boundaries are Dirichlet (ghost 2 u_b - u) or no-flux; colatitude
+ * boundaries (the poles) carry no flux; phi is periodic.
+ *
+ * Memory layout: a field is [ncomp][nr][nt][np] contiguous, np (phi)
+ * fastest; boundary data [ncomp][nt][np]; corner arrays [3][nr+1][nt+1][np]
+ * with components (r, theta, phi) at (r_faces[ic], t_faces[jc], p_faces[kc]).
+ *
+ * Ownership: every pointer argument is borrowed for the duration of the call
+ * (the bound field: until it is re-bound or the context destroyed).  Device
+ * pointers are HIP device memory on the context's device.  The context owns
+ * only its scratch memory.
+ *
+ * Streams: all device work is queued on the stream given to pa_init; calls
+ * that return host values synchronise that stream.  One context per host
+ * thread at a time.
+ *
+ * Errors: every call returns a pa_status; pa_last_error gives a message.
+ * Argument and state errors (PA_ERR_ARG, PA_ERR_STATE) leave the bound field
+ * untouched; numerical errors (PA_ERR_NOCONV, PA_ERR_BREAKDOWN,
+ * PA_ERR_NONFINITE, PA_ERR_MAXCYCLES) leave the last iterate in the field.
+ */
+#ifndef PARADV_H
+#define PARADV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pa_ctx pa_ctx;
+
+typedef enum {
+    PA_OK = 0,
+    PA_ERR_ARG = 1,        /* invalid argument (null, size, range) */
+    PA_ERR_ALLOC = 2,      /* device allocation failed */
+    PA_ERR_HIP = 3,        /* a HIP runtime call failed */
+    PA_ERR_NOCONV = 4,     /* PCG reached max_iter without meeting tol */
+    PA_ERR_BREAKDOWN = 5,  /* PCG: <p, M p> <= 0 or not finite */
+    PA_ERR_NONFINITE = 6,  /* NaN/Inf in the field, coefficients or time-step limit */
+    PA_ERR_STATE = 7,      /* call out of order (e.g. no field or coefficients) */
+    PA_ERR_MAXCYCLES = 8   /* the time-step limit needs more than max_cycles cycles */
+} pa_status;
+
+typedef enum { PA_OP_ISO7 = 0, PA_OP_FIELD_ALIGNED = 1 } pa_op;
+typedef enum { PA_BC_DIRICHLET = 0, PA_BC_NOFLUX = 1 } pa_bc;
+typedef enum { PA_FP64 = 0, PA_FP32_STAGES = 1 } pa_prec;
+typedef enum { PA_STS_RKL2 = 0, PA_STS_RKG2 = 1 } pa_sts;
+typedef enum { PA_PC_JACOBI = 0, PA_PC_LEARNED = 1 } pa_pc;
+
+#define PA_MAX_LOG 4096
+
+/* Grid and operator description (pa_init).  The face arrays are host
+ * memory, copied during pa_init: r_faces[nr+1] and t_faces[nt+1] strictly
+ * increasing with 0 <= t_faces < = pi, p_faces[np+1] strictly increasing
+ * (one period = p_faces[np] - p_faces[0]).  nr >= 1, nt >= 2, np >= 3,
+ * ncomp >= 1.  prec selects FP64 throughout or FP32 storage and stencil
+ * arithmetic for the STS stages (FP64 recurrence coefficients, FP64
+ * combination and FP64 reductions). */
+typedef struct {
+    int32_t nr, nt, np, ncomp;
+    const double* r_faces;
+    const double* t_faces;
+    const double* p_faces;
+    int32_t op;      /* pa_op */
+    int32_t bc_in;   /* pa_bc at r_faces[0] */
+    int32_t bc_out;  /* pa_bc at r_faces[nr] */
+    int32_t prec;    /* pa_prec */
+    /* optional device allocator (e.g. a framework's caching allocator);
+     * both NULL: hipMalloc / hipFree */
+    void* (*alloc)(size_t bytes, void* user);
+    void (*free)(void* ptr, void* user);
+    void* alloc_user;
+} pa_desc;
+
+/* Solver options (pa_set_options; pa_default_options fills defaults). */
+typedef struct {
+    int32_t force_odd;    /* 1: add a stage when s is even (Sec. 3.1, App. A). default 1 */
+    int32_t s_override;   /* >0: use exactly this many stages. default 0 */
+    int32_t pc;           /* pa_pc. default PA_PC_JACOBI */
+    int32_t max_iter;     /* PCG iteration limit per solve. default 10000 */
+    int32_t max_cycles;   /* cycle limit per advance. default 100000 */
+    int32_t force_iters;  /* >0: run exactly this many PCG iterations per solve. default 0 */
+    int32_t pcg_batch;    /* PCG iterations queued between host checks. default 16 */
+    int32_t replay_n;     /* >0: cycle lengths taken from replay_dt (parity replays) */
+    const double* replay_dt; /* host, replay_n entries; copied by pa_set_options */
+    double ptl_floor;     /* limit used = max(dt_PTL, ptl_floor * dt_E). default 1.0 */
+} pa_opts;
+
+/* Per-advance statistics. */
+typedef struct {
+    int32_t cycles, s_total, s_max, iters_total, iters_max, fallbacks, floored, status;
+    int64_t k_first;          /* linear index of max |F| at the first limit evaluation */
+    double dt_explicit;       /* explicit Euler limit used */
+    double dt_ptl_first, dt_ptl_min;
+    double rel_residual;      /* PCG: ||r||/||b|| of the last solve */
+    double ms_total;          /* wall time of the call on the stream, ms */
+    double dt_cycle[PA_MAX_LOG];   /* length of each cycle */
+    int32_t per_cycle[PA_MAX_LOG]; /* stages (STS) or PCG iterations (BE) per cycle */
+} pa_stats;
+
+/* Create a context on the current HIP device; all work goes to hip_stream
+ * (NULL: the null stream).  Copies the mesh, allocates scratch. */
+pa_status pa_init(const pa_desc* desc, void* hip_stream, pa_ctx** out);
+
+/* Release everything the context owns.  NULL is ignored. */
+void pa_destroy(pa_ctx* ctx);
+
+/* Last error message of this context ("" if none); valid until the next call. */
+const char* pa_last_error(const pa_ctx* ctx);
+
+void pa_default_options(pa_opts* opts);
+pa_status pa_set_options(pa_ctx* ctx, const pa_opts* opts);
+
+/* Bind the field advanced in place: device double[ncomp][nr][nt][np]. */
+pa_status pa_bind_field(pa_ctx* ctx, double* u_dev);
+
+/* Lagged coefficients (Eq. tc: kappa from the previous temperature T0).
+ * T0_dev: device double[nr][nt][np] or NULL for the constant coefficient
+ * `scale` (viscosity nu); otherwise c = scale * T0^expo (Spitzer: 2.5).
+ * B_dev: field-aligned operator only, device double[3][nr+1][nt+1][np],
+ * normalised here to bhat = B/|B| (zero where |B| = 0).  Also computes the
+ * Jacobi diagonal and the explicit Euler limit.  PA_ERR_NONFINITE if a
+ * coefficient is NaN/Inf or negative. */
+pa_status pa_set_coefficients(pa_ctx* ctx, const double* T0_dev, double scale, double expo,
+                              const double* B_dev);
+
+/* Dirichlet boundary values at r_in and r_out, device double[ncomp][nt][np]
+ * (copied; NULL leaves that side unchanged).  Ignored on no-flux sides. */
+pa_status pa_set_bc(pa_ctx* ctx, const double* ub_in_dev, const double* ub_out_dev);
+
+/* Explicit Euler stability limit dt_E = 2 / max_m sum_n |(V^-1 L)_mn|
+ * (Gershgorin bound; App. A uses dt_Euler without a definition). */
+pa_status pa_dt_explicit(pa_ctx* ctx, double* dt_e);
+
+/* F = F(u) (affine != 0: including boundary data) or its linear part, for
+ * device arrays of the field's shape.  u_dev and F_dev must not overlap. */
+pa_status pa_apply(pa_ctx* ctx, const double* u_dev, double* F_dev, int32_t affine);
+
+/* Diagonal of L = -V dF_lin/du on one component: device double[nr][nt][np]. */
+pa_status pa_diag(pa_ctx* ctx, double* diag_dev);
+
+/* Practical time step limit of the bound field, Eq. (ptl3): at the cell k of
+ * largest |F| (ties: lowest linear index) the minimum over its six face
+ * neighbours of -(u_k - u_nb)/(F_k - F_nb) where that pair has
+ * du*dF < 0 (Eq. ptl2); +inf when none constrains.  k_lin may be NULL. */
+pa_status pa_compute_ptl(pa_ctx* ctx, double* dt_ptl, int64_t* k_lin);
+
+/* Advance the bound field over dt with RKL2 (Meyer, Balsara & Aslam 2014,
+ * the paper's RKL2 reference) or RKG2 (App. A).  cycles > 0: that many equal
+ * cycles; cycles == 0: dynamic PTL cycling (Sec. 2): each cycle takes
+ * n = ceil(t_rem / max(dt_PTL, ptl_floor dt_E)) and length t_rem / n.
+ * Stages per cycle: App. A formula (RKG2), s = ceil((sqrt(9+16 r)-1)/2)
+ * (RKL2), r = dt_cycle/dt_E, odd rule per options.  stats may be NULL. */
+pa_status pa_advance_rkl2(pa_ctx* ctx, double dt, int32_t cycles, pa_stats* stats);
+pa_status pa_advance_rkg2(pa_ctx* ctx, double dt, int32_t cycles, pa_stats* stats);
+
+/* Advance the bound field over dt with Backward Euler (Sec. 3.1): each
+ * cycle solves (V + dt_c L) x = V u + dt_c h by point-Jacobi PCG from
+ * x0 = u until ||r||_2 <= tol ||b||_2.  Cycling as pa_advance_rkl2. */
+pa_status pa_advance_be_pcg(pa_ctx* ctx, double dt, double tol, int32_t cycles, pa_stats* stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

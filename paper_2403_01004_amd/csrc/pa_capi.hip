@@ -1,0 +1,854 @@
+// pa_capi.hip -- host side of the C ABI (include/paradv.h): context, mesh
+// metrics, coefficient set-up, the practical-time-step-limit controller and
+// the RKL2 / RKG2 / Backward-Euler+PCG drivers.  Every arithmetic step on
+// field data runs in the kernels of pa_kernels.hip and pa_vec.hip; the host
+// computes only 1-D metric factors, recurrence coefficients and the cycle
+// schedule.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/paradv.h"
+#include "pa_internal.h"
+
+using namespace pa;
+
+namespace {
+
+template <class T>
+struct MetricDev {
+    T *vr = nullptr, *vt = nullptr, *vp = nullptr, *gr = nullptr, *gtr = nullptr, *gtt = nullptr,
+      *gpt = nullptr, *gpp = nullptr;
+};
+
+}  // namespace
+
+struct pa_ctx {
+    pa_desc d{};
+    hipStream_t stream = nullptr;
+    int dev = 0;
+    std::string err;
+    pa_opts opt{};
+    std::vector<double> replay;
+    size_t N = 0, NT = 0, P = 0, NCO = 0;  // cells per comp, all comps, per level, corners
+    bool fp32 = false;
+    // mesh metrics
+    MetricDev<double> m64;
+    MetricDev<float> m32;
+    double *c_hr = nullptr, *c_wr = nullptr, *c_R = nullptr, *c_htt = nullptr, *c_sT = nullptr,
+           *c_dpc = nullptr;
+    // coefficients
+    double* coef64 = nullptr;
+    float* coef32 = nullptr;
+    bool coef_var = false;
+    double cscale = 1.0;
+    double* e64 = nullptr;
+    float* e32 = nullptr;
+    double* diagL = nullptr;
+    bool have_coef = false;
+    double dtE = 0.0;
+    // boundary data
+    double *ub_in = nullptr, *ub_out = nullptr;
+    float *ub_in32 = nullptr, *ub_out32 = nullptr;
+    // field and work buffers
+    double* u = nullptr;
+    double* w[4] = {nullptr, nullptr, nullptr, nullptr};
+    float* f[4] = {nullptr, nullptr, nullptr, nullptr};
+    // reductions
+    double* part = nullptr;
+    long long* part_idx = nullptr;
+    size_t part_cap = 0;
+    DevState* st = nullptr;
+    DevState* hst = nullptr;  // pinned host mirror
+    int* flag = nullptr;
+    int* hflag = nullptr;
+    int rch = 16;
+    std::vector<void*> allocs;
+};
+
+namespace {
+
+pa_status fail(pa_ctx* c, pa_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return s;
+}
+
+#define HIPCHK(c, call)                                                                   \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail((c), PA_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_));  \
+    } while (0)
+
+void* dev_alloc(pa_ctx* c, size_t bytes)
+{
+    void* p = nullptr;
+    if (bytes == 0) bytes = 16;
+    if (c->d.alloc) p = c->d.alloc(bytes, c->d.alloc_user);
+    else if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
+    if (p) c->allocs.push_back(p);
+    return p;
+}
+
+template <class T>
+bool dev_upload(pa_ctx* c, T** dst, const std::vector<double>& src)
+{
+    std::vector<T> tmp(src.begin(), src.end());
+    *dst = (T*)dev_alloc(c, sizeof(T) * tmp.size());
+    if (!*dst) return false;
+    return hipMemcpy(*dst, tmp.data(), sizeof(T) * tmp.size(), hipMemcpyHostToDevice) == hipSuccess;
+}
+
+template <class T>
+Geo<T> geo(const pa_ctx* c, const MetricDev<T>& m)
+{
+    Geo<T> g;
+    g.nr = c->d.nr; g.nt = c->d.nt; g.np = c->d.np; g.P = (int)c->P;
+    g.vr = m.vr; g.vt = m.vt; g.vp = m.vp; g.gr = m.gr; g.gtr = m.gtr; g.gtt = m.gtt;
+    g.gpt = m.gpt; g.gpp = m.gpp;
+    return g;
+}
+
+bool ensure_parts(pa_ctx* c, size_t n)
+{
+    if (n <= c->part_cap) return true;
+    c->part = (double*)dev_alloc(c, sizeof(double) * 3 * n);
+    c->part_idx = (long long*)dev_alloc(c, sizeof(long long) * n);
+    if (!c->part || !c->part_idx) return false;
+    c->part_cap = n;
+    return true;
+}
+
+// radial levels per workgroup: enough workgroups to fill 256 CUs several
+// times over, without making each chunk so short that the two halo levels
+// dominate
+int pick_rch(int nr, int P)
+{
+    const int nbx = (P + kBlock - 1) / kBlock;
+    int rch = 32;
+    while (rch > 4 && (long long)nbx * ((nr + rch - 1) / rch) < 2048) rch /= 2;
+    return rch;
+}
+
+template <class T>
+KArgs<T> base_args(pa_ctx* c, int r_lo, int r_hi)
+{
+    KArgs<T> a;
+    memset(&a, 0, sizeof a);
+    a.bc_in = c->d.bc_in;
+    a.bc_out = c->d.bc_out;
+    a.affine = 1;
+    a.r_lo = r_lo;
+    a.r_hi = r_hi;
+    a.rch = c->rch;
+    a.nbx = (int)((c->P + kBlock - 1) / kBlock);
+    a.nrc = (r_hi - r_lo + c->rch - 1) / c->rch;
+    a.nc = c->d.ncomp;
+    a.km2 = kKm2Array;
+    a.part = c->part;
+    a.part_idx = c->part_idx;
+    a.flag = c->flag;
+    if constexpr (sizeof(T) == 8) {
+        a.coef = c->coef_var ? (const T*)c->coef64 : nullptr;
+        a.e = (const T*)c->e64;
+        a.ub_in = (const T*)c->ub_in;
+        a.ub_out = (const T*)c->ub_out;
+    } else {
+        a.coef = c->coef_var ? (const T*)c->coef32 : nullptr;
+        a.e = (const T*)c->e32;
+        a.ub_in = (const T*)c->ub_in32;
+        a.ub_out = (const T*)c->ub_out32;
+    }
+    a.cs = (T)c->cscale;
+    return a;
+}
+
+template <class T>
+void stencil(pa_ctx* c, int mode, bool virt, const KArgs<T>& a)
+{
+    if constexpr (sizeof(T) == 8) {
+        const Geo<double> g = geo(c, c->m64);
+        if (c->d.op == PA_OP_ISO7) launch_iso7<double>(mode, virt, g, a, c->stream);
+        else launch_aligned<double>(mode, virt, g, a, c->stream);
+    } else {
+        const Geo<float> g = geo(c, c->m32);
+        if (c->d.op == PA_OP_ISO7) launch_iso7<float>(mode, virt, g, a, c->stream);
+        else launch_aligned<float>(mode, virt, g, a, c->stream);
+    }
+}
+
+int ntiles(pa_ctx* c, int nlev) { return stencil_tiles((int)c->P, nlev, c->rch, c->d.ncomp); }
+
+pa_status sync_state(pa_ctx* c)
+{
+    HIPCHK(c, hipMemcpyAsync(c->hst, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->hflag, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PA_OK;
+}
+
+// ------------------------------------------------------------ STS tables
+
+// RKL2 (Meyer, Balsara & Aslam 2014) and RKG2 with alpha = 3/2 (App. A):
+// mu[k], nu[k], mut[k], gam[k] for k = 1..s.
+void sts_table(int kind, int s, std::vector<double>& mu, std::vector<double>& nu,
+               std::vector<double>& mut, std::vector<double>& gam)
+{
+    mu.assign(s + 1, 0.0); nu.assign(s + 1, 0.0); mut.assign(s + 1, 0.0); gam.assign(s + 1, 0.0);
+    std::vector<double> b(s + 1);
+    if (kind == PA_STS_RKL2) {
+        const double w1 = 4.0 / ((double)s * s + s - 2.0);
+        for (int j = 0; j <= s; ++j)
+            b[j] = j < 2 ? 1.0 / 3.0 : ((double)j * j + j - 2.0) / (2.0 * j * (j + 1.0));
+        mut[1] = w1 / 3.0;
+        for (int j = 2; j <= s; ++j) {
+            mu[j] = (2.0 * j - 1.0) / j * b[j] / b[j - 1];
+            nu[j] = -(j - 1.0) / j * b[j] / b[j - 2];
+            mut[j] = mu[j] * w1;
+            gam[j] = (b[j - 1] - 1.0) * mut[j];
+        }
+    } else {
+        const double w = 6.0 / ((s + 4.0) * (s - 1.0));
+        for (int k = 0; k <= s; ++k)
+            b[k] = k == 0 ? 1.0 : k == 1 ? 1.0 / 3.0 : k == 2 ? 1.0 / 15.0
+                 : 4.0 * (k - 1.0) * (k + 4.0) / (3.0 * k * (k + 1.0) * (k + 2.0) * (k + 3.0));
+        mut[1] = w;
+        mu[2] = 0.5; nu[2] = -0.1; mut[2] = 0.5 * w; gam[2] = 0.0;
+        for (int k = 3; k <= s; ++k) {
+            mu[k] = (2.0 + 1.0 / k) * b[k] / b[k - 1];
+            nu[k] = -(1.0 + 1.0 / k) * b[k] / b[k - 2];
+            mut[k] = mu[k] * w;
+            gam[k] = (0.5 * k * (k + 1.0) * b[k - 1] - 1.0) * mut[k];
+        }
+    }
+}
+
+int stage_count(int kind, double ratio, int force_odd)
+{
+    const double x = kind == PA_STS_RKL2 ? 0.5 * (sqrt(9.0 + 16.0 * ratio) - 1.0)
+                                          : 0.5 * sqrt(25.0 + 24.0 * ratio) - 1.5;
+    int s = (int)ceil(x);
+    if (s < 2) s = 2;
+    if (force_odd && s % 2 == 0) ++s;
+    return s;
+}
+
+// ------------------------------------------------------------ passes
+
+// y0 = F(u0) plus per-tile argmax partials; u0, y0 of storage type T
+template <class T>
+void first_pass(pa_ctx* c, const T* u0, T* y0)
+{
+    KArgs<T> a = base_args<T>(c, 0, c->d.nr);
+    a.u = u0;
+    a.out = y0;
+    stencil<T>(c, kFirst, false, a);
+    launch_ptl_finalize<T>(c->part, c->part_idx, ntiles(c, c->d.nr), u0, y0, c->d.ncomp, c->d.nr,
+                           c->d.nt, c->d.np, c->st, c->stream);
+}
+
+// one STS cycle of length dt with s stages, in place on u0 (y0 = F(u0) given)
+template <class T>
+void sts_cycle(pa_ctx* c, int kind, int s, double dt, T* u0, T* y0, T* A, T* B)
+{
+    std::vector<double> mu, nu, mut, gam;
+    sts_table(kind, s, mu, nu, mut, gam);
+    const double a1 = mut[1] * dt;
+    T* prev = A;   // u_{k-1}
+    T* prev2 = B;  // u_{k-2}
+    for (int k = 2; k <= s; ++k) {
+        KArgs<T> a = base_args<T>(c, 0, c->d.nr);
+        a.u0 = u0;
+        a.y0 = y0;
+        a.a1 = a1;
+        a.mu = mu[k];
+        a.nu = nu[k];
+        a.c0 = 1.0 - mu[k] - nu[k];
+        a.mudt = mut[k] * dt;
+        a.gdt = gam[k] * dt;
+        bool virt = false;
+        T* out;
+        if (k == 2) {            // input u1 = u0 + a1 y0 (virtual), u_{k-2} = u0
+            virt = true;
+            a.u = u0;
+            a.km2 = kKm2U0;
+            out = A;
+        } else if (k == 3) {     // input u2 (A), u_{k-2} = u1 (virtual)
+            a.u = A;
+            a.km2 = kKm2Virtual;
+            out = (k == s) ? u0 : B;
+        } else {
+            a.u = prev;
+            a.ukm2 = prev2;
+            a.km2 = kKm2Array;
+            out = (k == s) ? u0 : prev2;
+        }
+        a.out = out;
+        stencil<T>(c, kStage, virt, a);
+        if (k == 2) { prev = A; prev2 = B; }
+        else { T* t = prev2; prev2 = prev; prev = out == u0 ? prev : t; }
+    }
+    if (s == 2) launch_copy(A, u0, sizeof(T) * c->NT, c->stream);
+}
+
+}  // namespace
+
+// ================================================================ ABI
+
+extern "C" {
+
+void pa_default_options(pa_opts* o)
+{
+    if (!o) return;
+    memset(o, 0, sizeof *o);
+    o->force_odd = 1;
+    o->pc = PA_PC_JACOBI;
+    o->max_iter = 10000;
+    o->max_cycles = 100000;
+    o->pcg_batch = 16;
+    o->ptl_floor = 1.0;
+}
+
+const char* pa_last_error(const pa_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+void pa_destroy(pa_ctx* c)
+{
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    for (void* p : c->allocs) {
+        if (c->d.free) c->d.free(p, c->d.alloc_user);
+        else (void)hipFree(p);
+    }
+    if (c->hst) (void)hipHostFree(c->hst);
+    if (c->hflag) (void)hipHostFree(c->hflag);
+    delete c;
+}
+
+pa_status pa_init(const pa_desc* d, void* stream, pa_ctx** out)
+{
+    if (!out) return PA_ERR_ARG;
+    *out = nullptr;
+    if (!d) return PA_ERR_ARG;
+    if (d->nr < 1 || d->nt < 2 || d->np < 3 || d->ncomp < 1 || !d->r_faces || !d->t_faces ||
+        !d->p_faces)
+        return PA_ERR_ARG;
+    if (d->op != PA_OP_ISO7 && d->op != PA_OP_FIELD_ALIGNED) return PA_ERR_ARG;
+    if ((d->bc_in != PA_BC_DIRICHLET && d->bc_in != PA_BC_NOFLUX) ||
+        (d->bc_out != PA_BC_DIRICHLET && d->bc_out != PA_BC_NOFLUX))
+        return PA_ERR_ARG;
+    if (d->prec != PA_FP64 && d->prec != PA_FP32_STAGES) return PA_ERR_ARG;
+    if ((d->alloc == nullptr) != (d->free == nullptr)) return PA_ERR_ARG;
+    const int nr = d->nr, nt = d->nt, np = d->np;
+    const double *R = d->r_faces, *TH = d->t_faces, *PH = d->p_faces;
+    for (int i = 0; i < nr; ++i)
+        if (!(R[i + 1] > R[i]) || !(R[i] > 0.0)) return PA_ERR_ARG;
+    for (int j = 0; j < nt; ++j)
+        if (!(TH[j + 1] > TH[j])) return PA_ERR_ARG;
+    if (TH[0] < 0.0 || TH[nt] > M_PI + 1e-12) return PA_ERR_ARG;
+    for (int k = 0; k < np; ++k)
+        if (!(PH[k + 1] > PH[k])) return PA_ERR_ARG;
+    if ((double)nr * nt * np * d->ncomp > 4.0e9) return PA_ERR_ARG;
+
+    pa_ctx* c = new pa_ctx();
+    c->d = *d;
+    c->d.r_faces = c->d.t_faces = c->d.p_faces = nullptr;
+    c->stream = (hipStream_t)stream;
+    pa_default_options(&c->opt);
+    (void)hipGetDevice(&c->dev);
+    c->P = (size_t)nt * np;
+    c->N = c->P * nr;
+    c->NT = c->N * d->ncomp;
+    c->NCO = (size_t)(nr + 1) * (nt + 1) * np;
+    c->fp32 = d->prec == PA_FP32_STAGES;
+    c->rch = pick_rch(nr, (int)c->P);
+
+    // 1-D metric factors (finite volume on the face mesh)
+    std::vector<double> rc(nr), tc(nt), pc(np);
+    for (int i = 0; i < nr; ++i) rc[i] = 0.5 * (R[i] + R[i + 1]);
+    for (int j = 0; j < nt; ++j) tc[j] = 0.5 * (TH[j] + TH[j + 1]);
+    for (int k = 0; k < np; ++k) pc[k] = 0.5 * (PH[k] + PH[k + 1]);
+    const double period = PH[np] - PH[0];
+    std::vector<double> dpc(np);  // centre distance between cells k-1 and k
+    for (int k = 0; k < np; ++k) dpc[k] = k == 0 ? pc[0] + period - pc[np - 1] : pc[k] - pc[k - 1];
+    std::vector<double> vr(nr), vt(nt), vp(np), gr(nr + 1), gtr(nr), gtt(nt + 1, 0.0), gpt(nt),
+        gpp(np);
+    for (int i = 0; i < nr; ++i) {
+        vr[i] = (R[i + 1] * R[i + 1] * R[i + 1] - R[i] * R[i] * R[i]) / 3.0;
+        gtr[i] = 0.5 * (R[i + 1] * R[i + 1] - R[i] * R[i]) / rc[i];
+    }
+    for (int ir = 0; ir <= nr; ++ir) {
+        const double dist = ir == 0 ? rc[0] - R[0] : ir == nr ? R[nr] - rc[nr - 1] : rc[ir] - rc[ir - 1];
+        gr[ir] = R[ir] * R[ir] / dist;
+    }
+    for (int j = 0; j < nt; ++j) {
+        vt[j] = cos(TH[j]) - cos(TH[j + 1]);
+        gpt[j] = (TH[j + 1] - TH[j]) / sin(tc[j]);
+    }
+    for (int jt = 1; jt < nt; ++jt) gtt[jt] = sin(TH[jt]) / (tc[jt] - tc[jt - 1]);
+    for (int k = 0; k < np; ++k) {
+        vp[k] = PH[k + 1] - PH[k];
+        gpp[k] = 1.0 / dpc[k];
+    }
+    // corner metric factors
+    std::vector<double> hr(nr + 1), wr(nr + 1), Rf(R, R + nr + 1), htt(nt + 1, 0.0), sT(nt + 1);
+    for (int ic = 0; ic <= nr; ++ic) {
+        if (ic == 0) { hr[ic] = 2.0 * (rc[0] - R[0]); wr[ic] = 0.5 * hr[ic]; }
+        else if (ic == nr) { hr[ic] = 2.0 * (R[nr] - rc[nr - 1]); wr[ic] = 0.5 * hr[ic]; }
+        else { hr[ic] = rc[ic] - rc[ic - 1]; wr[ic] = hr[ic]; }
+    }
+    for (int jc = 1; jc < nt; ++jc) htt[jc] = tc[jc] - tc[jc - 1];
+    for (int jc = 0; jc <= nt; ++jc) sT[jc] = sin(TH[jc]);
+
+    bool ok = dev_upload(c, &c->m64.vr, vr) && dev_upload(c, &c->m64.vt, vt) &&
+              dev_upload(c, &c->m64.vp, vp) && dev_upload(c, &c->m64.gr, gr) &&
+              dev_upload(c, &c->m64.gtr, gtr) && dev_upload(c, &c->m64.gtt, gtt) &&
+              dev_upload(c, &c->m64.gpt, gpt) && dev_upload(c, &c->m64.gpp, gpp) &&
+              dev_upload(c, &c->m32.vr, vr) && dev_upload(c, &c->m32.vt, vt) &&
+              dev_upload(c, &c->m32.vp, vp) && dev_upload(c, &c->m32.gr, gr) &&
+              dev_upload(c, &c->m32.gtr, gtr) && dev_upload(c, &c->m32.gtt, gtt) &&
+              dev_upload(c, &c->m32.gpt, gpt) && dev_upload(c, &c->m32.gpp, gpp) &&
+              dev_upload(c, &c->c_hr, hr) && dev_upload(c, &c->c_wr, wr) &&
+              dev_upload(c, &c->c_R, Rf) && dev_upload(c, &c->c_htt, htt) &&
+              dev_upload(c, &c->c_sT, sT) && dev_upload(c, &c->c_dpc, dpc);
+    const size_t NT = c->NT, N = c->N, bcn = c->P * d->ncomp;
+    c->coef64 = (double*)dev_alloc(c, sizeof(double) * N);
+    c->diagL = (double*)dev_alloc(c, sizeof(double) * N);
+    c->ub_in = (double*)dev_alloc(c, sizeof(double) * bcn);
+    c->ub_out = (double*)dev_alloc(c, sizeof(double) * bcn);
+    ok = ok && c->coef64 && c->diagL && c->ub_in && c->ub_out;
+    if (d->op == PA_OP_FIELD_ALIGNED) {
+        c->e64 = (double*)dev_alloc(c, sizeof(double) * 3 * c->NCO);
+        ok = ok && c->e64;
+    }
+    for (int q = 0; q < 4; ++q) {
+        c->w[q] = (double*)dev_alloc(c, sizeof(double) * NT);
+        ok = ok && c->w[q];
+    }
+    if (c->fp32) {
+        c->coef32 = (float*)dev_alloc(c, sizeof(float) * N);
+        c->ub_in32 = (float*)dev_alloc(c, sizeof(float) * bcn);
+        c->ub_out32 = (float*)dev_alloc(c, sizeof(float) * bcn);
+        ok = ok && c->coef32 && c->ub_in32 && c->ub_out32;
+        if (d->op == PA_OP_FIELD_ALIGNED) {
+            c->e32 = (float*)dev_alloc(c, sizeof(float) * 3 * c->NCO);
+            ok = ok && c->e32;
+        }
+        for (int q = 0; q < 4; ++q) {
+            c->f[q] = (float*)dev_alloc(c, sizeof(float) * NT);
+            ok = ok && c->f[q];
+        }
+    }
+    const size_t tiles = (size_t)stencil_tiles((int)c->P, nr, c->rch, d->ncomp);
+    const size_t nblk = (N + kBlock - 1) / kBlock;
+    ok = ok && ensure_parts(c, tiles > nblk ? (tiles > 4096 ? tiles : 4096) : (nblk > 4096 ? nblk : 4096));
+    c->st = (DevState*)dev_alloc(c, sizeof(DevState));
+    c->flag = (int*)dev_alloc(c, sizeof(int));
+    ok = ok && c->st && c->flag;
+    if (ok && hipHostMalloc((void**)&c->hst, sizeof(DevState), hipHostMallocDefault) != hipSuccess)
+        ok = false;
+    if (ok && hipHostMalloc((void**)&c->hflag, sizeof(int), hipHostMallocDefault) != hipSuccess)
+        ok = false;
+    if (!ok) {
+        pa_destroy(c);
+        return PA_ERR_ALLOC;
+    }
+    launch_fill_zero(c->ub_in, sizeof(double) * bcn, c->stream);
+    launch_fill_zero(c->ub_out, sizeof(double) * bcn, c->stream);
+    launch_fill_zero(c->st, sizeof(DevState), c->stream);
+    launch_fill_zero(c->flag, sizeof(int), c->stream);
+    if (c->fp32) {
+        launch_fill_zero(c->ub_in32, sizeof(float) * bcn, c->stream);
+        launch_fill_zero(c->ub_out32, sizeof(float) * bcn, c->stream);
+    }
+    if (hipStreamSynchronize(c->stream) != hipSuccess) {
+        pa_destroy(c);
+        return PA_ERR_HIP;
+    }
+    *out = c;
+    return PA_OK;
+}
+
+pa_status pa_set_options(pa_ctx* c, const pa_opts* o)
+{
+    if (!c) return PA_ERR_ARG;
+    if (!o) return fail(c, PA_ERR_ARG, "null options");
+    if (o->s_override < 0 || o->s_override == 1 || o->max_iter < 1 || o->max_cycles < 1 ||
+        o->force_iters < 0 || o->pcg_batch < 1 || o->replay_n < 0 || !(o->ptl_floor >= 0.0) ||
+        (o->replay_n > 0 && !o->replay_dt) || (o->pc != PA_PC_JACOBI && o->pc != PA_PC_LEARNED))
+        return fail(c, PA_ERR_ARG, "invalid option value");
+    if (o->pc == PA_PC_LEARNED) return fail(c, PA_ERR_ARG, "learned preconditioner not loaded");
+    c->opt = *o;
+    c->replay.assign(o->replay_dt, o->replay_dt + (o->replay_n > 0 ? o->replay_n : 0));
+    for (double x : c->replay)
+        if (!(x > 0.0) || !isfinite(x)) return fail(c, PA_ERR_ARG, "replay lengths must be > 0");
+    c->opt.replay_dt = nullptr;
+    c->err.clear();
+    return PA_OK;
+}
+
+pa_status pa_bind_field(pa_ctx* c, double* u)
+{
+    if (!c) return PA_ERR_ARG;
+    if (!u) return fail(c, PA_ERR_ARG, "null field");
+    c->u = u;
+    return PA_OK;
+}
+
+pa_status pa_set_bc(pa_ctx* c, const double* ui, const double* uo)
+{
+    if (!c) return PA_ERR_ARG;
+    const size_t n = c->P * c->d.ncomp;
+    if (ui) launch_copy(ui, c->ub_in, sizeof(double) * n, c->stream);
+    if (uo) launch_copy(uo, c->ub_out, sizeof(double) * n, c->stream);
+    if (c->fp32) {
+        launch_f64_to_f32(c->ub_in, c->ub_in32, n, c->stream);
+        launch_f64_to_f32(c->ub_out, c->ub_out32, n, c->stream);
+    }
+    HIPCHK(c, hipGetLastError());
+    return PA_OK;
+}
+
+pa_status pa_set_coefficients(pa_ctx* c, const double* T0, double scale, double expo,
+                              const double* B)
+{
+    if (!c) return PA_ERR_ARG;
+    if (!isfinite(scale) || scale < 0.0 || !isfinite(expo))
+        return fail(c, PA_ERR_ARG, "scale must be finite and >= 0, expo finite");
+    if (c->d.op == PA_OP_FIELD_ALIGNED && !B) return fail(c, PA_ERR_ARG, "field-aligned operator needs B");
+    c->have_coef = false;
+    launch_fill_zero(c->flag, sizeof(int), c->stream);
+    const int N = (int)c->N;
+    launch_coef(T0, scale, expo, N, c->coef64, c->coef32, c->flag, c->stream);
+    c->coef_var = T0 != nullptr;
+    c->cscale = scale;
+    const Geo<double> g = geo(c, c->m64);
+    int np_ = 0;
+    if (c->d.op == PA_OP_FIELD_ALIGNED) {
+        CornerGeo cg{c->c_hr, c->c_wr, c->c_R, c->c_htt, c->c_sT, c->c_dpc};
+        launch_corner_e(c->d.nr, c->d.nt, c->d.np, cg, c->coef64, B, c->e64, c->e32, c->flag,
+                        c->stream);
+        launch_diag_aligned(g, c->e64, c->d.bc_in, c->d.bc_out, c->diagL, c->part, c->stream, &np_);
+    } else {
+        launch_diag_iso7(g, c->coef_var ? c->coef64 : nullptr, scale, c->d.bc_in, c->d.bc_out,
+                         c->diagL, c->part, c->stream, &np_);
+    }
+    launch_reduce_max(c->part, np_, &c->st->gmax, c->stream);
+    HIPCHK(c, hipGetLastError());
+    pa_status s = sync_state(c);
+    if (s) return s;
+    if (*c->hflag) return fail(c, PA_ERR_NONFINITE, "non-finite or negative coefficient or field B");
+    const double gm = c->hst->gmax;
+    c->dtE = gm > 0.0 ? 2.0 / gm : INFINITY;
+    c->have_coef = true;
+    c->err.clear();
+    return PA_OK;
+}
+
+pa_status pa_dt_explicit(pa_ctx* c, double* dt)
+{
+    if (!c) return PA_ERR_ARG;
+    if (!dt) return fail(c, PA_ERR_ARG, "null output");
+    if (!c->have_coef) return fail(c, PA_ERR_STATE, "coefficients not set");
+    *dt = c->dtE;
+    return PA_OK;
+}
+
+pa_status pa_diag(pa_ctx* c, double* out)
+{
+    if (!c) return PA_ERR_ARG;
+    if (!out) return fail(c, PA_ERR_ARG, "null output");
+    if (!c->have_coef) return fail(c, PA_ERR_STATE, "coefficients not set");
+    launch_copy(c->diagL, out, sizeof(double) * c->N, c->stream);
+    HIPCHK(c, hipGetLastError());
+    return PA_OK;
+}
+
+pa_status pa_apply(pa_ctx* c, const double* u, double* F, int32_t affine)
+{
+    if (!c) return PA_ERR_ARG;
+    if (!u || !F) return fail(c, PA_ERR_ARG, "null array");
+    if (!c->have_coef) return fail(c, PA_ERR_STATE, "coefficients not set");
+    const size_t bytes = sizeof(double) * c->NT;
+    if ((const char*)u < (const char*)F + bytes && (const char*)F < (const char*)u + bytes)
+        return fail(c, PA_ERR_ARG, "u and F overlap");
+    KArgs<double> a = base_args<double>(c, 0, c->d.nr);
+    a.u = u;
+    a.out = F;
+    a.affine = affine ? 1 : 0;
+    stencil<double>(c, kApply, false, a);
+    HIPCHK(c, hipGetLastError());
+    return PA_OK;
+}
+
+pa_status pa_compute_ptl(pa_ctx* c, double* dt, int64_t* k)
+{
+    if (!c) return PA_ERR_ARG;
+    if (!dt) return fail(c, PA_ERR_ARG, "null output");
+    if (!c->have_coef) return fail(c, PA_ERR_STATE, "coefficients not set");
+    if (!c->u) return fail(c, PA_ERR_STATE, "no field bound");
+    launch_fill_zero(c->flag, sizeof(int), c->stream);
+    if (c->fp32) {
+        launch_f64_to_f32(c->u, c->f[0], c->NT, c->stream);
+        first_pass<float>(c, c->f[0], c->f[1]);
+    } else {
+        first_pass<double>(c, c->u, c->w[0]);
+    }
+    HIPCHK(c, hipGetLastError());
+    pa_status s = sync_state(c);
+    if (s) return s;
+    *dt = c->hst->dt_ptl;
+    if (k) *k = c->hst->kmax;
+    if (*c->hflag || isnan(*dt)) return fail(c, PA_ERR_NONFINITE, "non-finite F");
+    return PA_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- drivers
+
+namespace {
+
+struct Timer {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipStream_t s;
+    explicit Timer(hipStream_t st) : s(st)
+    {
+        (void)hipEventCreate(&a);
+        (void)hipEventCreate(&b);
+        (void)hipEventRecord(a, s);
+    }
+    double stop()
+    {
+        float ms = 0.f;
+        (void)hipEventRecord(b, s);
+        (void)hipEventSynchronize(b);
+        (void)hipEventElapsedTime(&ms, a, b);
+        return ms;
+    }
+    ~Timer()
+    {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+    }
+};
+
+// Cycle schedule shared by both schemes.  Returns PA_OK with *dtc and *last
+// set, or an error.  Requires the PTL pass of the current iterate to have
+// been queued when the schedule is dynamic.
+pa_status next_cycle(pa_ctx* c, double dt, int cycles, int ncyc, double t_rem, pa_stats* st,
+                     double* dtc, int* last)
+{
+    if (c->opt.replay_n > 0) {
+        if (ncyc >= (int)c->replay.size()) return fail(c, PA_ERR_ARG, "replay schedule too short");
+        *dtc = c->replay[ncyc];
+        *last = ncyc + 1 == (int)c->replay.size();
+    } else if (cycles > 0) {
+        *dtc = dt / cycles;
+        *last = ncyc + 1 == cycles;
+    } else {
+        pa_status s = sync_state(c);
+        if (s) return s;
+        const double ptl = c->hst->dt_ptl;
+        if (*c->hflag || isnan(ptl) || !(ptl > 0.0))
+            return fail(c, PA_ERR_NONFINITE, "non-finite field or time-step limit");
+        if (ncyc == 0) { st->dt_ptl_first = ptl; st->k_first = c->hst->kmax; }
+        if (ptl < st->dt_ptl_min) st->dt_ptl_min = ptl;
+        double lim = ptl;
+        if (lim < c->opt.ptl_floor * c->dtE) { lim = c->opt.ptl_floor * c->dtE; st->floored += 1; }
+        const double nreq = ceil(t_rem / lim);
+        if (!(nreq > 1.0)) { *dtc = t_rem; *last = 1; }
+        else { *dtc = t_rem / nreq; *last = 0; }
+    }
+    if (ncyc >= c->opt.max_cycles) return fail(c, PA_ERR_MAXCYCLES, "more than %d cycles", c->opt.max_cycles);
+    return PA_OK;
+}
+
+pa_status check_ready(pa_ctx* c, double dt)
+{
+    if (!c->have_coef) return fail(c, PA_ERR_STATE, "coefficients not set");
+    if (!c->u) return fail(c, PA_ERR_STATE, "no field bound");
+    if (!(dt > 0.0) || !isfinite(dt)) return fail(c, PA_ERR_ARG, "dt must be finite and > 0");
+    return PA_OK;
+}
+
+void init_stats(pa_stats* st)
+{
+    memset(st, 0, sizeof *st);
+    st->dt_ptl_first = st->dt_ptl_min = INFINITY;
+    st->k_first = -1;
+}
+
+template <class T>
+pa_status sts_advance(pa_ctx* c, int kind, double dt, int cycles, pa_stats* st, T* u0, T* y0, T* A,
+                      T* B)
+{
+    double t_rem = dt;
+    int ncyc = 0;
+    pa_status s = PA_OK;
+    while (true) {
+        first_pass<T>(c, u0, y0);
+        double dtc;
+        int last;
+        s = next_cycle(c, dt, cycles, ncyc, t_rem, st, &dtc, &last);
+        if (s) break;
+        const int sv = c->opt.s_override > 0 ? c->opt.s_override
+                                             : stage_count(kind, dtc / c->dtE, c->opt.force_odd);
+        if (ncyc < PA_MAX_LOG) { st->dt_cycle[ncyc] = dtc; st->per_cycle[ncyc] = sv; }
+        st->s_total += sv;
+        if (sv > st->s_max) st->s_max = sv;
+        sts_cycle<T>(c, kind, sv, dtc, u0, y0, A, B);
+        ++ncyc;
+        if (last) break;
+        t_rem -= dtc;
+    }
+    st->cycles = ncyc;
+    return s;
+}
+
+pa_status advance_sts(pa_ctx* c, int kind, double dt, int32_t cycles, pa_stats* user)
+{
+    if (!c) return PA_ERR_ARG;
+    pa_status s = check_ready(c, dt);
+    if (s) return s;
+    if (cycles < 0) return fail(c, PA_ERR_ARG, "cycles must be >= 0");
+    pa_stats local;
+    pa_stats* st = user ? user : &local;
+    init_stats(st);
+    st->dt_explicit = c->dtE;
+    Timer tm(c->stream);
+    launch_fill_zero(c->flag, sizeof(int), c->stream);
+    if (c->fp32) {
+        launch_f64_to_f32(c->u, c->f[0], c->NT, c->stream);
+        s = sts_advance<float>(c, kind, dt, cycles, st, c->f[0], c->f[1], c->f[2], c->f[3]);
+        launch_f32_to_f64(c->f[0], c->u, c->NT, c->stream);
+    } else {
+        s = sts_advance<double>(c, kind, dt, cycles, st, c->u, c->w[0], c->w[1], c->w[2]);
+    }
+    if (hipGetLastError() != hipSuccess && !s) s = fail(c, PA_ERR_HIP, "kernel launch failed");
+    st->ms_total = tm.stop();
+    if (!s) {
+        pa_status s2 = sync_state(c);
+        if (s2) s = s2;
+        else if (*c->hflag) s = fail(c, PA_ERR_NONFINITE, "non-finite values in the advance");
+    }
+    st->status = s;
+    if (!s) c->err.clear();
+    return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+pa_status pa_advance_rkl2(pa_ctx* c, double dt, int32_t cycles, pa_stats* st)
+{
+    return advance_sts(c, PA_STS_RKL2, dt, cycles, st);
+}
+
+pa_status pa_advance_rkg2(pa_ctx* c, double dt, int32_t cycles, pa_stats* st)
+{
+    return advance_sts(c, PA_STS_RKG2, dt, cycles, st);
+}
+
+pa_status pa_advance_be_pcg(pa_ctx* c, double dt, double tol, int32_t cycles, pa_stats* user)
+{
+    if (!c) return PA_ERR_ARG;
+    pa_status s = check_ready(c, dt);
+    if (s) return s;
+    if (cycles < 0) return fail(c, PA_ERR_ARG, "cycles must be >= 0");
+    if (!(tol >= 0.0) || !isfinite(tol)) return fail(c, PA_ERR_ARG, "tol must be finite and >= 0");
+    pa_stats local;
+    pa_stats* st = user ? user : &local;
+    init_stats(st);
+    st->dt_explicit = c->dtE;
+    Timer tm(c->stream);
+    launch_fill_zero(c->flag, sizeof(int), c->stream);
+    double* y0 = c->w[0];
+    double* r = c->w[1];
+    double* p = c->w[2];
+    double* q = c->w[3];
+    const Geo<double> g = geo(c, c->m64);
+    const int nc = c->d.ncomp, nr = c->d.nr;
+    const bool any_dir = c->d.bc_in == PA_BC_DIRICHLET || c->d.bc_out == PA_BC_DIRICHLET;
+    const int mt = ntiles(c, nr);
+    double t_rem = dt;
+    int ncyc = 0;
+    while (true) {
+        first_pass<double>(c, c->u, y0);
+        double dtc;
+        int last;
+        s = next_cycle(c, dt, cycles, ncyc, t_rem, st, &dtc, &last);
+        if (s) break;
+        // boundary-data part of F: F(0) on the two radial boundary levels
+        if (any_dir) {
+            for (int side = 0; side < 2; ++side) {
+                const int lv = side == 0 ? 0 : nr - 1;
+                if (side == 1 && nr == 1) break;
+                KArgs<double> a = base_args<double>(c, lv, lv + 1);
+                a.rch = 1;
+                a.nrc = 1;
+                a.u = c->u;
+                a.y0 = c->u;
+                a.a1 = -1.0;  // virtual input u - u = 0
+                a.out = q;
+                stencil<double>(c, kApply, true, a);
+            }
+        }
+        int nparts = 0;
+        launch_pcg_init(g, nc, dtc, c->u, y0, any_dir ? q : nullptr, c->diagL, r, p, c->part,
+                        &nparts, c->stream);
+        launch_pcg_start(c->part, nparts, c->st, tol, c->opt.max_iter, c->opt.force_iters,
+                         c->stream);
+        while (true) {
+            for (int b = 0; b < c->opt.pcg_batch; ++b) {
+                KArgs<double> a = base_args<double>(c, 0, nr);
+                a.u = p;
+                a.out = q;
+                a.affine = 0;
+                a.dt = dtc;
+                a.done = &c->st->done;
+                stencil<double>(c, kMatvec, false, a);
+                launch_pcg_alpha(c->part, mt, c->st, c->stream);
+                launch_pcg_update(g, nc, dtc, c->diagL, c->u, r, p, q, c->st, c->part, &nparts,
+                                  c->stream);
+                launch_pcg_beta(c->part, nparts, c->st, c->stream);
+                launch_pcg_dir(g, nc, dtc, c->diagL, r, p, c->st, c->stream);
+            }
+            s = sync_state(c);
+            if (s) break;
+            if (c->hst->done) break;
+        }
+        if (s) break;
+        const int its = c->hst->iters;
+        if (ncyc < PA_MAX_LOG) { st->dt_cycle[ncyc] = dtc; st->per_cycle[ncyc] = its; }
+        st->iters_total += its;
+        if (its > st->iters_max) st->iters_max = its;
+        st->rel_residual = c->hst->bb > 0.0 ? sqrt(c->hst->rr / c->hst->bb) : sqrt(c->hst->rr);
+        ++ncyc;
+        const int pst = c->hst->status;
+        if (pst == 4) { s = fail(c, PA_ERR_NOCONV, "PCG did not reach tol in %d iterations", its); break; }
+        if (pst == 5) { s = fail(c, PA_ERR_BREAKDOWN, "PCG breakdown (<p,Mp> <= 0)"); break; }
+        if (pst == 6) { s = fail(c, PA_ERR_NONFINITE, "non-finite residual"); break; }
+        if (last) break;
+        t_rem -= dtc;
+    }
+    st->cycles = ncyc;
+    if (hipGetLastError() != hipSuccess && !s) s = fail(c, PA_ERR_HIP, "kernel launch failed");
+    st->ms_total = tm.stop();
+    st->status = s;
+    if (!s) c->err.clear();
+    return s;
+}
+
+}  // extern "C"

@@ -1,0 +1,125 @@
+// pa_internal.h -- declarations shared by the GPU library's kernel and host
+// translation units (gfx950).  Not part of the public ABI (include/paradv.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pa {
+
+constexpr int kBlock = 256;   // threads per workgroup (4 waves of 64)
+constexpr int kRedBlock = 1024;
+
+// Separable 1-D metric factors of the finite-volume mesh (device arrays).
+//  V(i,j,k)           = vr[i] * vt[j] * vp[k]
+//  G_r(face ir, j, k) = gr[ir] * vt[j] * vp[k]        ir in [0, nr]
+//  G_t(i, face jt, k) = gtr[i] * gtt[jt] * vp[k]      jt in [0, nt], 0 at the poles
+//  G_p(i, j, face kf) = gtr[i] * gpt[j] * gpp[kf]     kf in [0, np), face between kf-1, kf
+template <class T>
+struct Geo {
+    int nr, nt, np, P;  // P = nt*np cells per radial level
+    const T* vr;
+    const T* vt;
+    const T* vp;
+    const T* gr;
+    const T* gtr;
+    const T* gtt;
+    const T* gpt;
+    const T* gpp;
+};
+
+enum Mode : int {
+    kApply = 0,   // out = F(u)
+    kFirst = 1,   // out = F(u); per-block argmax |F|; non-finite flag
+    kStage = 2,   // out = mu u + nu ukm2 + c0 u0 + mudt F(u) + gdt y0
+    kMatvec = 3,  // out = V u + dt L u (linear part); per-block <u, out>
+};
+
+// Source of the u_{k-2} term of an STS stage.
+enum Km2 : int { kKm2Array = 0, kKm2U0 = 1, kKm2Virtual = 2 };
+
+template <class T>
+struct KArgs {
+    const T* u;       // stencil input (or u0 when the input is virtual)
+    const T* y0;      // F(u0)
+    double a1;        // virtual input u1 = u0 + a1*y0 (a1 = mu~_1 dt)
+    const T* coef;    // 7-point: cell coefficient array, or null for constant `cs`
+    T cs;
+    const T* e;       // field-aligned: corner coefficients [3][nr+1][nt+1][np]
+    const T* ub_in;   // [nc][nt][np]
+    const T* ub_out;
+    int bc_in, bc_out, affine;
+    int r_lo, r_hi;   // radial levels processed [r_lo, r_hi)
+    int rch;          // radial levels per workgroup
+    int nbx, nrc, nc; // logical tiles: x-blocks, radial chunks, components
+    T* out;
+    const T* ukm2;
+    int km2;
+    const T* u0;
+    double mu, nu, c0, mudt, gdt, dt;
+    double* part;     // per-tile partial sums / maxima
+    long long* part_idx;
+    int* flag;        // non-finite flag (kFirst)
+    const int* done;  // skip the launch when *done != 0 (PCG), may be null
+};
+
+// stencil launchers (pa_kernels.hip)
+template <class T>
+void launch_iso7(int mode, bool virt, const Geo<T>& g, const KArgs<T>& a, hipStream_t s);
+template <class T>
+void launch_aligned(int mode, bool virt, const Geo<T>& g, const KArgs<T>& a, hipStream_t s);
+
+// number of logical tiles of a stencil launch (== entries of a.part)
+int stencil_tiles(int P, int nr_levels, int rch, int nc);
+
+// setup kernels
+void launch_coef(const double* T0, double scale, double expo, int n, double* c64, float* c32,
+                 int* flag, hipStream_t s);
+struct CornerGeo {
+    const double* hr;   // [nr+1] radial centre distance at corner plane ic
+    const double* wr;   // [nr+1] radial dual extent
+    const double* R;    // [nr+1] face radii
+    const double* htt;  // [nt+1] tc[jc]-tc[jc-1] (0 at poles)
+    const double* sT;   // [nt+1] sin(t_faces[jc])
+    const double* dpc;  // [np] phi centre distance between kc-1 and kc
+};
+void launch_corner_e(int nr, int nt, int np, const CornerGeo& cg, const double* coef,
+                     const double* B, double* e64, float* e32, int* flag, hipStream_t s);
+void launch_diag_iso7(const Geo<double>& g, const double* coef, double cs, int bc_in, int bc_out,
+                      double* diag, double* part, hipStream_t s, int* nparts);
+void launch_diag_aligned(const Geo<double>& g, const double* e, int bc_in, int bc_out,
+                         double* diag, double* part, hipStream_t s, int* nparts);
+
+// reductions and vector kernels (pa_vec.hip)
+struct DevState {
+    double dt_ptl;
+    long long kmax;
+    double gmax;       // Gershgorin maximum
+    double rho, pq, rz, rr, bb, alpha, beta;
+    int done, iters, status, nonfinite;
+    int max_iter, force_iters;
+    double tol;
+};
+void launch_reduce_max(const double* part, int n, double* outp, hipStream_t s);
+template <class T>
+void launch_ptl_finalize(const double* pval, const long long* pidx, int n, const T* u, const T* F,
+                         int nc, int nr, int nt, int np, DevState* st, hipStream_t s);
+void launch_pcg_init(const Geo<double>& g, int nc, double dt, const double* u, const double* y0,
+                     const double* hF, const double* diagL, double* r, double* p, double* part,
+                     int* nparts, hipStream_t s);
+void launch_pcg_start(const double* part, int n, DevState* st, double tol, int max_iter,
+                      int force_iters, hipStream_t s);
+void launch_pcg_alpha(const double* part, int n, DevState* st, hipStream_t s);
+void launch_pcg_update(const Geo<double>& g, int nc, double dt, const double* diagL, double* x,
+                       double* r, const double* p, const double* q, const DevState* st,
+                       double* part, int* nparts, hipStream_t s);
+void launch_pcg_beta(const double* part, int n, DevState* st, hipStream_t s);
+void launch_pcg_dir(const Geo<double>& g, int nc, double dt, const double* diagL, const double* r,
+                    double* p, const DevState* st, hipStream_t s);
+void launch_f64_to_f32(const double* a, float* b, size_t n, hipStream_t s);
+void launch_f32_to_f64(const float* a, double* b, size_t n, hipStream_t s);
+void launch_copy(const void* a, void* b, size_t bytes, hipStream_t s);
+void launch_fill_zero(void* a, size_t bytes, hipStream_t s);
+void launch_nonfinite(const double* a, size_t n, int* flag, hipStream_t s);
+
+}  // namespace pa

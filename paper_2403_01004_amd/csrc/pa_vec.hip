@@ -1,0 +1,407 @@
+// pa_vec.hip -- reductions, the PTL finalisation and the PCG vector kernels
+// (gfx950).  All reductions are deterministic: per-tile partials written by
+// the producing kernel, then one workgroup sums them in a fixed order
+// (strided per thread, then a fixed shuffle/LDS tree), so repeated runs are
+// bitwise identical.  The PCG scalars (alpha, beta, rho, the stopping test)
+// live on the device; a `done` flag turns the remaining kernels of a queued
+// batch of iterations into no-ops once the solve has stopped.
+#include "pa_internal.h"
+
+namespace pa {
+
+__device__ __forceinline__ double wsum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// sum of part[0..n) by one workgroup of kRedBlock threads; result in thread 0
+__device__ double red_sum(const double* part, int n)
+{
+    __shared__ double lds[kRedBlock / 64];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) v += part[i];
+    v = wsum(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += lds[w];
+    return s;
+}
+
+__global__ __launch_bounds__(kRedBlock) void k_reduce_max(const double* part, int n, double* outp)
+{
+    __shared__ double lds[kRedBlock / 64];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) v = fmax(v, part[i]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = lds[0];
+        for (int w = 1; w < kRedBlock / 64; ++w) b = fmax(b, lds[w]);
+        *outp = b;
+    }
+}
+
+void launch_reduce_max(const double* part, int n, double* outp, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reduce_max, dim3(1), dim3(kRedBlock), 0, s, part, n, outp);
+}
+
+// ---------------------------------------------------------------- PTL
+
+__device__ __forceinline__ bool better(double v, long long i, double bv, long long bi)
+{
+    return v > bv || (v == bv && i < bi);
+}
+
+// Eq. (ptl3): argmax |F| over the per-tile partials, then the minimum over
+// the six face neighbours of -(u_k - u_nb)/(F_k - F_nb) where du, dF != 0 and
+// du*dF < 0 (Eq. ptl2); +inf if none.  Neighbours: phi periodic, none across
+// a pole or a radial boundary.
+template <class T>
+__global__ __launch_bounds__(kRedBlock) void k_ptl_finalize(const double* pval,
+                                                            const long long* pidx, int n,
+                                                            const T* u, const T* F, int nc,
+                                                            int nr, int nt, int np, DevState* st)
+{
+    __shared__ double lv[kRedBlock / 64];
+    __shared__ long long li[kRedBlock / 64];
+    double v = -1.0;
+    long long ix = 0x7fffffffffffffffLL;
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        if (better(pval[i], pidx[i], v, ix)) { v = pval[i]; ix = pidx[i]; }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(v, o, 64);
+        const long long oi = __shfl_xor(ix, o, 64);
+        if (better(ov, oi, v, ix)) { v = ov; ix = oi; }
+    }
+    if ((threadIdx.x & 63) == 0) { lv[threadIdx.x >> 6] = v; li[threadIdx.x >> 6] = ix; }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int w = 1; w < kRedBlock / 64; ++w)
+        if (better(lv[w], li[w], v, ix)) { v = lv[w]; ix = li[w]; }
+    const long long N = (long long)nc * nr * nt * np;
+    if (ix < 0 || ix >= N) {  // every |F| was NaN
+        st->kmax = -1;
+        st->dt_ptl = __builtin_nan("");
+        return;
+    }
+    const long long best = ix;
+    const int k = (int)(best % np);
+    const int j = (int)((best / np) % nt);
+    const int i = (int)((best / ((long long)np * nt)) % nr);
+    const long long P = (long long)nt * np;
+    long long nb[6];
+    int nn = 0;
+    if (i > 0) nb[nn++] = best - P;
+    if (i < nr - 1) nb[nn++] = best + P;
+    if (j > 0) nb[nn++] = best - np;
+    if (j < nt - 1) nb[nn++] = best + np;
+    nb[nn++] = best - k + (k == 0 ? np - 1 : k - 1);
+    nb[nn++] = best - k + (k == np - 1 ? 0 : k + 1);
+    double dt = __builtin_inf();
+    const double uk = (double)u[best], Fk = (double)F[best];
+    for (int q = 0; q < nn; ++q) {
+        const double du = uk - (double)u[nb[q]];
+        const double dF = Fk - (double)F[nb[q]];
+        if (du != 0.0 && dF != 0.0 && du * dF < 0.0) {
+            const double c = -du / dF;
+            if (c < dt) dt = c;
+        }
+    }
+    st->kmax = best;
+    st->dt_ptl = dt;
+}
+
+template <class T>
+void launch_ptl_finalize(const double* pval, const long long* pidx, int n, const T* u, const T* F,
+                         int nc, int nr, int nt, int np, DevState* st, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_ptl_finalize<T>), dim3(1), dim3(kRedBlock), 0, s, pval, pidx, n, u, F,
+                       nc, nr, nt, np, st);
+}
+template void launch_ptl_finalize<double>(const double*, const long long*, int, const double*,
+                                          const double*, int, int, int, int, DevState*, hipStream_t);
+template void launch_ptl_finalize<float>(const double*, const long long*, int, const float*,
+                                         const float*, int, int, int, int, DevState*, hipStream_t);
+
+// ---------------------------------------------------------------- PCG
+
+// r0 = b - M u = dt V F(u) (y0 from the PTL pass), b = V (u + dt hF) with hF
+// = F(0) the boundary-data part of F, read on the two radial boundary levels
+// only (zero elsewhere; hF may be null when both sides are no-flux),
+// z = r/D, p = z; partials <r,z>, <r,r>, <b,b>.
+__global__ __launch_bounds__(kBlock) void k_pcg_init(Geo<double> g, int nc, double dt,
+                                                     const double* u, const double* y0,
+                                                     const double* hF, const double* dL,
+                                                     double* r, double* p, double* part)
+{
+    __shared__ double lds[kBlock / 64];
+    const int nr = g.nr, np = g.np, P = g.P;
+    const size_t N = (size_t)nr * P, NT = N * nc;
+    double rz = 0.0, rr = 0.0, bb = 0.0;
+    for (size_t m = (size_t)blockIdx.x * blockDim.x + threadIdx.x; m < NT;
+         m += (size_t)gridDim.x * blockDim.x) {
+        const size_t cell = m % N;
+        const int i = (int)(cell / P), pp = (int)(cell % P), j = pp / np, k = pp % np;
+        const double V = g.vr[i] * g.vt[j] * g.vp[k];
+        const double D = V + dt * dL[cell];
+        const double h = (hF && (i == 0 || i == nr - 1)) ? hF[m] : 0.0;
+        const double b = V * u[m] + dt * V * h;
+        const double rv = dt * V * y0[m];
+        const double z = rv / D;
+        r[m] = rv;
+        p[m] = z;
+        rz += rv * z;
+        rr += rv * rv;
+        bb += b * b;
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double vals[3] = {rz, rr, bb};
+    for (int q = 0; q < 3; ++q) {
+        double v = wsum(vals[q]);
+        __syncthreads();
+        if (lane == 0) lds[w] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double sacc = 0.0;
+            for (int x = 0; x < kBlock / 64; ++x) sacc += lds[x];
+            part[(size_t)q * gridDim.x + blockIdx.x] = sacc;
+        }
+    }
+}
+
+static int vec_blocks(size_t n)
+{
+    size_t nb = (n + kBlock - 1) / kBlock;
+    if (nb > 4096) nb = 4096;
+    return (int)nb;
+}
+
+void launch_pcg_init(const Geo<double>& g, int nc, double dt, const double* u, const double* y0,
+                     const double* hF, const double* diagL, double* r, double* p, double* part,
+                     int* nparts, hipStream_t s)
+{
+    const int nb = vec_blocks((size_t)g.nr * g.P * nc);
+    *nparts = nb;
+    hipLaunchKernelGGL(k_pcg_init, dim3(nb), dim3(kBlock), 0, s, g, nc, dt, u, y0, hF, diagL, r,
+                       p, part);
+}
+
+__global__ __launch_bounds__(kRedBlock) void k_pcg_start(const double* part, int n, DevState* st,
+                                                          double tol, int max_iter, int force_iters)
+{
+    const double rz = red_sum(part, n);
+    const double rr = red_sum(part + n, n);
+    const double bb = red_sum(part + 2 * n, n);
+    if (threadIdx.x != 0) return;
+    st->tol = tol;
+    st->max_iter = max_iter;
+    st->force_iters = force_iters;
+    st->rho = rz;
+    st->rr = rr;
+    st->bb = bb;
+    st->iters = 0;
+    st->status = 0;
+    st->done = 0;
+    if (!isfinite(rr) || !isfinite(bb)) { st->status = 6; st->done = 1; return; }
+    if (st->force_iters <= 0 && sqrt(rr) <= st->tol * sqrt(bb)) st->done = 1;
+}
+
+void launch_pcg_start(const double* part, int n, DevState* st, double tol, int max_iter,
+                      int force_iters, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pcg_start, dim3(1), dim3(kRedBlock), 0, s, part, n, st, tol, max_iter,
+                       force_iters);
+}
+
+__global__ __launch_bounds__(kRedBlock) void k_pcg_alpha(const double* part, int n, DevState* st)
+{
+    if (st->done) return;
+    const double pq = red_sum(part, n);
+    if (threadIdx.x != 0) return;
+    st->pq = pq;
+    if (!(pq > 0.0) || !isfinite(pq)) { st->status = 5; st->done = 1; return; }
+    st->alpha = st->rho / pq;
+}
+
+void launch_pcg_alpha(const double* part, int n, DevState* st, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(kRedBlock), 0, s, part, n, st);
+}
+
+// x += alpha p, r -= alpha q, z = r/D; partials <r,z>, <r,r>
+__global__ __launch_bounds__(kBlock) void k_pcg_update(Geo<double> g, int nc, double dt,
+                                                       const double* dL, double* x, double* r,
+                                                       const double* p, const double* q,
+                                                       const DevState* st, double* part)
+{
+    __shared__ double lds[kBlock / 64];
+    if (st->done) return;
+    const double alpha = st->alpha;
+    const int nr = g.nr, np = g.np, P = g.P;
+    const size_t N = (size_t)nr * P, NT = N * nc;
+    double rz = 0.0, rr = 0.0;
+    for (size_t m = (size_t)blockIdx.x * blockDim.x + threadIdx.x; m < NT;
+         m += (size_t)gridDim.x * blockDim.x) {
+        const size_t cell = m % N;
+        const int i = (int)(cell / P), pp = (int)(cell % P), j = pp / np, k = pp % np;
+        const double D = g.vr[i] * g.vt[j] * g.vp[k] + dt * dL[cell];
+        x[m] += alpha * p[m];
+        const double rv = r[m] - alpha * q[m];
+        r[m] = rv;
+        const double z = rv / D;
+        rz += rv * z;
+        rr += rv * rv;
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double vals[2] = {rz, rr};
+    for (int t = 0; t < 2; ++t) {
+        double v = wsum(vals[t]);
+        __syncthreads();
+        if (lane == 0) lds[w] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double sacc = 0.0;
+            for (int xx = 0; xx < kBlock / 64; ++xx) sacc += lds[xx];
+            part[(size_t)t * gridDim.x + blockIdx.x] = sacc;
+        }
+    }
+}
+
+void launch_pcg_update(const Geo<double>& g, int nc, double dt, const double* diagL, double* x,
+                       double* r, const double* p, const double* q, const DevState* st,
+                       double* part, int* nparts, hipStream_t s)
+{
+    const int nb = vec_blocks((size_t)g.nr * g.P * nc);
+    *nparts = nb;
+    hipLaunchKernelGGL(k_pcg_update, dim3(nb), dim3(kBlock), 0, s, g, nc, dt, diagL, x, r, p, q,
+                       st, part);
+}
+
+// stopping test and beta (Hestenes-Stiefel PCG with rho = <r, z>)
+__global__ __launch_bounds__(kRedBlock) void k_pcg_beta(const double* part, int n, DevState* st)
+{
+    if (st->done) return;
+    const double rz = red_sum(part, n);
+    const double rr = red_sum(part + n, n);
+    if (threadIdx.x != 0) return;
+    st->iters += 1;
+    st->rr = rr;
+    if (!isfinite(rr)) { st->status = 6; st->done = 1; return; }
+    if (st->force_iters > 0) {
+        if (st->iters >= st->force_iters) { st->done = 1; return; }
+    } else {
+        if (sqrt(rr) <= st->tol * sqrt(st->bb)) { st->done = 1; return; }
+        if (st->iters >= st->max_iter) { st->status = 4; st->done = 1; return; }
+    }
+    st->beta = rz / st->rho;
+    st->rho = rz;
+}
+
+void launch_pcg_beta(const double* part, int n, DevState* st, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(kRedBlock), 0, s, part, n, st);
+}
+
+// p = r/D + beta p
+__global__ __launch_bounds__(kBlock) void k_pcg_dir(Geo<double> g, int nc, double dt,
+                                                    const double* dL, const double* r, double* p,
+                                                    const DevState* st)
+{
+    if (st->done) return;
+    const double beta = st->beta;
+    const int nr = g.nr, np = g.np, P = g.P;
+    const size_t N = (size_t)nr * P, NT = N * nc;
+    for (size_t m = (size_t)blockIdx.x * blockDim.x + threadIdx.x; m < NT;
+         m += (size_t)gridDim.x * blockDim.x) {
+        const size_t cell = m % N;
+        const int i = (int)(cell / P), pp = (int)(cell % P), j = pp / np, k = pp % np;
+        const double D = g.vr[i] * g.vt[j] * g.vp[k] + dt * dL[cell];
+        p[m] = r[m] / D + beta * p[m];
+    }
+}
+
+void launch_pcg_dir(const Geo<double>& g, int nc, double dt, const double* diagL, const double* r,
+                    double* p, const DevState* st, hipStream_t s)
+{
+    const int nb = vec_blocks((size_t)g.nr * g.P * nc);
+    hipLaunchKernelGGL(k_pcg_dir, dim3(nb), dim3(kBlock), 0, s, g, nc, dt, diagL, r, p, st);
+}
+
+// ---------------------------------------------------------------- misc
+
+__global__ void k_f64_to_f32(const double* a, float* b, size_t n)
+{
+    for (size_t m = (size_t)blockIdx.x * blockDim.x + threadIdx.x; m < n;
+         m += (size_t)gridDim.x * blockDim.x)
+        b[m] = (float)a[m];
+}
+__global__ void k_f32_to_f64(const float* a, double* b, size_t n)
+{
+    for (size_t m = (size_t)blockIdx.x * blockDim.x + threadIdx.x; m < n;
+         m += (size_t)gridDim.x * blockDim.x)
+        b[m] = (double)a[m];
+}
+__global__ void k_copy16(const uint4* a, uint4* b, size_t n)
+{
+    for (size_t m = (size_t)blockIdx.x * blockDim.x + threadIdx.x; m < n;
+         m += (size_t)gridDim.x * blockDim.x)
+        b[m] = a[m];
+}
+__global__ void k_copy1(const unsigned char* a, unsigned char* b, size_t n)
+{
+    for (size_t m = (size_t)blockIdx.x * blockDim.x + threadIdx.x; m < n;
+         m += (size_t)gridDim.x * blockDim.x)
+        b[m] = a[m];
+}
+__global__ void k_zero1(unsigned char* a, size_t n)
+{
+    for (size_t m = (size_t)blockIdx.x * blockDim.x + threadIdx.x; m < n;
+         m += (size_t)gridDim.x * blockDim.x)
+        a[m] = 0;
+}
+__global__ void k_nonfinite(const double* a, size_t n, int* flag)
+{
+    int bad = 0;
+    for (size_t m = (size_t)blockIdx.x * blockDim.x + threadIdx.x; m < n;
+         m += (size_t)gridDim.x * blockDim.x)
+        if (!isfinite(a[m])) bad = 1;
+    if (bad) atomicOr(flag, 1);
+}
+
+void launch_f64_to_f32(const double* a, float* b, size_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_f64_to_f32, dim3(vec_blocks(n)), dim3(kBlock), 0, s, a, b, n);
+}
+void launch_f32_to_f64(const float* a, double* b, size_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_f32_to_f64, dim3(vec_blocks(n)), dim3(kBlock), 0, s, a, b, n);
+}
+void launch_copy(const void* a, void* b, size_t bytes, hipStream_t s)
+{
+    if (((uintptr_t)a % 16 == 0) && ((uintptr_t)b % 16 == 0) && bytes % 16 == 0)
+        hipLaunchKernelGGL(k_copy16, dim3(vec_blocks(bytes / 16)), dim3(kBlock), 0, s,
+                           (const uint4*)a, (uint4*)b, bytes / 16);
+    else
+        hipLaunchKernelGGL(k_copy1, dim3(vec_blocks(bytes)), dim3(kBlock), 0, s,
+                           (const unsigned char*)a, (unsigned char*)b, bytes);
+}
+void launch_fill_zero(void* a, size_t bytes, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero1, dim3(vec_blocks(bytes)), dim3(kBlock), 0, s, (unsigned char*)a,
+                       bytes);
+}
+void launch_nonfinite(const double* a, size_t n, int* flag, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_nonfinite, dim3(vec_blocks(n)), dim3(kBlock), 0, s, a, n, flag);
+}
+
+}  // namespace pa

@@ -1,0 +1,277 @@
+"""GPU (HIP, gfx950) results against the CPU oracle on the same seeded inputs.
+
+Bar (FP64): relative L2 error <= 1e-12 for every advanced field, and equal
+discrete decisions (cycle count, stages per cycle, PCG iterations, argmax
+index).  Operator applications are compared element by element.  Shapes
+cover ragged plane sizes (not multiples of the 256-cell workgroup), several
+radial chunks per launch, the smallest legal mesh, both boundary kinds and
+both operators; the full 151 x 301 x 400 workload is compared on whole
+fields for the operator, the limit, one STS cycle and a few PCG iterations.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2403_01004_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-12
+
+
+def rel_l2(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_01004_amd import paradv
+    paradv.load()
+    return paradv
+
+
+def problem(op, shape, bc="dirichlet", seed=0, ncomp=None):
+    nr, nt, np_ = shape
+    if op == "aligned":
+        p = inputs.conduction(nr, nt, np_, seed=seed + 201, noise_amp=0.02)
+    elif ncomp == 3:
+        p = inputs.viscosity(nr, nt, np_, seed=seed + 202)
+    else:
+        p = inputs.heat_iso(nr, nt, np_, seed=seed + 101)
+    p.bc_in = p.bc_out = bc
+    return p
+
+
+def pair(dev, oracle_mod, prob, prec="fp64"):
+    g = dev.Operator.from_problem(prob, prec=prec)
+    o = oracle_mod.Oracle.from_problem(prob)
+    return g, o
+
+
+SHAPES = [(9, 10, 13), (17, 24, 40), (1, 2, 3), (6, 12, 400)]
+CASES = [("iso7", None), ("aligned", None), ("iso7", 3)]
+
+
+def _log(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("op,nc", CASES)
+@pytest.mark.parametrize("bc", ["dirichlet", "noflux"])
+def test_apply_diag_dtE(dev, oracle_mod, shape, op, nc, bc):
+    _log("apply", shape, op, nc, bc)
+    prob = problem(op, shape, bc, ncomp=nc)
+    g, o = pair(dev, oracle_mod, prob)
+    u = prob.u
+    for affine in (True, False):
+        Fg = g.apply(u, affine).cpu().numpy()
+        Fo = o.apply(u, affine)
+        err = np.abs(Fg - Fo).max() / max(np.abs(Fo).max(), 1e-300)
+        assert err < 1e-13, (affine, err)
+    d = g.diag().cpu().numpy()
+    assert np.abs(d - o.diag()).max() <= 1e-13 * np.abs(o.diag()).max()
+    assert abs(g.dt_explicit() - o.dt_explicit()) <= 1e-13 * o.dt_explicit()
+
+
+@pytest.mark.parametrize("shape", SHAPES[:3])
+@pytest.mark.parametrize("op,nc", CASES)
+def test_ptl(dev, oracle_mod, shape, op, nc):
+    _log("ptl", shape, op, nc)
+    prob = problem(op, shape, ncomp=nc)
+    g, o = pair(dev, oracle_mod, prob)
+    g.bind(prob.u)
+    dtg, kg = g.ptl()
+    dto, ko = o.ptl(prob.u)
+    assert kg == ko
+    assert dtg == dto or abs(dtg - dto) <= 1e-12 * dto
+
+
+@pytest.mark.parametrize("shape", [(9, 10, 13), (17, 24, 40)])
+@pytest.mark.parametrize("op,nc", CASES)
+@pytest.mark.parametrize("kind", ["rkl2", "rkg2"])
+def test_sts_advance(dev, oracle_mod, shape, op, nc, kind):
+    _log("sts", shape, op, nc, kind)
+    prob = problem(op, shape, ncomp=nc)
+    g, o = pair(dev, oracle_mod, prob)
+    dtE = o.dt_explicit()
+    for cycles, ratio, s_ovr in ((1, 20.0, 0), (2, 9.0, 4), (0, 50.0, 0), (1, 1e-3, 0), (1, 5.0, 2),
+                                 (1, 5.0, 3)):
+        g.set_options(s_override=s_ovr)
+        u = g.bind(prob.u)
+        st = g.advance_sts(ratio * dtE, cycles, sts=kind)
+        uo, so = o.advance_sts(prob.u, ratio * dtE, cycles, sts=kind, s_override=s_ovr)
+        assert st["cycles"] == so["cycles"]
+        assert list(st["per_cycle"]) == list(so["per_cycle"])
+        assert rel_l2(u.cpu().numpy(), uo) <= REL, (cycles, ratio, s_ovr)
+
+
+def be_true_residual(o, prob, x, dt):
+    """||b - M x|| / ||b|| with the oracle's operator: M = V + dt L,
+    b = V u^n + dt V F(0)."""
+    V = o.volumes()[None]
+    b = V * prob.u + dt * V * o.apply(np.zeros_like(prob.u))
+    Mx = V * x - dt * V * o.apply(x, affine=False)
+    return np.linalg.norm(b - Mx) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("shape", [(9, 10, 13), (17, 24, 40)])
+@pytest.mark.parametrize("op,nc", CASES)
+def test_be_advance(dev, oracle_mod, shape, op, nc):
+    """A PCG iterate stopped at ||r|| <= tol ||b|| is defined only to about
+    tol * cond: two correct FP64 runs whose dot products round differently
+    drift apart by a fraction of the iterate's distance to the exact
+    solution.  So: (a) near-exact solves (tol 1e-13) match to 1e-12;
+    (b) at tol 1e-10, identical cycle and iteration counts, agreement to
+    1e-9 relative, and the GPU result satisfies the oracle's own
+    Backward-Euler system to the tolerance."""
+    _log("be", shape, op, nc)
+    prob = problem(op, shape, ncomp=nc)
+    g, o = pair(dev, oracle_mod, prob)
+    dtE = o.dt_explicit()
+    dt = 30.0 * dtE
+    u = g.bind(prob.u)
+    st = g.advance_be(dt, 1e-13, 1)
+    uo, so = o.advance_be(prob.u, dt, 1e-13, 1)
+    assert abs(st["iters_total"] - so["iters_total"]) <= 2
+    assert rel_l2(u.cpu().numpy(), uo) <= REL
+    u = g.bind(prob.u)
+    st = g.advance_be(dt, 1e-10, 1)
+    uo, so = o.advance_be(prob.u, dt, 1e-10, 1)
+    assert st["iters_total"] == so["iters_total"]
+    assert rel_l2(u.cpu().numpy(), uo) <= 1e-9
+    assert be_true_residual(o, prob, u.cpu().numpy(), dt) <= 1.001e-10
+    assert st["rel_residual"] <= 1e-10
+    u = g.bind(prob.u)
+    st = g.advance_be(50.0 * dtE, 1e-10, 0)
+    uo, so = o.advance_be(prob.u, 50.0 * dtE, 1e-10, 0)
+    assert st["cycles"] == so["cycles"]
+    assert list(st["per_cycle"]) == list(so["per_cycle"])
+    assert rel_l2(u.cpu().numpy(), uo) <= 1e-9
+
+
+def test_small_workload_32x32x64(dev, oracle_mod):
+    """Scalar heat equation, kappa = T^{5/2}, Dirichlet T: one RKL2 advance
+    with 10 stages at 24.3 dt_E and one BE + Jacobi-PCG step (tol 1e-10)."""
+    prob = inputs.heat_iso(32, 32, 64)
+    g, o = pair(dev, oracle_mod, prob)
+    dt = 24.3 * o.dt_explicit()
+    g.set_options(s_override=10, force_odd=0)
+    u = g.bind(prob.u)
+    st = g.advance_rkl2(dt, 1)
+    uo, so = o.advance_sts(prob.u, dt, 1, "rkl2", force_odd=False, s_override=10)
+    assert st["s_total"] == 10 and rel_l2(u.cpu().numpy(), uo) <= REL
+    g.set_options()
+    u = g.bind(prob.u)
+    st = g.advance_be(dt, 1e-10, 1)
+    uo, so = o.advance_be(prob.u, dt, 1e-10, 1)
+    assert st["iters_total"] == so["iters_total"]
+    assert rel_l2(u.cpu().numpy(), uo) <= 1e-9
+    assert be_true_residual(o, prob, u.cpu().numpy(), dt) <= 1.001e-10
+    u = g.bind(prob.u)
+    g.advance_be(dt, 1e-13, 1)
+    uo, so = o.advance_be(prob.u, dt, 1e-13, 1)
+    assert rel_l2(u.cpu().numpy(), uo) <= REL
+
+
+def test_deterministic(dev, oracle_mod):
+    prob = problem("aligned", (17, 24, 40))
+    g, _ = pair(dev, oracle_mod, prob)
+    outs = []
+    for _ in range(2):
+        u = g.bind(prob.u)
+        g.advance_be(40 * g.dt_explicit(), 1e-10, 0)
+        g.advance_rkl2(40 * g.dt_explicit(), 0)
+        outs.append(u.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_error_paths(dev, oracle_mod):
+    import torch
+    prob = problem("aligned", (6, 8, 10))
+    g = dev.Operator(prob.mesh, "aligned")
+    u = g.bind(prob.u)
+    before = u.clone()
+    with pytest.raises(dev.PaError) as e:
+        g.advance_rkl2(1.0)
+    assert e.value.status == dev.PA_ERR_STATE
+    with pytest.raises(dev.PaError) as e:
+        g.set_coefficients(np.full(prob.mesh.shape, np.nan), 1.0, 2.5, prob.B)
+    assert e.value.status == dev.PA_ERR_NONFINITE
+    g.set_coefficients(prob.T0, 1.0, 2.5, prob.B)
+    g.set_bc(prob.ub_in, prob.ub_out)
+    with pytest.raises(dev.PaError) as e:
+        g.advance_rkl2(-1.0)
+    assert e.value.status == dev.PA_ERR_ARG
+    with pytest.raises(dev.PaError) as e:
+        g.set_options(s_override=1)
+    assert e.value.status == dev.PA_ERR_ARG
+    assert torch.equal(u, before)
+    dtE = g.dt_explicit()
+    g.set_options(max_iter=1)
+    assert g.advance_be(50 * dtE, 1e-10, 1, check=False)["status"] == dev.PA_ERR_NOCONV
+    g.set_options(max_cycles=1)
+    g.bind(prob.u)
+    assert g.advance_rkl2(50 * dtE, 0, check=False)["status"] == dev.PA_ERR_MAXCYCLES
+    g.set_options()
+    bad = prob.u.copy()
+    bad[0, 2, 3, 4] = np.inf
+    g.bind(bad)
+    with pytest.raises(dev.PaError) as e:
+        g.ptl()
+    assert e.value.status == dev.PA_ERR_NONFINITE
+
+
+# ---------------------------------------------------------------- full size
+
+@pytest.fixture(scope="module")
+def c2(dev, oracle_mod):
+    _log("building 151x301x400 conduction and viscosity inputs")
+    return inputs.conduction(), inputs.viscosity()
+
+
+def test_fullsize_conduction(dev, oracle_mod, c2):
+    prob = c2[0]
+    g, o = pair(dev, oracle_mod, prob)
+    _log("full conduction: apply")
+    Fg = g.apply(prob.u).cpu().numpy()
+    Fo = o.apply(prob.u)
+    assert np.abs(Fg - Fo).max() <= 1e-13 * np.abs(Fo).max()
+    assert abs(g.dt_explicit() - o.dt_explicit()) <= 1e-13 * o.dt_explicit()
+    g.bind(prob.u)
+    assert g.ptl() == o.ptl(prob.u) or abs(g.ptl()[0] - o.ptl(prob.u)[0]) <= 1e-12 * o.ptl(prob.u)[0]
+    dt = 50 * o.dt_explicit()
+    _log("full conduction: one RKL2 cycle")
+    u = g.bind(prob.u)
+    st = g.advance_rkl2(dt, 1)
+    uo, so = o.advance_sts(prob.u, dt, 1, "rkl2")
+    assert st["s_total"] == so["s_total"] == 15
+    assert rel_l2(u.cpu().numpy(), uo) <= REL
+    _log("full conduction: 4 PCG iterations")
+    g.set_options(force_iters=4)
+    u = g.bind(prob.u)
+    g.advance_be(dt, 1e-10, 1)
+    uo, so = o.advance_be(prob.u, dt, 1e-10, 1, force_iters=4)
+    assert rel_l2(u.cpu().numpy(), uo) <= REL
+    g.set_options()
+
+
+def test_fullsize_viscosity(dev, oracle_mod, c2):
+    prob = c2[1]
+    g, o = pair(dev, oracle_mod, prob)
+    _log("full viscosity: apply")
+    Fg = g.apply(prob.u).cpu().numpy()
+    Fo = o.apply(prob.u)
+    assert np.abs(Fg - Fo).max() <= 1e-13 * np.abs(Fo).max()
+    dt = 50 * o.dt_explicit()
+    _log("full viscosity: one RKG2 cycle")
+    u = g.bind(prob.u)
+    st = g.advance_rkg2(dt, 1)
+    uo, so = o.advance_sts(prob.u, dt, 1, "rkg2")
+    assert st["s_total"] == so["s_total"]
+    assert rel_l2(u.cpu().numpy(), uo) <= REL
