@@ -1,0 +1,223 @@
+#!/usr/bin/env python3
+"""Benchmark of the parabolic-operator advance on one MI355X.
+
+One step = one pass of the whole hot path over the 151 x 301 x 400 spherical
+shell (18.2 M cells): lagged-coefficient set-up, then for both split
+operators -- field-aligned Spitzer conduction on T and isotropic viscosity
+on three velocity components -- a PTL-cycled RKL2 advance and a PTL-cycled
+Backward Euler + Jacobi-PCG advance (tol 1e-10), each over dt = 50 times the
+operator's explicit Euler limit.  Every advance starts from the same
+seeded synthetic fields (copied on the device inside the timed region).
+
+value = grid-point operator applications per second: cells x components x
+(STS stages + PCG iterations) summed over the step, divided by the step
+time.  Also reported: seconds per PTL-cycled advance, the roofline of the
+dominant kernel (average launch duration from HIP events recorded on the
+library's stream during the timed steps), and the CPU oracle on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gpts/s per stage & s per PTL-cycled advance; HBM roofline %; PCG iters vs Jacobi"
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "spherical shell 151x301x400 (18.2M cells): field-aligned conduction + 3-component viscosity, PTL-cycled RKL2 and BE+Jacobi-PCG at dt = 50 dt_E"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def bytes_per_launch(op, ncomp, cls, N, NCO, coef_var, stage_k=None):
+    """Algorithmic HBM bytes of one launch (FP64): every array the kernel
+    needs read once, every output written once.  Field-aligned coefficients
+    are 3 doubles per corner; the 7-point operator reads a cell coefficient
+    array only when the coefficient varies."""
+    coef = 24 * NCO if op == "aligned" else (8 * N if coef_var else 0)
+    f = 8 * N * ncomp
+    if cls == "first":
+        return 2 * f + coef
+    if cls == "stage":
+        nread = {2: 2, 3: 3}.get(stage_k, 4)
+        return (nread + 1) * f + coef
+    if cls == "matvec":
+        return 2 * f + coef
+    if cls == "update":
+        return 6 * f + 8 * N
+    if cls == "dir":
+        return 3 * f + 8 * N
+    if cls == "init":
+        return 4 * f + 8 * N
+    return 0
+
+
+def stage_bytes(op, ncomp, N, NCO, coef_var, per_cycle):
+    """Sum of algorithmic bytes over the stage launches of an STS advance."""
+    tot = 0
+    for s in per_cycle:
+        for k in range(2, int(s) + 1):
+            tot += bytes_per_launch(op, ncomp, "stage", N, NCO, coef_var, stage_k=k)
+    return tot
+
+
+def run_cpu_baseline(cond, budget_s=30.0):
+    """Oracle (as it stands) on a bounded sample: one RKL2 cycle of the
+    151x301x400 conduction advance (PTL evaluation + 15 stages)."""
+    import oracle
+    oracle.build(force=False)
+    o = oracle.Oracle.from_problem(cond)
+    dtE = o.dt_explicit()
+    t0 = time.perf_counter()
+    out, st = o.advance_sts(cond.u, 50 * dtE, cycles=1, sts="rkl2")
+    t = time.perf_counter() - t0
+    N = cond.mesh.ncells
+    return {"value": N * st["s_total"] / t / 1e9, "unit": "Gpts/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"one RKL2 cycle ({st['s_total']} stages, dt = 50 dt_E) of the 151x301x400 "
+                      f"field-aligned conduction advance; {t:.1f} s on the host"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--shape", default="151,301,400")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the advance is built for a single MI355X "
+              "(multi-GPU sharding is not part of this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2403_01004_amd import inputs, paradv
+    if not torch.cuda.is_available():
+        print("no GPU available", file=sys.stderr)
+        sys.exit(1)
+    nr, nt, np_ = (int(x) for x in args.shape.split(","))
+    dev = torch.device("cuda:0")
+    log(f"building inputs {nr}x{nt}x{np_}")
+    cond = inputs.conduction(nr, nt, np_)
+    visc = inputs.viscosity(nr, nt, np_)
+    N = nr * nt * np_
+    NCO = (nr + 1) * (nt + 1) * np_
+
+    gc = paradv.Operator(cond.mesh, "aligned", 1, "dirichlet", "dirichlet", "fp64")
+    gv = paradv.Operator(visc.mesh, "iso7", 3, "dirichlet", "dirichlet", "fp64")
+    gc.set_bc(cond.ub_in, cond.ub_out)
+    gv.set_bc(visc.ub_in, visc.ub_out)
+    T0 = torch.as_tensor(cond.T0, device=dev)
+    B = torch.as_tensor(cond.B, device=dev)
+    uc0 = torch.as_tensor(cond.u, device=dev)
+    uv0 = torch.as_tensor(visc.u, device=dev)
+    uc = torch.empty_like(uc0)
+    uv = torch.empty_like(uv0)
+
+    def step(timing):
+        for g in (gc, gv):
+            g.set_options(timing=int(timing))
+        t = {}
+        gc.set_coefficients(T0, 1.0, 2.5, B)
+        gv.set_coefficients(None, 1e-3, 0.0, None)
+        dtc, dtv = 50 * gc.dt_explicit(), 50 * gv.dt_explicit()
+        uc.copy_(uc0)
+        gc.bind(uc)
+        t["rkl2_conduction"] = gc.advance_rkl2(dtc, 0)
+        uv.copy_(uv0)
+        gv.bind(uv)
+        t["rkl2_viscosity"] = gv.advance_rkl2(dtv, 0)
+        uc.copy_(uc0)
+        gc.bind(uc)
+        t["be_conduction"] = gc.advance_be(dtc, 1e-10, 0)
+        uv.copy_(uv0)
+        gv.bind(uv)
+        t["be_viscosity"] = gv.advance_be(dtv, 1e-10, 0)
+        return t
+
+    for w in range(args.warmup):
+        log(f"warmup {w}")
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for k in range(args.steps):
+        stats.append(step(True))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+
+    ncomp = {"rkl2_conduction": 1, "rkl2_viscosity": 3, "be_conduction": 1, "be_viscosity": 3}
+    ops = {"rkl2_conduction": "aligned", "rkl2_viscosity": "iso7", "be_conduction": "aligned",
+           "be_viscosity": "iso7"}
+    work = 0
+    adv = {}
+    kern = {}   # (advance, class) -> [ms, calls, bytes]
+    for t in stats:
+        for name, s in t.items():
+            n = s["s_total"] + s["iters_total"]
+            work += N * ncomp[name] * n
+            a = adv.setdefault(name, {"s": 0.0, "cycles": 0, "stages": 0, "pcg_iters": 0})
+            a["s"] += s["ms_total"] / 1e3 / args.steps
+            a["cycles"] = s["cycles"]
+            a["stages"] = s["s_total"]
+            a["pcg_iters"] = s["iters_total"]
+            for cls, ms in s["kernel_ms"].items():
+                calls = s["kernel_calls"][cls]
+                if calls == 0:
+                    continue
+                if cls in ("matvec", "update", "dir"):
+                    # launches queued after the solve stopped exit at once;
+                    # count one effective launch per iteration and charge
+                    # all launch time to them
+                    calls = s["iters_total"]
+                    if calls == 0:
+                        continue
+                if cls == "stage":
+                    by = stage_bytes(ops[name], ncomp[name], N, NCO, False, s["per_cycle"])
+                else:
+                    by = calls * bytes_per_launch(ops[name], ncomp[name], cls, N, NCO, False)
+                e = kern.setdefault((name, cls), [0.0, 0, 0])
+                e[0] += ms
+                e[1] += calls
+                e[2] += by
+    value = work / elapsed / 1e9
+    (dname, dcls), (dms, dcalls, dbytes) = max(kern.items(), key=lambda kv: kv[1][0])
+    avg_ms = dms / dcalls
+    achieved = dbytes / dcalls / (avg_ms / 1e3) / 1e9
+    kernels = {f"{a}/{c}": {"ms_total": round(v[0] / args.steps, 3), "calls": v[1] // args.steps,
+                            "avg_us": round(1e3 * v[0] / v[1], 2),
+                            "GB_s": round(v[2] / (v[0] / 1e3) / 1e9, 1) if v[2] else None}
+               for (a, c), v in sorted(kern.items(), key=lambda kv: -kv[1][0])}
+
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "Gpts/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "grid": [nr, nt, np_], "dt_over_dtE": 50,
+                   "pcg_tol": 1e-10, "sts": "rkl2", "preconditioner": "jacobi"},
+        "s_per_advance": {k: round(v["s"], 4) for k, v in adv.items()},
+        "advances": adv,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": f"{dname}/{dcls}", "avg_launch_us": round(1e3 * avg_ms, 2),
+                     "bytes_per_launch": int(dbytes / dcalls)},
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = run_cpu_baseline(cond)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

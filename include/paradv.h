@@ -106,7 +106,21 @@ typedef struct {
     int32_t replay_n;     /* >0: cycle lengths taken from replay_dt (parity replays) */
     const double* replay_dt; /* host, replay_n entries; copied by pa_set_options */
     double ptl_floor;     /* limit used = max(dt_PTL, ptl_floor * dt_E). default 1.0 */
+    int32_t timing;       /* 1: time every kernel launch by class (pa_stats.kernel_*). default 0 */
 } pa_opts;
+
+/* kernel classes of pa_stats.kernel_ms / kernel_calls */
+enum {
+    PA_K_FIRST = 0,   /* y0 = F(u) + argmax |F| (PTL pass) */
+    PA_K_STAGE = 1,   /* fused STS stage */
+    PA_K_MATVEC = 2,  /* PCG matvec q = M p + <p,q> */
+    PA_K_UPDATE = 3,  /* PCG x, r update + <r,z>, <r,r> */
+    PA_K_DIR = 4,     /* PCG direction p = z + beta p */
+    PA_K_INIT = 5,    /* PCG start (residual, boundary data) */
+    PA_K_REDUCE = 6,  /* one-workgroup reductions and scalar updates */
+    PA_K_OTHER = 7,   /* conversions and copies */
+    PA_NKCLASS = 8
+};
 
 /* Per-advance statistics. */
 typedef struct {
@@ -116,6 +130,8 @@ typedef struct {
     double dt_ptl_first, dt_ptl_min;
     double rel_residual;      /* PCG: ||r||/||b|| of the last solve */
     double ms_total;          /* wall time of the call on the stream, ms */
+    double kernel_ms[PA_NKCLASS];     /* with opts.timing: summed launch durations per class */
+    int32_t kernel_calls[PA_NKCLASS]; /* with opts.timing: launches per class */
     double dt_cycle[PA_MAX_LOG];   /* length of each cycle */
     int32_t per_cycle[PA_MAX_LOG]; /* stages (STS) or PCG iterations (BE) per cycle */
 } pa_stats;

@@ -80,6 +80,8 @@ def _load():
     lib.or_sts_coeffs.argtypes = [i, i, _D, _D, _D, _D]
     lib.or_sts_stages.restype = i
     lib.or_sts_stages.argtypes = [i, d, i]
+    lib.or_num_threads.restype = i
+    lib.or_num_threads.argtypes = []
     lib.or_advance.restype = i
     lib.or_advance.argtypes = [vp, _D, d, i, i, i, i, i, d, i, i, i, d, _D, i,
                                ctypes.POINTER(_Stats)]
@@ -106,6 +108,11 @@ def sts_coeffs(kind: str, s: int):
     if lib.or_sts_coeffs(STS[kind], s, *[_ptr(a) for a in arr]) != 0:
         raise ValueError("s must be >= 2")
     return tuple(arr)
+
+
+def num_threads() -> int:
+    """OpenMP threads used by the oracle's parallel loops."""
+    return int(_load().or_num_threads())
 
 
 def sts_stages(kind: str, ratio: float, force_odd: bool = True) -> int:

@@ -818,3 +818,16 @@ int or_advance(or_ctx* o, double* u, double dt, int cycles, int scheme, int sts_
     st->cycles = ncyc;
     return status;
 }
+
+/* number of OpenMP threads the oracle's parallel loops use */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -34,6 +34,7 @@ double or_ptl_fullgrid(int nc, int nr, int nt, int np, const double* u, const do
 double or_ptl(or_ctx* o, const double* u, int64_t* kmax);
 int or_sts_coeffs(int kind, int s, double* mu, double* nu, double* mut, double* gam);
 int or_sts_stages(int kind, double ratio, int force_odd);
+int or_num_threads(void);
 int or_advance(or_ctx* o, double* u, double dt, int cycles, int scheme, int sts_kind,
                int force_odd, int s_override, double tol, int max_iter, int force_iters,
                int max_cycles, double ptl_floor, const double* replay_dt, int replay_n,

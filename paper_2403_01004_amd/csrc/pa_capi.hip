@@ -49,6 +49,7 @@ struct pa_ctx {
     double* e64 = nullptr;
     float* e32 = nullptr;
     double* diagL = nullptr;
+    double* Dbuf = nullptr;  // Jacobi diagonal V + dt diag(L) of the current BE solve
     bool have_coef = false;
     double dtE = 0.0;
     // boundary data
@@ -68,6 +69,15 @@ struct pa_ctx {
     int* hflag = nullptr;
     int rch = 16;
     std::vector<void*> allocs;
+    // per-class launch timing (opts.timing): event pairs queued on the
+    // stream, read back at the next synchronisation point
+    struct Pending {
+        int cls;
+        hipEvent_t a, b;
+    };
+    std::vector<hipEvent_t> ev_free;
+    std::vector<Pending> ev_pending;
+    pa_stats* tstats = nullptr;
 };
 
 namespace {
@@ -189,11 +199,61 @@ void stencil(pa_ctx* c, int mode, bool virt, const KArgs<T>& a)
 
 int ntiles(pa_ctx* c, int nlev) { return stencil_tiles((int)c->P, nlev, c->rch, c->d.ncomp); }
 
+hipEvent_t get_event(pa_ctx* c)
+{
+    if (!c->ev_free.empty()) {
+        hipEvent_t e = c->ev_free.back();
+        c->ev_free.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// times the launches queued during its lifetime under one kernel class
+struct KScope {
+    pa_ctx* c;
+    int cls;
+    hipEvent_t a = nullptr;
+    KScope(pa_ctx* c_, int cls_) : c(c_), cls(cls_)
+    {
+        if (c->opt.timing && c->tstats) {
+            a = get_event(c);
+            if (a) (void)hipEventRecord(a, c->stream);
+        }
+    }
+    ~KScope()
+    {
+        if (!a) return;
+        hipEvent_t b = get_event(c);
+        if (!b) { c->ev_free.push_back(a); return; }
+        (void)hipEventRecord(b, c->stream);
+        c->ev_pending.push_back({cls, a, b});
+    }
+};
+
+// after a stream synchronisation: accumulate the finished event pairs
+void flush_timing(pa_ctx* c)
+{
+    for (auto& p : c->ev_pending) {
+        float ms = 0.f;
+        if (c->tstats && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            c->tstats->kernel_ms[p.cls] += ms;
+            c->tstats->kernel_calls[p.cls] += 1;
+        }
+        c->ev_free.push_back(p.a);
+        c->ev_free.push_back(p.b);
+    }
+    c->ev_pending.clear();
+}
+
 pa_status sync_state(pa_ctx* c)
 {
     HIPCHK(c, hipMemcpyAsync(c->hst, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->hflag, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    flush_timing(c);
     return PA_OK;
 }
 
@@ -252,7 +312,11 @@ void first_pass(pa_ctx* c, const T* u0, T* y0)
     KArgs<T> a = base_args<T>(c, 0, c->d.nr);
     a.u = u0;
     a.out = y0;
-    stencil<T>(c, kFirst, false, a);
+    {
+        KScope t(c, PA_K_FIRST);
+        stencil<T>(c, kFirst, false, a);
+    }
+    KScope t(c, PA_K_REDUCE);
     launch_ptl_finalize<T>(c->part, c->part_idx, ntiles(c, c->d.nr), u0, y0, c->d.ncomp, c->d.nr,
                            c->d.nt, c->d.np, c->st, c->stream);
 }
@@ -294,11 +358,17 @@ void sts_cycle(pa_ctx* c, int kind, int s, double dt, T* u0, T* y0, T* A, T* B)
             out = (k == s) ? u0 : prev2;
         }
         a.out = out;
-        stencil<T>(c, kStage, virt, a);
+        {
+            KScope t(c, PA_K_STAGE);
+            stencil<T>(c, kStage, virt, a);
+        }
         if (k == 2) { prev = A; prev2 = B; }
         else { T* t = prev2; prev2 = prev; prev = out == u0 ? prev : t; }
     }
-    if (s == 2) launch_copy(A, u0, sizeof(T) * c->NT, c->stream);
+    if (s == 2) {
+        KScope t(c, PA_K_OTHER);
+        launch_copy(A, u0, sizeof(T) * c->NT, c->stream);
+    }
 }
 
 }  // namespace
@@ -330,6 +400,11 @@ void pa_destroy(pa_ctx* c)
         if (c->d.free) c->d.free(p, c->d.alloc_user);
         else (void)hipFree(p);
     }
+    for (auto& p : c->ev_pending) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (hipEvent_t e : c->ev_free) (void)hipEventDestroy(e);
     if (c->hst) (void)hipHostFree(c->hst);
     if (c->hflag) (void)hipHostFree(c->hflag);
     delete c;
@@ -424,9 +499,10 @@ pa_status pa_init(const pa_desc* d, void* stream, pa_ctx** out)
     const size_t NT = c->NT, N = c->N, bcn = c->P * d->ncomp;
     c->coef64 = (double*)dev_alloc(c, sizeof(double) * N);
     c->diagL = (double*)dev_alloc(c, sizeof(double) * N);
+    c->Dbuf = (double*)dev_alloc(c, sizeof(double) * N);
     c->ub_in = (double*)dev_alloc(c, sizeof(double) * bcn);
     c->ub_out = (double*)dev_alloc(c, sizeof(double) * bcn);
-    ok = ok && c->coef64 && c->diagL && c->ub_in && c->ub_out;
+    ok = ok && c->coef64 && c->diagL && c->Dbuf && c->ub_in && c->ub_out;
     if (d->op == PA_OP_FIELD_ALIGNED) {
         c->e64 = (double*)dev_alloc(c, sizeof(double) * 3 * c->NCO);
         ok = ok && c->e64;
@@ -727,21 +803,27 @@ pa_status advance_sts(pa_ctx* c, int kind, double dt, int32_t cycles, pa_stats* 
     init_stats(st);
     st->dt_explicit = c->dtE;
     Timer tm(c->stream);
+    c->tstats = st;
     launch_fill_zero(c->flag, sizeof(int), c->stream);
     if (c->fp32) {
-        launch_f64_to_f32(c->u, c->f[0], c->NT, c->stream);
+        {
+            KScope t(c, PA_K_OTHER);
+            launch_f64_to_f32(c->u, c->f[0], c->NT, c->stream);
+        }
         s = sts_advance<float>(c, kind, dt, cycles, st, c->f[0], c->f[1], c->f[2], c->f[3]);
+        KScope t(c, PA_K_OTHER);
         launch_f32_to_f64(c->f[0], c->u, c->NT, c->stream);
     } else {
         s = sts_advance<double>(c, kind, dt, cycles, st, c->u, c->w[0], c->w[1], c->w[2]);
     }
     if (hipGetLastError() != hipSuccess && !s) s = fail(c, PA_ERR_HIP, "kernel launch failed");
     st->ms_total = tm.stop();
+    pa_status s2 = sync_state(c);
     if (!s) {
-        pa_status s2 = sync_state(c);
         if (s2) s = s2;
         else if (*c->hflag) s = fail(c, PA_ERR_NONFINITE, "non-finite values in the advance");
     }
+    c->tstats = nullptr;
     st->status = s;
     if (!s) c->err.clear();
     return s;
@@ -761,6 +843,78 @@ pa_status pa_advance_rkg2(pa_ctx* c, double dt, int32_t cycles, pa_stats* st)
     return advance_sts(c, PA_STS_RKG2, dt, cycles, st);
 }
 
+}  // extern "C"
+
+namespace {
+
+// One PCG solve of M d = r0 from the state queued by launch_pcg_init /
+// launch_pcg_resid + launch_pcg_start: iterations are queued in batches of
+// pcg_batch and the host reads the device state after each batch.  PT is
+// the storage type of the search direction and the matvec (double, or float
+// for the FP32-matvec inner solves); x, r and all scalars are FP64.
+template <class PT>
+pa_status pcg_loop(pa_ctx* c, double dtc, double* r, PT* p, PT* q)
+{
+    const int nr = c->d.nr, nc = c->d.ncomp;
+    const int mt = ntiles(c, nr);
+    int nparts = 0;
+    while (true) {
+        for (int b = 0; b < c->opt.pcg_batch; ++b) {
+            KArgs<PT> a = base_args<PT>(c, 0, nr);
+            a.u = p;
+            a.out = q;
+            a.affine = 0;
+            a.dt = dtc;
+            a.done = &c->st->done;
+            {
+                KScope t(c, PA_K_MATVEC);
+                stencil<PT>(c, kMatvec, false, a);
+            }
+            {
+                KScope t(c, PA_K_REDUCE);
+                launch_pcg_alpha(c->part, mt, c->st, c->stream);
+            }
+            {
+                KScope t(c, PA_K_UPDATE);
+                launch_pcg_update<PT>(c->N, nc, c->Dbuf, c->u, r, p, q, c->st, c->part, &nparts,
+                                      c->stream);
+            }
+            {
+                KScope t(c, PA_K_REDUCE);
+                launch_pcg_beta(c->part, nparts, c->st, c->stream);
+            }
+            KScope t(c, PA_K_DIR);
+            launch_pcg_dir<PT>(c->N, nc, c->Dbuf, r, p, c->st, c->stream);
+        }
+        pa_status s = sync_state(c);
+        if (s) return s;
+        if (c->hst->done) return PA_OK;
+    }
+}
+
+// F(0) on the two radial boundary levels into q (the boundary-data part of
+// F, used to form b = V u + dt V F(0))
+void boundary_data(pa_ctx* c, double* q)
+{
+    const int nr = c->d.nr;
+    for (int side = 0; side < 2; ++side) {
+        const int lv = side == 0 ? 0 : nr - 1;
+        if (side == 1 && nr == 1) break;
+        KArgs<double> a = base_args<double>(c, lv, lv + 1);
+        a.rch = 1;
+        a.nrc = 1;
+        a.u = c->u;
+        a.y0 = c->u;
+        a.a1 = -1.0;  // virtual input u - u = 0
+        a.out = q;
+        stencil<double>(c, kApply, true, a);
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
 pa_status pa_advance_be_pcg(pa_ctx* c, double dt, double tol, int32_t cycles, pa_stats* user)
 {
     if (!c) return PA_ERR_ARG;
@@ -773,6 +927,7 @@ pa_status pa_advance_be_pcg(pa_ctx* c, double dt, double tol, int32_t cycles, pa
     init_stats(st);
     st->dt_explicit = c->dtE;
     Timer tm(c->stream);
+    c->tstats = st;
     launch_fill_zero(c->flag, sizeof(int), c->stream);
     double* y0 = c->w[0];
     double* r = c->w[1];
@@ -781,7 +936,9 @@ pa_status pa_advance_be_pcg(pa_ctx* c, double dt, double tol, int32_t cycles, pa
     const Geo<double> g = geo(c, c->m64);
     const int nc = c->d.ncomp, nr = c->d.nr;
     const bool any_dir = c->d.bc_in == PA_BC_DIRICHLET || c->d.bc_out == PA_BC_DIRICHLET;
-    const int mt = ntiles(c, nr);
+    // inner solves of the FP32-matvec variant stop at this fraction of the
+    // true residual they start from
+    const double eta = 1e-5;
     double t_rem = dt;
     int ncyc = 0;
     while (true) {
@@ -790,47 +947,64 @@ pa_status pa_advance_be_pcg(pa_ctx* c, double dt, double tol, int32_t cycles, pa
         int last;
         s = next_cycle(c, dt, cycles, ncyc, t_rem, st, &dtc, &last);
         if (s) break;
-        // boundary-data part of F: F(0) on the two radial boundary levels
-        if (any_dir) {
-            for (int side = 0; side < 2; ++side) {
-                const int lv = side == 0 ? 0 : nr - 1;
-                if (side == 1 && nr == 1) break;
-                KArgs<double> a = base_args<double>(c, lv, lv + 1);
-                a.rch = 1;
-                a.nrc = 1;
-                a.u = c->u;
-                a.y0 = c->u;
-                a.a1 = -1.0;  // virtual input u - u = 0
-                a.out = q;
-                stencil<double>(c, kApply, true, a);
+        int nparts = 0, its = 0;
+        if (!c->fp32) {
+            {
+                KScope t(c, PA_K_INIT);
+                if (any_dir) boundary_data(c, q);
+                launch_pcg_init<double>(g, nc, dtc, c->u, y0, any_dir ? q : nullptr, c->diagL,
+                                        c->Dbuf, r, p, nullptr, c->part, &nparts, c->stream);
             }
-        }
-        int nparts = 0;
-        launch_pcg_init(g, nc, dtc, c->u, y0, any_dir ? q : nullptr, c->diagL, r, p, c->part,
-                        &nparts, c->stream);
-        launch_pcg_start(c->part, nparts, c->st, tol, c->opt.max_iter, c->opt.force_iters,
-                         c->stream);
-        while (true) {
-            for (int b = 0; b < c->opt.pcg_batch; ++b) {
+            {
+                KScope t(c, PA_K_REDUCE);
+                launch_pcg_start(c->part, nparts, c->st, tol, c->opt.max_iter,
+                                 c->opt.force_iters, 0, 0.0, c->stream);
+            }
+            s = pcg_loop<double>(c, dtc, r, p, q);
+            if (s) break;
+            its = c->hst->iters;
+        } else {
+            // defect correction: FP32-matvec PCG on M d = b - M x, x += d,
+            // repeated until the FP64 true residual meets tol
+            double* bvec = p;  // b lives in the FP64 direction buffer
+            float* p32 = c->f[0];
+            float* q32 = c->f[1];
+            {
+                KScope t(c, PA_K_INIT);
+                if (any_dir) boundary_data(c, q);
+                launch_pcg_init<float>(g, nc, dtc, c->u, y0, any_dir ? q : nullptr, c->diagL,
+                                       c->Dbuf, r, p32, bvec, c->part, &nparts, c->stream);
+            }
+            int outer = 0;
+            while (true) {
+                {
+                    KScope t(c, PA_K_REDUCE);
+                    launch_pcg_start(c->part, nparts, c->st, tol, c->opt.max_iter - its,
+                                     c->opt.force_iters, 1, eta, c->stream);
+                }
+                s = sync_state(c);
+                if (s || c->hst->done) break;
+                s = pcg_loop<float>(c, dtc, r, p32, q32);
+                if (s) break;
+                its += c->hst->iters;
+                ++outer;
+                if (c->hst->status != 0 || c->opt.force_iters > 0) break;
+                if (its >= c->opt.max_iter) { c->hst->status = 4; break; }
+                // FP64 true residual r = b - M x and a fresh start
                 KArgs<double> a = base_args<double>(c, 0, nr);
-                a.u = p;
+                a.u = c->u;
                 a.out = q;
                 a.affine = 0;
                 a.dt = dtc;
-                a.done = &c->st->done;
-                stencil<double>(c, kMatvec, false, a);
-                launch_pcg_alpha(c->part, mt, c->st, c->stream);
-                launch_pcg_update(g, nc, dtc, c->diagL, c->u, r, p, q, c->st, c->part, &nparts,
-                                  c->stream);
-                launch_pcg_beta(c->part, nparts, c->st, c->stream);
-                launch_pcg_dir(g, nc, dtc, c->diagL, r, p, c->st, c->stream);
+                {
+                    KScope t(c, PA_K_INIT);
+                    stencil<double>(c, kMatvec, false, a);
+                    launch_pcg_resid<float>(c->N, nc, bvec, q, c->Dbuf, r, p32, c->part, &nparts,
+                                            c->stream);
+                }
             }
-            s = sync_state(c);
             if (s) break;
-            if (c->hst->done) break;
         }
-        if (s) break;
-        const int its = c->hst->iters;
         if (ncyc < PA_MAX_LOG) { st->dt_cycle[ncyc] = dtc; st->per_cycle[ncyc] = its; }
         st->iters_total += its;
         if (its > st->iters_max) st->iters_max = its;
@@ -846,6 +1020,8 @@ pa_status pa_advance_be_pcg(pa_ctx* c, double dt, double tol, int32_t cycles, pa
     st->cycles = ncyc;
     if (hipGetLastError() != hipSuccess && !s) s = fail(c, PA_ERR_HIP, "kernel launch failed");
     st->ms_total = tm.stop();
+    (void)sync_state(c);
+    c->tstats = nullptr;
     st->status = s;
     if (!s) c->err.clear();
     return s;

@@ -95,27 +95,32 @@ struct DevState {
     double dt_ptl;
     long long kmax;
     double gmax;       // Gershgorin maximum
-    double rho, pq, rz, rr, bb, alpha, beta;
+    double rho, pq, rz, rr, bb, alpha, beta, rr0, eta;
     int done, iters, status, nonfinite;
-    int max_iter, force_iters;
+    int max_iter, force_iters, mode;
     double tol;
 };
 void launch_reduce_max(const double* part, int n, double* outp, hipStream_t s);
 template <class T>
 void launch_ptl_finalize(const double* pval, const long long* pidx, int n, const T* u, const T* F,
                          int nc, int nr, int nt, int np, DevState* st, hipStream_t s);
+template <class PT>
 void launch_pcg_init(const Geo<double>& g, int nc, double dt, const double* u, const double* y0,
-                     const double* hF, const double* diagL, double* r, double* p, double* part,
-                     int* nparts, hipStream_t s);
+                     const double* hF, const double* diagL, double* D, double* r, PT* p,
+                     double* b, double* part, int* nparts, hipStream_t s);
+template <class PT>
+void launch_pcg_resid(size_t N, int nc, const double* b, const double* q, const double* D,
+                      double* r, PT* p, double* part, int* nparts, hipStream_t s);
 void launch_pcg_start(const double* part, int n, DevState* st, double tol, int max_iter,
-                      int force_iters, hipStream_t s);
+                      int force_iters, int mode, double eta, hipStream_t s);
 void launch_pcg_alpha(const double* part, int n, DevState* st, hipStream_t s);
-void launch_pcg_update(const Geo<double>& g, int nc, double dt, const double* diagL, double* x,
-                       double* r, const double* p, const double* q, const DevState* st,
-                       double* part, int* nparts, hipStream_t s);
+template <class PT>
+void launch_pcg_update(size_t N, int nc, const double* D, double* x, double* r, const PT* p,
+                       const PT* q, const DevState* st, double* part, int* nparts, hipStream_t s);
 void launch_pcg_beta(const double* part, int n, DevState* st, hipStream_t s);
-void launch_pcg_dir(const Geo<double>& g, int nc, double dt, const double* diagL, const double* r,
-                    double* p, const DevState* st, hipStream_t s);
+template <class PT>
+void launch_pcg_dir(size_t N, int nc, const double* D, const double* r, PT* p, const DevState* st,
+                    hipStream_t s);
 void launch_f64_to_f32(const double* a, float* b, size_t n, hipStream_t s);
 void launch_f32_to_f64(const float* a, double* b, size_t n, hipStream_t s);
 void launch_copy(const void* a, void* b, size_t bytes, hipStream_t s);

@@ -100,13 +100,29 @@ struct Acc {
     int bad = 0;
 };
 
-template <class T, int MODE, bool VIRT>
+// pointwise streams an STS stage combines with F (prefetched one level ahead)
+template <class T>
+struct Streams {
+    T u0 = 0, y0 = 0, km2 = 0;
+};
+
+template <class T, int MODE>
+__device__ __forceinline__ void load_streams(const KArgs<T>& a, size_t m, Streams<T>& s)
+{
+    if constexpr (MODE == kStage) {
+        s.u0 = __builtin_nontemporal_load(a.u0 + m);
+        s.y0 = __builtin_nontemporal_load(a.y0 + m);
+        if (a.km2 == kKm2Array) s.km2 = __builtin_nontemporal_load(a.ukm2 + m);
+    }
+}
+
+template <class T, int MODE>
 __device__ __forceinline__ void epilogue(const KArgs<T>& a, size_t m, T Lu, T V, T uc,
-                                         Acc<T, MODE>& acc)
+                                         const Streams<T>& st, Acc<T, MODE>& acc)
 {
     if constexpr (MODE == kApply || MODE == kFirst) {
         const T F = -Lu / V;
-        a.out[m] = F;
+        __builtin_nontemporal_store(F, a.out + m);
         if constexpr (MODE == kFirst) {
             const double af = fabs((double)F);
             if (af > acc.best) { acc.best = af; acc.bidx = (long long)m; }
@@ -114,17 +130,17 @@ __device__ __forceinline__ void epilogue(const KArgs<T>& a, size_t m, T Lu, T V,
         }
     } else if constexpr (MODE == kStage) {
         const double F = (double)(-Lu / V);
-        const double u0v = (double)a.u0[m];
-        const double y0v = (double)a.y0[m];
+        const double u0v = (double)st.u0;
+        const double y0v = (double)st.y0;
         double km2;
-        if (a.km2 == kKm2Array) km2 = (double)a.ukm2[m];
+        if (a.km2 == kKm2Array) km2 = (double)st.km2;
         else if (a.km2 == kKm2U0) km2 = u0v;
         else km2 = (double)(T)(u0v + a.a1 * y0v);
         const double r = a.mu * (double)uc + a.nu * km2 + a.c0 * u0v + a.mudt * F + a.gdt * y0v;
-        a.out[m] = (T)r;
+        __builtin_nontemporal_store((T)r, a.out + m);
     } else {  // kMatvec
         const T q = V * uc + (T)a.dt * Lu;
-        a.out[m] = q;
+        __builtin_nontemporal_store(q, a.out + m);
         acc.dot += (double)uc * (double)q;
     }
 }
@@ -146,14 +162,24 @@ __device__ void finish(const KArgs<T>& a, int L, Acc<T, MODE>& acc)
     }
 }
 
-// ------------------------------------------------------------ 7-point
-
 template <class T, bool VIRT>
 __device__ __forceinline__ T ldu(const KArgs<T>& a, const T* u, const T* y, size_t q)
 {
     if constexpr (VIRT) return (T)((double)u[q] + a.a1 * (double)y[q]);
     else return u[q];
 }
+
+// ------------------------------------------------------------ 7-point
+//
+// Registers per thread: the centre column at levels i-1, i, i+1 and the
+// four in-plane neighbours at level i; the loads for level i+1 (centre i+2,
+// neighbours, coefficients, stage streams) are issued before level i is
+// computed, so every wave keeps two levels of loads in flight.
+
+template <class T>
+struct Ring7 {
+    T up, w, e, s, n, cp, cw, ce, cs, cn;
+};
 
 template <class T, int MODE, bool VIRT>
 __global__ __launch_bounds__(kBlock) void k_iso7(Geo<T> g, KArgs<T> a)
@@ -179,8 +205,37 @@ __global__ __launch_bounds__(kBlock) void k_iso7(Geo<T> g, KArgs<T> a)
     const T vtj = g.vt[j], vpk = g.vp[k];
     const T gts = g.gtt[j], gtn = g.gtt[j + 1], gpj = g.gpt[j], gpw = g.gpp[k], gpe = g.gpp[kp];
     const size_t ob = (size_t)c * P + pp;  // boundary data offset
+    const int rowo = j * np;
     Acc<T, MODE> acc;
+
+    // loads of level lv+1's centre and level lv's in-plane data.  Every load
+    // is unconditional at an in-bounds address: across a pole the row is
+    // clamped to the cell's own row (the colatitude coupling there is exactly
+    // zero), above the outer level the centre is clamped to the last level
+    // (the boundary closure replaces it).
+    const int rs = hs ? rowo - np : rowo, rn = hn ? rowo + np : rowo;
+    auto fetch = [&](int lv, Ring7<T>& R) {
+        const size_t lvb = (size_t)lv * P;
+        const size_t lup = (lv + 1 < nr) ? lvb + P : lvb;
+        R.up = ldu<T, VIRT>(a, u, y, lup + pp);
+        R.w = ldu<T, VIRT>(a, u, y, lvb + rowo + km);
+        R.e = ldu<T, VIRT>(a, u, y, lvb + rowo + kp);
+        R.s = ldu<T, VIRT>(a, u, y, lvb + rs + k);
+        R.n = ldu<T, VIRT>(a, u, y, lvb + rn + k);
+        if (varc) {
+            R.cp = cf[lup + pp];
+            R.cw = cf[lvb + rowo + km];
+            R.ce = cf[lvb + rowo + kp];
+            R.cs = cf[lvb + rs + k];
+            R.cn = cf[lvb + rn + k];
+        } else {
+            R.cp = R.cw = R.ce = R.cs = R.cn = a.cs;
+        }
+    };
+
     T um = 0, uc = 0, cm = a.cs, cc = a.cs;
+    Ring7<T> cur = {};
+    Streams<T> scur;
     if (i0 < i1) {
         uc = ldu<T, VIRT>(a, u, y, (size_t)i0 * P + pp);
         if (varc) cc = cf[(size_t)i0 * P + pp];
@@ -188,129 +243,181 @@ __global__ __launch_bounds__(kBlock) void k_iso7(Geo<T> g, KArgs<T> a)
             um = ldu<T, VIRT>(a, u, y, (size_t)(i0 - 1) * P + pp);
             if (varc) cm = cf[(size_t)(i0 - 1) * P + pp];
         }
+        fetch(i0, cur);
+        load_streams<T, MODE>(a, cb + (size_t)i0 * P + pp, scur);
     }
     for (int i = i0; i < i1; ++i) {
-        const size_t lv = (size_t)i * P;
-        T up = 0, cp = a.cs;
-        if (i + 1 < nr) {
-            up = ldu<T, VIRT>(a, u, y, lv + P + pp);
-            if (varc) cp = cf[lv + P + pp];
-        }
-        const size_t rowb = lv + (size_t)j * np;
-        const T uw = ldu<T, VIRT>(a, u, y, rowb + km);
-        const T ue = ldu<T, VIRT>(a, u, y, rowb + kp);
-        const T us = hs ? ldu<T, VIRT>(a, u, y, rowb - np + k) : T(0);
-        const T un = hn ? ldu<T, VIRT>(a, u, y, rowb + np + k) : T(0);
-        T cw = a.cs, ce = a.cs, csb = a.cs, cn = a.cs;
-        if (varc) {
-            cw = cf[rowb + km];
-            ce = cf[rowb + kp];
-            if (hs) csb = cf[rowb - np + k];
-            if (hn) cn = cf[rowb + np + k];
+        Ring7<T> nxt = {};
+        Streams<T> snxt;
+        const bool more = i + 1 < i1;
+        if (more) {
+            fetch(i + 1, nxt);
+            load_streams<T, MODE>(a, cb + (size_t)(i + 1) * P + pp, snxt);
         }
         const T half = T(0.5);
         const T gtri = g.gtr[i];
-        T Lu = 0;
-        if (i > 0) Lu += half * (cc + cm) * (g.gr[i] * vtj * vpk) * (uc - um);
-        else if (a.bc_in == 0) {
-            const T ub = a.affine ? a.ub_in[ob] : T(0);
-            Lu += cc * (g.gr[0] * vtj * vpk) * (uc - ub);
+        // radial faces (i is uniform across the workgroup)
+        T Cl, ul, Cu, uu;
+        if (i > 0) {
+            Cl = half * (cc + cm) * (g.gr[i] * vtj * vpk);
+            ul = um;
+        } else {
+            Cl = (a.bc_in == 0) ? cc * (g.gr[0] * vtj * vpk) : T(0);
+            ul = a.affine ? a.ub_in[ob] : T(0);
         }
-        if (i < nr - 1) Lu += half * (cc + cp) * (g.gr[i + 1] * vtj * vpk) * (uc - up);
-        else if (a.bc_out == 0) {
-            const T ub = a.affine ? a.ub_out[ob] : T(0);
-            Lu += cc * (g.gr[nr] * vtj * vpk) * (uc - ub);
+        if (i < nr - 1) {
+            Cu = half * (cc + cur.cp) * (g.gr[i + 1] * vtj * vpk);
+            uu = cur.up;
+        } else {
+            Cu = (a.bc_out == 0) ? cc * (g.gr[nr] * vtj * vpk) : T(0);
+            uu = a.affine ? a.ub_out[ob] : T(0);
         }
-        if (hs) Lu += half * (cc + csb) * (gtri * gts * vpk) * (uc - us);
-        if (hn) Lu += half * (cc + cn) * (gtri * gtn * vpk) * (uc - un);
-        Lu += half * (cc + cw) * (gtri * gpj * gpw) * (uc - uw);
-        Lu += half * (cc + ce) * (gtri * gpj * gpe) * (uc - ue);
+        T Lu = Cl * (uc - ul);
+        Lu += Cu * (uc - uu);
+        Lu += half * (cc + cur.cs) * (gtri * gts * vpk) * (uc - cur.s);
+        Lu += half * (cc + cur.cn) * (gtri * gtn * vpk) * (uc - cur.n);
+        Lu += half * (cc + cur.cw) * (gtri * gpj * gpw) * (uc - cur.w);
+        Lu += half * (cc + cur.ce) * (gtri * gpj * gpe) * (uc - cur.e);
         const T V = g.vr[i] * vtj * vpk;
-        if (valid) epilogue<T, MODE, VIRT>(a, cb + lv + pp, Lu, V, uc, acc);
-        um = uc; uc = up; cm = cc; cc = cp;
+        if (valid) epilogue<T, MODE>(a, cb + (size_t)i * P + pp, Lu, V, uc, scur, acc);
+        um = uc; uc = cur.up; cm = cc; cc = cur.cp;
+        cur = nxt;
+        scur = snxt;
     }
     finish<T, MODE>(a, L, acc);
 }
 
 // ------------------------------------------------------------ field-aligned
+//
+// Per thread and level: the 3x3 (theta, phi) neighbourhood of the thread's
+// cell (rows j-1, j+1 only when the corners that use them exist) and the
+// three coefficients of the four corners A(j,k) B(j,k+1) C(j+1,k) D(j+1,k+1)
+// of the corner plane above.  Level i+2 and corner plane i+2 are fetched
+// while level i is computed.
 
-// values of one radial level on the 3x3 (theta, phi) neighbourhood of the
-// thread's cell; rows j-1 / j+1 only when the corners using them exist
+template <class T>
+struct Nb9 {
+    T x00, x01, x02, x10, x11, x12, x20, x21, x22;
+};
+template <class T>
+struct E12 {
+    T ar, at, ap, br, bt, bp, cr, ct, cp, dr, dt, dp;
+};
+
+// rows r0/r2 are clamped to the cell's own row at the poles, where the
+// corners that use them have zero coefficients
 template <class T, bool VIRT>
-__device__ __forceinline__ void load3x3(const KArgs<T>& a, const T* u, const T* y, size_t lv,
-                                        const int (&off)[3][3], bool hasA, bool hasC, T (&x)[3][3])
+__device__ __forceinline__ void load9(const KArgs<T>& a, const T* u, const T* y, size_t lv, int r0,
+                                      int r1, int r2, int c0, int c1, int c2, Nb9<T>& x)
 {
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-        const bool use = (r == 0) ? hasA : (r == 2) ? hasC : true;
-#pragma unroll
-        for (int q = 0; q < 3; ++q) x[r][q] = use ? ldu<T, VIRT>(a, u, y, lv + off[r][q]) : T(0);
-    }
+    x.x00 = ldu<T, VIRT>(a, u, y, lv + r0 + c0);
+    x.x01 = ldu<T, VIRT>(a, u, y, lv + r0 + c1);
+    x.x02 = ldu<T, VIRT>(a, u, y, lv + r0 + c2);
+    x.x10 = ldu<T, VIRT>(a, u, y, lv + r1 + c0);
+    x.x11 = ldu<T, VIRT>(a, u, y, lv + r1 + c1);
+    x.x12 = ldu<T, VIRT>(a, u, y, lv + r1 + c2);
+    x.x20 = ldu<T, VIRT>(a, u, y, lv + r2 + c0);
+    x.x21 = ldu<T, VIRT>(a, u, y, lv + r2 + c1);
+    x.x22 = ldu<T, VIRT>(a, u, y, lv + r2 + c2);
+}
+
+template <class T>
+__device__ __forceinline__ void load_e(const T* e, size_t nco, size_t q0, size_t q1, int k, int kp,
+                                       E12<T>& E)
+{
+    E.ar = e[q0 + k]; E.at = e[nco + q0 + k]; E.ap = e[2 * nco + q0 + k];
+    E.br = e[q0 + kp]; E.bt = e[nco + q0 + kp]; E.bp = e[2 * nco + q0 + kp];
+    E.cr = e[q1 + k]; E.ct = e[nco + q1 + k]; E.cp = e[2 * nco + q1 + k];
+    E.dr = e[q1 + kp]; E.dt = e[nco + q1 + kp]; E.dp = e[2 * nco + q1 + kp];
 }
 
 // mirror ghost level across a radial boundary: Dirichlet 2 u_b - u (u_b = 0
 // in linear mode), no-flux u
 template <class T>
-__device__ __forceinline__ void ghost3x3(const T (&x)[3][3], const T* ub, int bc, int affine,
-                                         size_t ob, const int (&off)[3][3], bool hasA, bool hasC,
-                                         T (&gx)[3][3])
+__device__ __forceinline__ T ghost1(T x, const T* ub, size_t o, int bc, int affine)
 {
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-        const bool use = (r == 0) ? hasA : (r == 2) ? hasC : true;
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            if (bc == 0) {
-                const T b = (affine && use) ? ub[ob + off[r][q]] : T(0);
-                gx[r][q] = T(2) * b - x[r][q];
-            } else {
-                gx[r][q] = x[r][q];
-            }
-        }
-    }
+    if (bc != 0) return x;
+    const T b = affine ? ub[o] : T(0);
+    return T(2) * b - x;
 }
 
-// Fluxes t of the four corners A(j,k) B(j,k+1) C(j+1,k) D(j+1,k+1) of corner
-// plane ic, between levels lo and hi, and the scatter weights of the
-// thread's cell as the upper (wt) and lower (wb) cell of that plane.
 template <class T>
-__device__ __forceinline__ void corner_plane(const T (&lo)[3][3], const T (&hi)[3][3], const T* e,
-                                             size_t nco, size_t qrow0, size_t qrow1, int k, int kp,
-                                             bool hasA, bool hasC, int kind, int bc, T& up_sum,
-                                             T& dn_sum)
+__device__ __forceinline__ void ghost9(const Nb9<T>& x, const T* ub, int bc, int affine,
+                                       size_t ob, int r0, int r1, int r2, int c0, int c1, int c2,
+                                       Nb9<T>& gx)
 {
-    // kind: 0 interior plane, 1 inner boundary (real cells above), 2 outer boundary
-    T s[3][3], d[3][3];
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int q = 0; q < 3; ++q) { s[r][q] = lo[r][q] + hi[r][q]; d[r][q] = hi[r][q] - lo[r][q]; }
-    up_sum = 0;
-    dn_sum = 0;
-    const T qt = T(0.25), hf = T(0.5);
-#pragma unroll
-    for (int cr = 0; cr < 4; ++cr) {
-        const int r0 = cr >> 1, c0 = cr & 1;
-        if ((r0 == 0 && !hasA) || (r0 == 1 && !hasC)) continue;
-        const size_t q = (r0 ? qrow1 : qrow0) + (c0 ? kp : k);
-        const T er = e[q], et = e[nco + q], ep = e[2 * nco + q];
-        const T Dr = qt * (d[r0][c0] + d[r0][c0 + 1] + d[r0 + 1][c0] + d[r0 + 1][c0 + 1]);
-        const T Dt = qt * (s[r0 + 1][c0] + s[r0 + 1][c0 + 1] - s[r0][c0] - s[r0][c0 + 1]);
-        const T Dp = qt * (s[r0][c0 + 1] + s[r0 + 1][c0 + 1] - s[r0][c0] - s[r0 + 1][c0]);
-        const T t = er * Dr + et * Dt + ep * Dp;
-        // the thread's cell sits at row 1, column 1 of the neighbourhood
-        const T st = r0 ? T(-1) : T(1);
-        const T sp = c0 ? T(-1) : T(1);
-        const T tang = st * et + sp * ep;
-        if (kind == 0) {
-            up_sum += qt * (er + tang) * t;
-            dn_sum += qt * (-er + tang) * t;
-        } else if (kind == 1) {
-            up_sum += (bc == 0 ? hf * er : hf * tang) * t;
-        } else {
-            dn_sum += (bc == 0 ? -hf * er : hf * tang) * t;
-        }
+    gx.x00 = ghost1(x.x00, ub, ob + r0 + c0, bc, affine);
+    gx.x01 = ghost1(x.x01, ub, ob + r0 + c1, bc, affine);
+    gx.x02 = ghost1(x.x02, ub, ob + r0 + c2, bc, affine);
+    gx.x10 = ghost1(x.x10, ub, ob + r1 + c0, bc, affine);
+    gx.x11 = ghost1(x.x11, ub, ob + r1 + c1, bc, affine);
+    gx.x12 = ghost1(x.x12, ub, ob + r1 + c2, bc, affine);
+    gx.x20 = ghost1(x.x20, ub, ob + r2 + c0, bc, affine);
+    gx.x21 = ghost1(x.x21, ub, ob + r2 + c1, bc, affine);
+    gx.x22 = ghost1(x.x22, ub, ob + r2 + c2, bc, affine);
+}
+
+// Scatter weights of the thread's cell for one corner plane: as the upper
+// cell (wu) and the lower cell (wd) of a corner with coefficients (er, et, ep)
+// where st, sp = +1 when the cell is the corner's upper row / column.
+// kind 0: interior plane; 1: inner radial boundary (real cells above);
+// 2: outer radial boundary (real cells below).
+template <class T>
+struct PlaneW {
+    T ru, rd, tu, td;  // wu = ru*er + tu*tang, wd = rd*er + td*tang
+};
+
+template <class T>
+__device__ __forceinline__ PlaneW<T> plane_weights(int kind, int bc)
+{
+    PlaneW<T> w;
+    if (kind == 0) {
+        w.ru = T(0.25); w.rd = T(-0.25); w.tu = T(0.25); w.td = T(0.25);
+    } else if (kind == 1) {
+        w.ru = bc == 0 ? T(0.5) : T(0); w.tu = bc == 0 ? T(0) : T(0.5); w.rd = T(0); w.td = T(0);
+    } else {
+        w.rd = bc == 0 ? T(-0.5) : T(0); w.td = bc == 0 ? T(0) : T(0.5); w.ru = T(0); w.tu = T(0);
     }
+    return w;
+}
+
+// one corner: flux t = e . D, D the averaged differences over its 2x2x2
+// cells (lower level l*, upper level h*: 00 = (row0,col0), 01 = (row0,col1),
+// 10 = (row1,col0), 11 = (row1,col1)); accumulates the cell's weight times t
+template <class T>
+__device__ __forceinline__ void corner1(T l00, T l01, T l10, T l11, T h00, T h01, T h10, T h11,
+                                        T er, T et, T ep, T st, T sp, const PlaneW<T>& w, T& up,
+                                        T& dn)
+{
+    const T qt = T(0.25);
+    const T s00 = l00 + h00, s01 = l01 + h01, s10 = l10 + h10, s11 = l11 + h11;
+    const T Dr = qt * ((h00 - l00) + (h01 - l01) + (h10 - l10) + (h11 - l11));
+    const T Dt = qt * (s10 + s11 - s00 - s01);
+    const T Dp = qt * (s01 + s11 - s00 - s10);
+    const T t = er * Dr + et * Dt + ep * Dp;
+    const T tang = st * et + sp * ep;
+    up += (w.ru * er + w.tu * tang) * t;
+    dn += (w.rd * er + w.td * tang) * t;
+}
+
+template <class T>
+__device__ __forceinline__ void corner_plane(const Nb9<T>& lo, const Nb9<T>& hi, const E12<T>& E,
+                                             const PlaneW<T>& w, T& up, T& dn)
+{
+    up = 0;
+    dn = 0;
+    // A: rows (j-1, j), columns (k-1, k): the cell is row 1, column 1
+    corner1<T>(lo.x00, lo.x01, lo.x10, lo.x11, hi.x00, hi.x01, hi.x10, hi.x11, E.ar, E.at, E.ap,
+               T(1), T(1), w, up, dn);
+    // B: rows (j-1, j), columns (k, k+1)
+    corner1<T>(lo.x01, lo.x02, lo.x11, lo.x12, hi.x01, hi.x02, hi.x11, hi.x12, E.br, E.bt, E.bp,
+               T(1), T(-1), w, up, dn);
+    // C: rows (j, j+1), columns (k-1, k)
+    corner1<T>(lo.x10, lo.x11, lo.x20, lo.x21, hi.x10, hi.x11, hi.x20, hi.x21, E.cr, E.ct, E.cp,
+               T(-1), T(1), w, up, dn);
+    // D: rows (j, j+1), columns (k, k+1)
+    corner1<T>(lo.x11, lo.x12, lo.x21, lo.x22, hi.x11, hi.x12, hi.x21, hi.x22, E.dr, E.dt, E.dp,
+               T(-1), T(-1), w, up, dn);
 }
 
 template <class T, int MODE, bool VIRT>
@@ -326,57 +433,66 @@ __global__ __launch_bounds__(kBlock) void k_aligned(Geo<T> g, KArgs<T> a)
     const int pp = valid ? p : P - 1;
     const int j = pp / np, k = pp - j * np;
     const int km = (k == 0) ? np - 1 : k - 1, kp = (k == np - 1) ? 0 : k + 1;
-    const bool hasA = j >= 1, hasC = j + 1 <= nt - 1;
-    int off[3][3];
-    const int cols[3] = {km, k, kp};
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int q = 0; q < 3; ++q) off[r][q] = (j + r - 1) * np + cols[q];
+    const int r1 = j * np;
+    const int r0 = (j >= 1) ? r1 - np : r1, r2 = (j + 1 <= nt - 1) ? r1 + np : r1;
     const size_t cb = (size_t)c * nr * P;
     const T* u = a.u + cb;
     const T* y = VIRT ? a.y0 + cb : nullptr;
     const size_t ob = (size_t)c * P;
     const size_t nco = (size_t)(nr + 1) * (nt + 1) * np;
     const size_t cplane = (size_t)(nt + 1) * np;
+    const size_t qa = (size_t)j * np, qc = (size_t)(j + 1) * np;  // corner rows j, j+1 (<= nt)
     const int i0 = a.r_lo + rc * a.rch;
     const int i1 = min(a.r_hi, i0 + a.rch);
     const T vtj = g.vt[j], vpk = g.vp[k];
     Acc<T, MODE> acc;
-    T lo[3][3], hi[3][3];
+    Nb9<T> lo = {}, hi = {}, nx = {};
+    E12<T> E = {}, En = {};
+    Streams<T> scur, snxt;
     T carry = 0;
     if (i0 < i1) {
-        load3x3<T, VIRT>(a, u, y, (size_t)i0 * P, off, hasA, hasC, hi);
-        if (i0 == 0) ghost3x3<T>(hi, a.ub_in, a.bc_in, a.affine, ob, off, hasA, hasC, lo);
-        else load3x3<T, VIRT>(a, u, y, (size_t)(i0 - 1) * P, off, hasA, hasC, lo);
+        load9<T, VIRT>(a, u, y, (size_t)i0 * P, r0, r1, r2, km, k, kp, hi);
+        if (i0 == 0)
+            ghost9<T>(hi, a.ub_in, a.bc_in, a.affine, ob, r0, r1, r2, km, k, kp, lo);
+        else
+            load9<T, VIRT>(a, u, y, (size_t)(i0 - 1) * P, r0, r1, r2, km, k, kp, lo);
+        load_e<T>(a.e, nco, (size_t)i0 * cplane + qa, (size_t)i0 * cplane + qc, k, kp, E);
         T up, dn;
-        const size_t qb = (size_t)i0 * cplane;
-        corner_plane<T>(lo, hi, a.e, nco, qb + (size_t)j * np, qb + (size_t)(j + 1) * np, k, kp,
-                        hasA, hasC, i0 == 0 ? 1 : 0, a.bc_in, up, dn);
+        corner_plane<T>(lo, hi, E, plane_weights<T>(i0 == 0 ? 1 : 0, a.bc_in), up, dn);
         carry = up;
+        // level i0+1 and corner plane i0+1 for the first iteration
+        load9<T, VIRT>(a, u, y, (size_t)min(i0 + 1, nr - 1) * P, r0, r1, r2, km, k, kp, nx);
+        load_e<T>(a.e, nco, (size_t)(i0 + 1) * cplane + qa, (size_t)(i0 + 1) * cplane + qc, k, kp,
+                  E);
+        load_streams<T, MODE>(a, cb + (size_t)i0 * P + pp, scur);
     }
     for (int i = i0; i < i1; ++i) {
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int q = 0; q < 3; ++q) lo[r][q] = hi[r][q];
         const int ic = i + 1;
+        lo = hi;
         int kind = 0, bc = 0;
         if (ic < nr) {
-            load3x3<T, VIRT>(a, u, y, (size_t)ic * P, off, hasA, hasC, hi);
+            hi = nx;
         } else {
-            ghost3x3<T>(lo, a.ub_out, a.bc_out, a.affine, ob, off, hasA, hasC, hi);
+            ghost9<T>(lo, a.ub_out, a.bc_out, a.affine, ob, r0, r1, r2, km, k, kp, hi);
             kind = 2;
             bc = a.bc_out;
         }
+        // prefetch level i+2 and corner plane i+2 for the next iteration
+        const bool more = i + 1 < i1;
+        if (more) {
+            load9<T, VIRT>(a, u, y, (size_t)min(ic + 1, nr - 1) * P, r0, r1, r2, km, k, kp, nx);
+            load_e<T>(a.e, nco, (size_t)(ic + 1) * cplane + qa, (size_t)(ic + 1) * cplane + qc, k,
+                      kp, En);
+            load_streams<T, MODE>(a, cb + (size_t)(i + 1) * P + pp, snxt);
+        }
         T up, dn;
-        const size_t qb = (size_t)ic * cplane;
-        corner_plane<T>(lo, hi, a.e, nco, qb + (size_t)j * np, qb + (size_t)(j + 1) * np, k, kp,
-                        hasA, hasC, kind, bc, up, dn);
+        corner_plane<T>(lo, hi, E, plane_weights<T>(kind, bc), up, dn);
         const T Lu = carry + dn;
         carry = up;
         const T V = g.vr[i] * vtj * vpk;
-        if (valid) epilogue<T, MODE, VIRT>(a, cb + (size_t)i * P + pp, Lu, V, lo[1][1], acc);
+        if (valid) epilogue<T, MODE>(a, cb + (size_t)i * P + pp, Lu, V, lo.x11, scur, acc);
+        E = En;
+        scur = snxt;
     }
     finish<T, MODE>(a, L, acc);
 }

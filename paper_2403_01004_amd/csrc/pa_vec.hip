@@ -134,50 +134,6 @@ template void launch_ptl_finalize<float>(const double*, const long long*, int, c
 
 // ---------------------------------------------------------------- PCG
 
-// r0 = b - M u = dt V F(u) (y0 from the PTL pass), b = V (u + dt hF) with hF
-// = F(0) the boundary-data part of F, read on the two radial boundary levels
-// only (zero elsewhere; hF may be null when both sides are no-flux),
-// z = r/D, p = z; partials <r,z>, <r,r>, <b,b>.
-__global__ __launch_bounds__(kBlock) void k_pcg_init(Geo<double> g, int nc, double dt,
-                                                     const double* u, const double* y0,
-                                                     const double* hF, const double* dL,
-                                                     double* r, double* p, double* part)
-{
-    __shared__ double lds[kBlock / 64];
-    const int nr = g.nr, np = g.np, P = g.P;
-    const size_t N = (size_t)nr * P, NT = N * nc;
-    double rz = 0.0, rr = 0.0, bb = 0.0;
-    for (size_t m = (size_t)blockIdx.x * blockDim.x + threadIdx.x; m < NT;
-         m += (size_t)gridDim.x * blockDim.x) {
-        const size_t cell = m % N;
-        const int i = (int)(cell / P), pp = (int)(cell % P), j = pp / np, k = pp % np;
-        const double V = g.vr[i] * g.vt[j] * g.vp[k];
-        const double D = V + dt * dL[cell];
-        const double h = (hF && (i == 0 || i == nr - 1)) ? hF[m] : 0.0;
-        const double b = V * u[m] + dt * V * h;
-        const double rv = dt * V * y0[m];
-        const double z = rv / D;
-        r[m] = rv;
-        p[m] = z;
-        rz += rv * z;
-        rr += rv * rv;
-        bb += b * b;
-    }
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    double vals[3] = {rz, rr, bb};
-    for (int q = 0; q < 3; ++q) {
-        double v = wsum(vals[q]);
-        __syncthreads();
-        if (lane == 0) lds[w] = v;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double sacc = 0.0;
-            for (int x = 0; x < kBlock / 64; ++x) sacc += lds[x];
-            part[(size_t)q * gridDim.x + blockIdx.x] = sacc;
-        }
-    }
-}
-
 static int vec_blocks(size_t n)
 {
     size_t nb = (n + kBlock - 1) / kBlock;
@@ -185,18 +141,128 @@ static int vec_blocks(size_t n)
     return (int)nb;
 }
 
-void launch_pcg_init(const Geo<double>& g, int nc, double dt, const double* u, const double* y0,
-                     const double* hF, const double* diagL, double* r, double* p, double* part,
-                     int* nparts, hipStream_t s)
+// deterministic per-block sums of up to 3 accumulators into part[q*nb + b]
+template <int NV>
+__device__ __forceinline__ void block_partials(const double (&v)[NV], double* part)
 {
-    const int nb = vec_blocks((size_t)g.nr * g.P * nc);
-    *nparts = nb;
-    hipLaunchKernelGGL(k_pcg_init, dim3(nb), dim3(kBlock), 0, s, g, nc, dt, u, y0, hF, diagL, r,
-                       p, part);
+    __shared__ double lds[kBlock / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        const double x = wsum(v[q]);
+        __syncthreads();
+        if (lane == 0) lds[w] = x;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double sacc = 0.0;
+            for (int t = 0; t < kBlock / 64; ++t) sacc += lds[t];
+            part[(size_t)q * gridDim.x + blockIdx.x] = sacc;
+        }
+    }
 }
 
+// Start of a Backward Euler solve, per cell (all components):
+// D = V + dt diag(L) (stored), b = V (u + dt hF) with hF = F(0) the
+// boundary-data part of F (read on the two radial boundary levels only; may
+// be null when both sides are no-flux), r0 = b - M u = dt V F(u) (y0 from
+// the PTL pass), p = r0/D.  Writes D, r, p (and b when bout != null);
+// partials <r,z>, <r,r>, <b,b>.
+template <class PT>
+__global__ __launch_bounds__(kBlock) void k_pcg_init(Geo<double> g, int nc, double dt,
+                                                     const double* u, const double* y0,
+                                                     const double* hF, const double* dL,
+                                                     double* Dout, double* r, PT* p, double* bout,
+                                                     double* part)
+{
+    const int nr = g.nr, np = g.np;
+    const unsigned P = (unsigned)g.P, N = (unsigned)nr * P;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (unsigned cell = blockIdx.x * blockDim.x + threadIdx.x; cell < N;
+         cell += gridDim.x * blockDim.x) {
+        const unsigned i = cell / P, pp = cell - i * P, j = pp / (unsigned)np, k = pp - j * np;
+        const double V = g.vr[i] * g.vt[j] * g.vp[k];
+        const double D = V + dt * dL[cell];
+        Dout[cell] = D;
+        const bool bnd = hF && (i == 0 || i == (unsigned)nr - 1);
+        for (int c = 0; c < nc; ++c) {
+            const size_t m = (size_t)c * N + cell;
+            const double h = bnd ? hF[m] : 0.0;
+            const double b = V * u[m] + dt * V * h;
+            const double rv = dt * V * y0[m];
+            const double z = rv / D;
+            r[m] = rv;
+            p[m] = (PT)z;
+            if (bout) bout[m] = b;
+            acc[0] += rv * z;
+            acc[1] += rv * rv;
+            acc[2] += b * b;
+        }
+    }
+    block_partials<3>(acc, part);
+}
+
+template <class PT>
+void launch_pcg_init(const Geo<double>& g, int nc, double dt, const double* u, const double* y0,
+                     const double* hF, const double* diagL, double* D, double* r, PT* p,
+                     double* b, double* part, int* nparts, hipStream_t s)
+{
+    const int nb = vec_blocks((size_t)g.nr * g.P);
+    *nparts = nb;
+    hipLaunchKernelGGL((k_pcg_init<PT>), dim3(nb), dim3(kBlock), 0, s, g, nc, dt, u, y0, hF, diagL,
+                       D, r, p, b, part);
+}
+template void launch_pcg_init<double>(const Geo<double>&, int, double, const double*, const double*,
+                                      const double*, const double*, double*, double*, double*,
+                                      double*, double*, int*, hipStream_t);
+template void launch_pcg_init<float>(const Geo<double>&, int, double, const double*, const double*,
+                                     const double*, const double*, double*, double*, float*,
+                                     double*, double*, int*, hipStream_t);
+
+// Defect correction: r = b - q (q = M x from an FP64 matvec), p = r/D;
+// partials <r,z>, <r,r>, <b,b>.
+template <class PT>
+__global__ __launch_bounds__(kBlock) void k_pcg_resid(unsigned N, int nc, const double* b,
+                                                      const double* q, const double* D, double* r,
+                                                      PT* p, double* part)
+{
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (unsigned cell = blockIdx.x * blockDim.x + threadIdx.x; cell < N;
+         cell += gridDim.x * blockDim.x) {
+        const double d = D[cell];
+        for (int c = 0; c < nc; ++c) {
+            const size_t m = (size_t)c * N + cell;
+            const double bv = b[m];
+            const double rv = bv - q[m];
+            const double z = rv / d;
+            r[m] = rv;
+            p[m] = (PT)z;
+            acc[0] += rv * z;
+            acc[1] += rv * rv;
+            acc[2] += bv * bv;
+        }
+    }
+    block_partials<3>(acc, part);
+}
+
+template <class PT>
+void launch_pcg_resid(size_t N, int nc, const double* b, const double* q, const double* D,
+                      double* r, PT* p, double* part, int* nparts, hipStream_t s)
+{
+    const int nb = vec_blocks(N);
+    *nparts = nb;
+    hipLaunchKernelGGL((k_pcg_resid<PT>), dim3(nb), dim3(kBlock), 0, s, (unsigned)N, nc, b, q, D, r,
+                       p, part);
+}
+template void launch_pcg_resid<float>(size_t, int, const double*, const double*, const double*,
+                                      double*, float*, double*, int*, hipStream_t);
+template void launch_pcg_resid<double>(size_t, int, const double*, const double*, const double*,
+                                       double*, double*, double*, int*, hipStream_t);
+
+// mode 0: stop when ||r|| <= tol ||b||.  mode 1 (inner solve of a defect
+// correction): stop when ||r|| <= eta ||r0|| or ||r|| <= tol ||b||.
 __global__ __launch_bounds__(kRedBlock) void k_pcg_start(const double* part, int n, DevState* st,
-                                                          double tol, int max_iter, int force_iters)
+                                                          double tol, int max_iter, int force_iters,
+                                                          int mode, double eta)
 {
     const double rz = red_sum(part, n);
     const double rr = red_sum(part + n, n);
@@ -211,15 +277,18 @@ __global__ __launch_bounds__(kRedBlock) void k_pcg_start(const double* part, int
     st->iters = 0;
     st->status = 0;
     st->done = 0;
+    st->mode = mode;
+    st->rr0 = rr;
+    st->eta = eta;
     if (!isfinite(rr) || !isfinite(bb)) { st->status = 6; st->done = 1; return; }
     if (st->force_iters <= 0 && sqrt(rr) <= st->tol * sqrt(bb)) st->done = 1;
 }
 
 void launch_pcg_start(const double* part, int n, DevState* st, double tol, int max_iter,
-                      int force_iters, hipStream_t s)
+                      int force_iters, int mode, double eta, hipStream_t s)
 {
     hipLaunchKernelGGL(k_pcg_start, dim3(1), dim3(kRedBlock), 0, s, part, n, st, tol, max_iter,
-                       force_iters);
+                       force_iters, mode, eta);
 }
 
 __global__ __launch_bounds__(kRedBlock) void k_pcg_alpha(const double* part, int n, DevState* st)
@@ -238,55 +307,46 @@ void launch_pcg_alpha(const double* part, int n, DevState* st, hipStream_t s)
 }
 
 // x += alpha p, r -= alpha q, z = r/D; partials <r,z>, <r,r>
-__global__ __launch_bounds__(kBlock) void k_pcg_update(Geo<double> g, int nc, double dt,
-                                                       const double* dL, double* x, double* r,
-                                                       const double* p, const double* q,
-                                                       const DevState* st, double* part)
+template <class PT>
+__global__ __launch_bounds__(kBlock) void k_pcg_update(unsigned N, int nc, const double* Db,
+                                                       double* x, double* r, const PT* p,
+                                                       const PT* q, const DevState* st,
+                                                       double* part)
 {
-    __shared__ double lds[kBlock / 64];
     if (st->done) return;
     const double alpha = st->alpha;
-    const int nr = g.nr, np = g.np, P = g.P;
-    const size_t N = (size_t)nr * P, NT = N * nc;
-    double rz = 0.0, rr = 0.0;
-    for (size_t m = (size_t)blockIdx.x * blockDim.x + threadIdx.x; m < NT;
-         m += (size_t)gridDim.x * blockDim.x) {
-        const size_t cell = m % N;
-        const int i = (int)(cell / P), pp = (int)(cell % P), j = pp / np, k = pp % np;
-        const double D = g.vr[i] * g.vt[j] * g.vp[k] + dt * dL[cell];
-        x[m] += alpha * p[m];
-        const double rv = r[m] - alpha * q[m];
-        r[m] = rv;
-        const double z = rv / D;
-        rz += rv * z;
-        rr += rv * rv;
-    }
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    double vals[2] = {rz, rr};
-    for (int t = 0; t < 2; ++t) {
-        double v = wsum(vals[t]);
-        __syncthreads();
-        if (lane == 0) lds[w] = v;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double sacc = 0.0;
-            for (int xx = 0; xx < kBlock / 64; ++xx) sacc += lds[xx];
-            part[(size_t)t * gridDim.x + blockIdx.x] = sacc;
+    double acc[2] = {0.0, 0.0};
+    for (unsigned cell = blockIdx.x * blockDim.x + threadIdx.x; cell < N;
+         cell += gridDim.x * blockDim.x) {
+        const double D = Db[cell];
+        for (int c = 0; c < nc; ++c) {
+            const size_t m = (size_t)c * N + cell;
+            x[m] += alpha * (double)p[m];
+            const double rv = r[m] - alpha * (double)q[m];
+            r[m] = rv;
+            const double z = rv / D;
+            acc[0] += rv * z;
+            acc[1] += rv * rv;
         }
     }
+    block_partials<2>(acc, part);
 }
 
-void launch_pcg_update(const Geo<double>& g, int nc, double dt, const double* diagL, double* x,
-                       double* r, const double* p, const double* q, const DevState* st,
-                       double* part, int* nparts, hipStream_t s)
+template <class PT>
+void launch_pcg_update(size_t N, int nc, const double* D, double* x, double* r, const PT* p,
+                       const PT* q, const DevState* st, double* part, int* nparts, hipStream_t s)
 {
-    const int nb = vec_blocks((size_t)g.nr * g.P * nc);
+    const int nb = vec_blocks(N);
     *nparts = nb;
-    hipLaunchKernelGGL(k_pcg_update, dim3(nb), dim3(kBlock), 0, s, g, nc, dt, diagL, x, r, p, q,
-                       st, part);
+    hipLaunchKernelGGL((k_pcg_update<PT>), dim3(nb), dim3(kBlock), 0, s, (unsigned)N, nc, D, x, r,
+                       p, q, st, part);
 }
+template void launch_pcg_update<double>(size_t, int, const double*, double*, double*, const double*,
+                                        const double*, const DevState*, double*, int*, hipStream_t);
+template void launch_pcg_update<float>(size_t, int, const double*, double*, double*, const float*,
+                                       const float*, const DevState*, double*, int*, hipStream_t);
 
-// stopping test and beta (Hestenes-Stiefel PCG with rho = <r, z>)
+// stopping test and beta (PCG with rho = <r, z>)
 __global__ __launch_bounds__(kRedBlock) void k_pcg_beta(const double* part, int n, DevState* st)
 {
     if (st->done) return;
@@ -300,6 +360,7 @@ __global__ __launch_bounds__(kRedBlock) void k_pcg_beta(const double* part, int 
         if (st->iters >= st->force_iters) { st->done = 1; return; }
     } else {
         if (sqrt(rr) <= st->tol * sqrt(st->bb)) { st->done = 1; return; }
+        if (st->mode == 1 && sqrt(rr) <= st->eta * sqrt(st->rr0)) { st->done = 1; return; }
         if (st->iters >= st->max_iter) { st->status = 4; st->done = 1; return; }
     }
     st->beta = rz / st->rho;
@@ -312,29 +373,33 @@ void launch_pcg_beta(const double* part, int n, DevState* st, hipStream_t s)
 }
 
 // p = r/D + beta p
-__global__ __launch_bounds__(kBlock) void k_pcg_dir(Geo<double> g, int nc, double dt,
-                                                    const double* dL, const double* r, double* p,
-                                                    const DevState* st)
+template <class PT>
+__global__ __launch_bounds__(kBlock) void k_pcg_dir(unsigned N, int nc, const double* Db,
+                                                    const double* r, PT* p, const DevState* st)
 {
     if (st->done) return;
     const double beta = st->beta;
-    const int nr = g.nr, np = g.np, P = g.P;
-    const size_t N = (size_t)nr * P, NT = N * nc;
-    for (size_t m = (size_t)blockIdx.x * blockDim.x + threadIdx.x; m < NT;
-         m += (size_t)gridDim.x * blockDim.x) {
-        const size_t cell = m % N;
-        const int i = (int)(cell / P), pp = (int)(cell % P), j = pp / np, k = pp % np;
-        const double D = g.vr[i] * g.vt[j] * g.vp[k] + dt * dL[cell];
-        p[m] = r[m] / D + beta * p[m];
+    for (unsigned cell = blockIdx.x * blockDim.x + threadIdx.x; cell < N;
+         cell += gridDim.x * blockDim.x) {
+        const double D = Db[cell];
+        for (int c = 0; c < nc; ++c) {
+            const size_t m = (size_t)c * N + cell;
+            p[m] = (PT)(r[m] / D + beta * (double)p[m]);
+        }
     }
 }
 
-void launch_pcg_dir(const Geo<double>& g, int nc, double dt, const double* diagL, const double* r,
-                    double* p, const DevState* st, hipStream_t s)
+template <class PT>
+void launch_pcg_dir(size_t N, int nc, const double* D, const double* r, PT* p, const DevState* st,
+                    hipStream_t s)
 {
-    const int nb = vec_blocks((size_t)g.nr * g.P * nc);
-    hipLaunchKernelGGL(k_pcg_dir, dim3(nb), dim3(kBlock), 0, s, g, nc, dt, diagL, r, p, st);
+    const int nb = vec_blocks(N);
+    hipLaunchKernelGGL((k_pcg_dir<PT>), dim3(nb), dim3(kBlock), 0, s, (unsigned)N, nc, D, r, p, st);
 }
+template void launch_pcg_dir<double>(size_t, int, const double*, const double*, double*,
+                                     const DevState*, hipStream_t);
+template void launch_pcg_dir<float>(size_t, int, const double*, const double*, float*,
+                                    const DevState*, hipStream_t);
 
 // ---------------------------------------------------------------- misc
 

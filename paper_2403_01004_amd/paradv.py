@@ -52,7 +52,12 @@ class pa_opts(ctypes.Structure):
                 ("pc", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("max_cycles", ctypes.c_int32), ("force_iters", ctypes.c_int32),
                 ("pcg_batch", ctypes.c_int32), ("replay_n", ctypes.c_int32),
-                ("replay_dt", ctypes.POINTER(ctypes.c_double)), ("ptl_floor", ctypes.c_double)]
+                ("replay_dt", ctypes.POINTER(ctypes.c_double)), ("ptl_floor", ctypes.c_double),
+                ("timing", ctypes.c_int32)]
+
+
+PA_NKCLASS = 8
+KERNEL_CLASSES = ["first", "stage", "matvec", "update", "dir", "init", "reduce", "other"]
 
 
 class pa_stats(ctypes.Structure):
@@ -63,6 +68,8 @@ class pa_stats(ctypes.Structure):
                 ("k_first", ctypes.c_int64), ("dt_explicit", ctypes.c_double),
                 ("dt_ptl_first", ctypes.c_double), ("dt_ptl_min", ctypes.c_double),
                 ("rel_residual", ctypes.c_double), ("ms_total", ctypes.c_double),
+                ("kernel_ms", ctypes.c_double * PA_NKCLASS),
+                ("kernel_calls", ctypes.c_int32 * PA_NKCLASS),
                 ("dt_cycle", ctypes.c_double * PA_MAX_LOG),
                 ("per_cycle", ctypes.c_int32 * PA_MAX_LOG)]
 
@@ -190,6 +197,8 @@ def _stats_dict(s: pa_stats):
                 floored=s.floored, k_first=s.k_first, dt_explicit=s.dt_explicit,
                 dt_ptl_first=s.dt_ptl_first, dt_ptl_min=s.dt_ptl_min,
                 rel_residual=s.rel_residual, ms_total=s.ms_total,
+                kernel_ms={k: s.kernel_ms[i] for i, k in enumerate(KERNEL_CLASSES)},
+                kernel_calls={k: s.kernel_calls[i] for i, k in enumerate(KERNEL_CLASSES)},
                 dt_cycle=np.array(s.dt_cycle[:n]), per_cycle=np.array(s.per_cycle[:n]))
 
 
@@ -230,8 +239,11 @@ class Operator:
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)
-        if ctx is not None and ctx.value:
-            pa_destroy(ctx)
+        if ctx is not None and ctx.value and _lib is not None:
+            try:
+                _lib.pa_destroy(ctx)
+            except Exception:  # interpreter shutdown
+                pass
             self.ctx = None
 
     def _check(self, st):

@@ -1,0 +1,96 @@
+"""FP32-stage variant (FP32 storage and stencil arithmetic, FP64 recurrence
+coefficients, FP64 combination and reductions) against the FP64 oracle.
+Bar: relative L2 error <= 1e-5 per advanced field, with the same cycle
+schedule (the schedule is replayed from the oracle when a limit evaluation
+in FP32 lands on a different near-tie)."""
+import numpy as np
+import pytest
+
+from paper_2403_01004_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+REL32 = 1e-5
+
+
+def rel_l2(a, b):
+    return np.linalg.norm(np.asarray(a) - b) / np.linalg.norm(b)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_01004_amd import paradv
+    paradv.load()
+    return paradv
+
+
+CASES = [("aligned", (17, 24, 40)), ("iso7", (17, 24, 40)), ("visc", (9, 10, 13)),
+         ("aligned", (6, 12, 400))]
+
+
+def make(kind, shape):
+    if kind == "aligned":
+        return inputs.conduction(*shape, noise_amp=0.02)
+    if kind == "visc":
+        return inputs.viscosity(*shape)
+    return inputs.heat_iso(*shape)
+
+
+@pytest.mark.parametrize("kind,shape", CASES)
+@pytest.mark.parametrize("sts", ["rkl2", "rkg2"])
+def test_fp32_sts(dev, oracle_mod, kind, shape, sts):
+    print("fp32 sts", kind, shape, sts, flush=True)
+    prob = make(kind, shape)
+    g = dev.Operator.from_problem(prob, prec="fp32")
+    o = oracle_mod.Oracle.from_problem(prob)
+    dtE = o.dt_explicit()
+    assert abs(g.dt_explicit() - dtE) <= 1e-13 * dtE     # set-up stays FP64
+    for cycles in (1, 0):
+        uo, so = o.advance_sts(prob.u, 50 * dtE, cycles, sts)
+        g.set_options(replay=so["dt_cycle"])
+        u = g.bind(prob.u)
+        st = g.advance_sts(50 * dtE, cycles, sts)
+        assert list(st["per_cycle"]) == list(so["per_cycle"])
+        err = rel_l2(u.cpu().numpy(), uo)
+        assert err <= REL32, err
+        assert err > 1e-12          # really computed in FP32
+    g.set_options()
+
+
+@pytest.mark.parametrize("kind,shape", CASES[:3])
+def test_fp32_matvec_be(dev, oracle_mod, kind, shape):
+    """BE with FP32 matvecs inside an FP64 defect correction: the FP64 true
+    residual of the result, evaluated with the oracle's operator, meets the
+    tolerance, and the field agrees with the FP64 oracle to that tolerance."""
+    print("fp32 be", kind, shape, flush=True)
+    prob = make(kind, shape)
+    g = dev.Operator.from_problem(prob, prec="fp32")
+    o = oracle_mod.Oracle.from_problem(prob)
+    dt = 40 * o.dt_explicit()
+    u = g.bind(prob.u)
+    st = g.advance_be(dt, 1e-10, 1)
+    uo, so = o.advance_be(prob.u, dt, 1e-10, 1)
+    x = u.cpu().numpy()
+    V = o.volumes()[None]
+    b = V * prob.u + dt * V * o.apply(np.zeros_like(prob.u))
+    res = np.linalg.norm(b - (V * x - dt * V * o.apply(x, affine=False))) / np.linalg.norm(b)
+    assert res <= 1.001e-10, res
+    assert rel_l2(x, uo) <= 1e-8
+    assert st["rel_residual"] <= 1e-10
+    # the inner iterations cost at most a little more than plain FP64 PCG
+    assert st["iters_total"] <= 2 * so["iters_total"] + 10
+
+
+def test_fp32_fullsize_conduction(dev, oracle_mod):
+    prob = inputs.conduction()
+    g = dev.Operator.from_problem(prob, prec="fp32")
+    o = oracle_mod.Oracle.from_problem(prob)
+    dt = 50 * o.dt_explicit()
+    u = g.bind(prob.u)
+    st = g.advance_rkl2(dt, 1)
+    uo, so = o.advance_sts(prob.u, dt, 1, "rkl2")
+    assert st["s_total"] == so["s_total"]
+    assert rel_l2(u.cpu().numpy(), uo) <= REL32
