@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Gpts/s per stage & s per PTL-cycled advance; HBM roofline %; PCG iters vs Jacobi"
 HBM_PEAK_GBS = 8000.0
+COPY_ELEMS = 1 << 27          # 1 GiB of FP64 read and 1 GiB written
 WORKLOAD = "spherical shell 151x301x400 (18.2M cells): field-aligned conduction + 3-component viscosity, PTL-cycled RKL2 and BE+Jacobi-PCG at dt = 50 dt_E"
 
 
@@ -85,6 +86,104 @@ def run_cpu_baseline(cond, budget_s=30.0):
                       f"field-aligned conduction advance; {t:.1f} s on the host"}
 
 
+def rel_l2(a, b):
+    import torch
+    return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
+
+def fp32_leg(paradv, torch, dev, cond, visc, reps=3):
+    """FP32 stencil and STS stages (FP64 recurrence coefficients, combination
+    and reductions) and the FP32-matvec BE solve (FP64 defect correction)
+    against the FP64 path on the same inputs: seconds per PTL-cycled advance
+    and relative L2 error per field.  The FP64 path matches the oracle to
+    1e-12, so its result stands in for the oracle's at this size."""
+    out = {}
+    for name, prob, op, nc, T0, scale, expo in (
+            ("conduction", cond, "aligned", 1, cond.T0, 1.0, 2.5),
+            ("viscosity", visc, "iso7", 3, None, 1e-3, 0.0)):
+        res = {}
+        ref = {}
+        for prec in ("fp64", "fp32"):
+            g = paradv.Operator(prob.mesh, op, nc, "dirichlet", "dirichlet", prec)
+            g.set_bc(prob.ub_in, prob.ub_out)
+            g.set_coefficients(None if T0 is None else torch.as_tensor(T0, device=dev), scale,
+                               expo, None if prob.B is None else torch.as_tensor(prob.B, device=dev))
+            dt = 50 * g.dt_explicit()
+            u0 = torch.as_tensor(prob.u, device=dev)
+            u = torch.empty_like(u0)
+            for kind in ("rkl2", "be"):
+                times = []
+                for k in range(reps + 1):
+                    u.copy_(u0)
+                    g.bind(u)
+                    st = g.advance_rkl2(dt, 0) if kind == "rkl2" else g.advance_be(dt, 1e-10, 0)
+                    if k > 0:
+                        times.append(st["ms_total"] / 1e3)
+                key = f"{kind}_{prec}"
+                res[key] = {"s_per_advance": round(min(times), 4), "cycles": st["cycles"],
+                            "stages" if kind == "rkl2" else "pcg_iters":
+                                st["s_total"] if kind == "rkl2" else st["iters_total"]}
+                if prec == "fp64":
+                    ref[kind] = u.clone()
+                else:
+                    res[key]["rel_err_vs_fp64"] = [round(rel_l2(u[c], ref[kind][c]), 9)
+                                                   for c in range(nc)]
+                    res[key]["speedup_vs_fp64"] = round(
+                        res[f"{kind}_fp64"]["s_per_advance"] / res[key]["s_per_advance"], 3)
+            del g
+            torch.cuda.empty_cache()
+        out[name] = res
+    return out
+
+
+def learned_leg(paradv, inputs, torch, dev, nr, nt, np_, reps=2):
+    """BE on the transition-region conduction problem: Jacobi PCG against
+    FCG(1) with the learned preconditioner, trained on the GPU on pairs
+    from the plain solver at the first cycle's step (training time reported
+    separately), same tolerance 1e-10 on the true residual."""
+    tr = inputs.transition_region(nr, nt, np_)
+    g = paradv.Operator.from_problem(tr)
+    u0 = torch.as_tensor(tr.u, device=dev)
+    u = torch.empty_like(u0)
+    dt = 50 * g.dt_explicit()
+
+    def run(pc):
+        g.set_options(pc=paradv.PCS[pc])
+        best = None
+        for k in range(reps + 1):
+            u.copy_(u0)
+            g.bind(u)
+            st = g.advance_be(dt, 1e-10, 0)
+            if k > 0 and (best is None or st["ms_total"] < best["ms_total"]):
+                best = st
+        return best
+
+    sj = run("jacobi")
+    dt1 = float(sj["dt_cycle"][0])
+    u.copy_(u0)
+    g.bind(u)
+    g.lpc_set_weights(paradv.he_init(4300))
+    t0 = time.perf_counter()
+    rep = g.lpc_train(dt1)
+    t_train = time.perf_counter() - t0
+    sl = run("learned")
+    return {
+        "workload": f"transition-region conduction {nr}x{nt}x{np_}, BE PTL-cycled at dt = 50 dt_E, tol 1e-10",
+        "jacobi": {"s_per_advance": round(sj["ms_total"] / 1e3, 4), "pcg_iters": sj["iters_total"],
+                   "cycles": sj["cycles"]},
+        "learned": {"s_per_advance": round(sl["ms_total"] / 1e3, 4), "pcg_iters": sl["iters_total"],
+                    "cycles": sl["cycles"], "fallbacks": sl["fallbacks"],
+                    "rel_residual": sl["rel_residual"]},
+        "iters_ratio": round(sl["iters_total"] / max(sj["iters_total"], 1), 3),
+        "speedup_vs_jacobi": round(sj["ms_total"] / max(sl["ms_total"], 1e-9), 3),
+        "training": {"s": round(t_train, 2), "pairs": rep["pairs"], "steps": rep["steps"],
+                     "snapshots": rep["snapshots"], "ref_iters": rep["ref_iters"],
+                     "loss_first": round(rep["loss_first"], 5),
+                     "loss_last": round(rep["loss_last"], 5),
+                     "ms_pairs": round(rep["ms_pairs"], 1), "ms_train": round(rep["ms_train"], 1)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +191,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--shape", default="151,301,400")
+    ap.add_argument("--legs", default="fp32,learned",
+                    help="extra legs reported beside the timed step: fp32, learned, none")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the advance is built for a single MI355X "
@@ -142,6 +243,23 @@ def main():
         gv.bind(uv)
         t["be_viscosity"] = gv.advance_be(dtv, 1e-10, 0)
         return t
+
+    # plain device copy of known size: the achievable-bandwidth reference,
+    # and the kernel whose FETCH_SIZE / WRITE_SIZE counters calibrate the
+    # HBM traffic of the hot kernels in a --pmc run
+    ca = torch.ones(COPY_ELEMS, dtype=torch.float64, device=dev)
+    cb = torch.empty_like(ca)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    copy_ms = []
+    for k in range(4):
+        e0.record()
+        cb.copy_(ca)
+        e1.record()
+        e1.synchronize()
+        if k:
+            copy_ms.append(e0.elapsed_time(e1))
+    copy_gbs = 2 * 8 * COPY_ELEMS / (min(copy_ms) / 1e3) / 1e9
+    del ca, cb
 
     for w in range(args.warmup):
         log(f"warmup {w}")
@@ -212,7 +330,15 @@ def main():
                      "kernel": f"{dname}/{dcls}", "avg_launch_us": round(1e3 * avg_ms, 2),
                      "bytes_per_launch": int(dbytes / dcalls)},
         "kernels": kernels,
+        "copy_GB_s": round(copy_gbs, 1),
     }
+    legs = [x for x in args.legs.split(",") if x and x != "none"]
+    if "fp32" in legs:
+        log("fp32 leg")
+        out["fp32_stages"] = fp32_leg(paradv, torch, dev, cond, visc)
+    if "learned" in legs:
+        log("learned-preconditioner leg")
+        out["learned_pc"] = learned_leg(paradv, inputs, torch, dev, nr, nt, np_)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = run_cpu_baseline(cond)

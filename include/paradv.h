@@ -98,7 +98,8 @@ typedef struct {
 typedef struct {
     int32_t force_odd;    /* 1: add a stage when s is even (Sec. 3.1, App. A). default 1 */
     int32_t s_override;   /* >0: use exactly this many stages. default 0 */
-    int32_t pc;           /* pa_pc. default PA_PC_JACOBI */
+    int32_t pc;           /* pa_pc. default PA_PC_JACOBI; PA_PC_LEARNED needs weights
+                             (pa_lpc_set_weights), ncomp == 1 and PA_FP64 */
     int32_t max_iter;     /* PCG iteration limit per solve. default 10000 */
     int32_t max_cycles;   /* cycle limit per advance. default 100000 */
     int32_t force_iters;  /* >0: run exactly this many PCG iterations per solve. default 0 */
@@ -119,12 +120,15 @@ enum {
     PA_K_INIT = 5,    /* PCG start (residual, boundary data) */
     PA_K_REDUCE = 6,  /* one-workgroup reductions and scalar updates */
     PA_K_OTHER = 7,   /* conversions and copies */
-    PA_NKCLASS = 8
+    PA_K_NN = 8,      /* learned preconditioner: features, network, FCG vector steps */
+    PA_NKCLASS = 9
 };
 
 /* Per-advance statistics. */
 typedef struct {
-    int32_t cycles, s_total, s_max, iters_total, iters_max, fallbacks, floored, status;
+    int32_t cycles, s_total, s_max, iters_total, iters_max;
+    int32_t fallbacks;        /* learned PC: Jacobi steps taken plus restarts as Jacobi PCG */
+    int32_t floored, status;
     int64_t k_first;          /* linear index of max |F| at the first limit evaluation */
     double dt_explicit;       /* explicit Euler limit used */
     double dt_ptl_first, dt_ptl_min;
@@ -196,6 +200,83 @@ pa_status pa_advance_rkg2(pa_ctx* ctx, double dt, int32_t cycles, pa_stats* stat
  * cycle solves (V + dt_c L) x = V u + dt_c h by point-Jacobi PCG from
  * x0 = u until ||r||_2 <= tol ||b||_2.  Cycling as pa_advance_rkl2. */
 pa_status pa_advance_be_pcg(pa_ctx* ctx, double dt, double tol, int32_t cycles, pa_stats* stats);
+
+/* ------------------------------------------------------------------------
+ * Learned preconditioner for the Backward Euler solve.
+ *
+ * Not part of the paper: it replaces the point-Jacobi step of Sec. 3.1's
+ * PCG (the paper keeps Jacobi because its ILU0 alternative does not
+ * vectorise) with P(r) = r/D + sigma N(c), where D = V + dt diag(L),
+ * sigma = RMS(r/D) over the grid and N is a three-layer 3x3x3 convolutional
+ * network 8 -> 16 (+bias, ReLU) -> 16 (+bias, ReLU) -> 1 on the cell grid
+ * (zero padding in r and theta, periodic in phi).  Input channels per cell
+ * m: c0 = (r/D)/sigma, c1 = V/D, c2..c7 = -dt L(m, nb)/D(m) for the face
+ * neighbours nb = r-, r+, theta-, theta+, phi-, phi+ (0 where none).  The
+ * network runs in BF16 (round to nearest even) with FP32 accumulation, bias
+ * and ReLU, on the matrix cores.  Because P is nonlinear the solve uses
+ * flexible CG truncated to one previous direction (Notay, SIAM J. Sci.
+ * Comput. 22 (2000)): beta = -<z, q_prev>/<p_prev, q_prev>, alpha =
+ * <p, r>/<p, q>.  A step with <z, r> <= 0 takes z = r/D instead; less than
+ * 10% reduction of ||r|| over 20 iterations restarts the solve as Jacobi
+ * PCG from the current iterate.  Stopping rule and tolerance as
+ * pa_advance_be_pcg.  Single-component FP64 contexts only.
+ *
+ * Parameters: flat FP32 vector of PA_LPC_NPARAM values, in this order:
+ * W1[16][8][3][3][3], b1[16], W2[16][16][3][3][3], b2[16], W3[1][16][3][3][3]
+ * (W[co][ci][dr][dtheta][dphi], tap offsets -1, 0, +1).
+ * ---------------------------------------------------------------------- */
+#define PA_LPC_NPARAM 10832
+
+/* Training options (pa_lpc_default_train_opts fills defaults). */
+typedef struct {
+    int32_t npairs;      /* (residual, error) crops generated. default 2000 */
+    int32_t crop_r, crop_t, crop_p; /* crop size in cells (clipped to the grid). default 32 */
+    int32_t batch;       /* crops per Adam step. default 16 */
+    int32_t epochs;      /* passes over the crops. default 30 */
+    int32_t nsnap;       /* plain-PCG iterates sampled per solve. default 16 */
+    int32_t seed;        /* crop positions and batch order. default 4300 */
+    double lr;           /* Adam step (beta1 0.9, beta2 0.999, eps 1e-8). default 1e-3 */
+    double tol_star;     /* tolerance of the reference solve x*. default 1e-12 */
+} pa_lpc_train_opts;
+
+typedef struct {
+    int32_t pairs, snapshots, steps, ref_iters; /* ref_iters: Jacobi-PCG iterations of x* */
+    double loss_first, loss_last;  /* mean loss over the first and last epoch */
+    double ms_pairs, ms_train;     /* wall time: pair generation, optimisation */
+} pa_lpc_report;
+
+void pa_lpc_default_train_opts(pa_lpc_train_opts* opts);
+
+/* Set / read the network parameters (host float[PA_LPC_NPARAM]).  Setting
+ * resets the Adam moments.  PA_ERR_NONFINITE for NaN/Inf values. */
+pa_status pa_lpc_set_weights(pa_ctx* ctx, const float* theta);
+pa_status pa_lpc_get_weights(pa_ctx* ctx, float* theta);
+
+/* The eight input channels for residual r_dev (device double[nr][nt][np])
+ * of the system at step dt, as FP32 values of the BF16 inputs: device
+ * float[8][nr][nt][np]. */
+pa_status pa_lpc_features(pa_ctx* ctx, double dt, const double* r_dev, float* feat_dev);
+
+/* z = P(r) for the system at step dt (device arrays double[nr][nt][np]). */
+pa_status pa_lpc_apply(pa_ctx* ctx, double dt, const double* r_dev, double* z_dev);
+
+/* Training loss over npairs (r, e) pairs on the whole grid (device
+ * double[npairs][nr][nt][np] each), mean over pairs of
+ * |D^1/2 (P(r) - e)|^2 / |D^1/2 e|^2, and its gradient in the parameters
+ * (host double *loss, host float grad[PA_LPC_NPARAM]).  periodic_phi = 0
+ * evaluates the network with zero padding in phi (as on training crops). */
+pa_status pa_lpc_loss_grad(pa_ctx* ctx, double dt, int32_t npairs, const double* r_dev,
+                           const double* e_dev, int32_t periodic_phi, double* loss, float* grad);
+
+/* Train the network on the system (V + dt L) x = V u + dt h of the bound
+ * field: a Jacobi-PCG solve from x0 = u to tol_star gives x*; its iterates
+ * x_k at nsnap iteration counts give pairs (r_k = b - M x_k, e_k = x* - x_k),
+ * from which npairs crops are cut at seeded positions (c0 normalised by the
+ * whole grid's sigma); Adam on the loss above over batches of crops, the
+ * network zero-padded at crop faces.  The bound field is left unchanged.
+ * report may be NULL. */
+pa_status pa_lpc_train(pa_ctx* ctx, double dt, const pa_lpc_train_opts* opts,
+                       pa_lpc_report* report);
 
 #ifdef __cplusplus
 }

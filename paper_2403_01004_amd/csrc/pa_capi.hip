@@ -9,6 +9,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -78,6 +79,24 @@ struct pa_ctx {
     std::vector<hipEvent_t> ev_free;
     std::vector<Pending> ev_pending;
     pa_stats* tstats = nullptr;
+    // learned preconditioner (single-component FP64 contexts)
+    bool nn_ready = false;         // weights loaded
+    bool nn_cpl_ok = false;        // face couplings match the coefficients
+    int nn_adam_t = 0;
+    float *nn_th = nullptr, *nn_m = nullptr, *nn_v = nullptr, *nn_grad = nullptr;
+    NNWeights nn_w{};
+    double* nn_scal = nullptr;     // [0] sigma, [1] loss, [2..2+kMaxPairs) per-pair sigma
+    int* nn_flag = nullptr;        // FCG step takes the Jacobi direction
+    double* nn_cpl = nullptr;      // [6][N] face couplings L(m, nb)
+    __bf16* nn_xs = nullptr;       // [N][8] input channels on the whole grid
+    double* nn_z = nullptr;        // [N] preconditioned residual
+    double* nn_b = nullptr;        // [N] right-hand side of the current solve
+    size_t nn_fcap = 0, nn_bcap = 0;  // points of the forward / backward work buffers
+    __bf16 *nn_a1 = nullptr, *nn_a2 = nullptr;   // [cap][16] activations
+    float* nn_out = nullptr;                     // [cap] network output
+    __bf16 *nn_ga = nullptr, *nn_gb = nullptr;   // [cap][16] activation gradients
+    __bf16* nn_g1 = nullptr;                     // [cap] output gradient
+    float* nn_wpart = nullptr;                   // weight-gradient partials
 };
 
 namespace {
@@ -142,9 +161,9 @@ bool ensure_parts(pa_ctx* c, size_t n)
 // radial levels per workgroup: enough workgroups to fill 256 CUs several
 // times over, without making each chunk so short that the two halo levels
 // dominate
-int pick_rch(int nr, int P)
+int pick_rch(int nr, int nt, int np)
 {
-    const int nbx = (P + kBlock - 1) / kBlock;
+    const int nbx = tiles_per_plane(nt, np);
     int rch = 32;
     while (rch > 4 && (long long)nbx * ((nr + rch - 1) / rch) < 2048) rch /= 2;
     return rch;
@@ -161,7 +180,7 @@ KArgs<T> base_args(pa_ctx* c, int r_lo, int r_hi)
     a.r_lo = r_lo;
     a.r_hi = r_hi;
     a.rch = c->rch;
-    a.nbx = (int)((c->P + kBlock - 1) / kBlock);
+    a.nbx = tiles_per_plane(c->d.nt, c->d.np);
     a.nrc = (r_hi - r_lo + c->rch - 1) / c->rch;
     a.nc = c->d.ncomp;
     a.km2 = kKm2Array;
@@ -197,7 +216,10 @@ void stencil(pa_ctx* c, int mode, bool virt, const KArgs<T>& a)
     }
 }
 
-int ntiles(pa_ctx* c, int nlev) { return stencil_tiles((int)c->P, nlev, c->rch, c->d.ncomp); }
+int ntiles(pa_ctx* c, int nlev)
+{
+    return stencil_tiles(c->d.nt, c->d.np, nlev, c->rch, c->d.ncomp);
+}
 
 hipEvent_t get_event(pa_ctx* c)
 {
@@ -446,7 +468,7 @@ pa_status pa_init(const pa_desc* d, void* stream, pa_ctx** out)
     c->NT = c->N * d->ncomp;
     c->NCO = (size_t)(nr + 1) * (nt + 1) * np;
     c->fp32 = d->prec == PA_FP32_STAGES;
-    c->rch = pick_rch(nr, (int)c->P);
+    c->rch = pick_rch(nr, nt, np);
 
     // 1-D metric factors (finite volume on the face mesh)
     std::vector<double> rc(nr), tc(nt), pc(np);
@@ -525,7 +547,7 @@ pa_status pa_init(const pa_desc* d, void* stream, pa_ctx** out)
             ok = ok && c->f[q];
         }
     }
-    const size_t tiles = (size_t)stencil_tiles((int)c->P, nr, c->rch, d->ncomp);
+    const size_t tiles = (size_t)stencil_tiles(nt, np, nr, c->rch, d->ncomp);
     const size_t nblk = (N + kBlock - 1) / kBlock;
     ok = ok && ensure_parts(c, tiles > nblk ? (tiles > 4096 ? tiles : 4096) : (nblk > 4096 ? nblk : 4096));
     c->st = (DevState*)dev_alloc(c, sizeof(DevState));
@@ -563,7 +585,11 @@ pa_status pa_set_options(pa_ctx* c, const pa_opts* o)
         o->force_iters < 0 || o->pcg_batch < 1 || o->replay_n < 0 || !(o->ptl_floor >= 0.0) ||
         (o->replay_n > 0 && !o->replay_dt) || (o->pc != PA_PC_JACOBI && o->pc != PA_PC_LEARNED))
         return fail(c, PA_ERR_ARG, "invalid option value");
-    if (o->pc == PA_PC_LEARNED) return fail(c, PA_ERR_ARG, "learned preconditioner not loaded");
+    if (o->pc == PA_PC_LEARNED) {
+        if (c->d.ncomp != 1 || c->fp32)
+            return fail(c, PA_ERR_ARG, "learned preconditioner: single-component FP64 contexts only");
+        if (!c->nn_ready) return fail(c, PA_ERR_STATE, "learned preconditioner: no weights set");
+    }
     c->opt = *o;
     c->replay.assign(o->replay_dt, o->replay_dt + (o->replay_n > 0 ? o->replay_n : 0));
     for (double x : c->replay)
@@ -603,6 +629,7 @@ pa_status pa_set_coefficients(pa_ctx* c, const double* T0, double scale, double 
         return fail(c, PA_ERR_ARG, "scale must be finite and >= 0, expo finite");
     if (c->d.op == PA_OP_FIELD_ALIGNED && !B) return fail(c, PA_ERR_ARG, "field-aligned operator needs B");
     c->have_coef = false;
+    c->nn_cpl_ok = false;
     launch_fill_zero(c->flag, sizeof(int), c->stream);
     const int N = (int)c->N;
     launch_coef(T0, scale, expo, N, c->coef64, c->coef32, c->flag, c->stream);
@@ -847,45 +874,53 @@ pa_status pa_advance_rkg2(pa_ctx* c, double dt, int32_t cycles, pa_stats* st)
 
 namespace {
 
-// One PCG solve of M d = r0 from the state queued by launch_pcg_init /
-// launch_pcg_resid + launch_pcg_start: iterations are queued in batches of
-// pcg_batch and the host reads the device state after each batch.  PT is
-// the storage type of the search direction and the matvec (double, or float
-// for the FP32-matvec inner solves); x, r and all scalars are FP64.
+// Queue n PCG iterations (each skipped on the device once the solve is
+// done).  PT is the storage type of the search direction and the matvec
+// (double, or float for the FP32-matvec inner solves); x, r and all scalars
+// are FP64.
 template <class PT>
-pa_status pcg_loop(pa_ctx* c, double dtc, double* r, PT* p, PT* q)
+void pcg_queue(pa_ctx* c, double dtc, double* r, PT* p, PT* q, int n)
 {
     const int nr = c->d.nr, nc = c->d.ncomp;
     const int mt = ntiles(c, nr);
     int nparts = 0;
-    while (true) {
-        for (int b = 0; b < c->opt.pcg_batch; ++b) {
-            KArgs<PT> a = base_args<PT>(c, 0, nr);
-            a.u = p;
-            a.out = q;
-            a.affine = 0;
-            a.dt = dtc;
-            a.done = &c->st->done;
-            {
-                KScope t(c, PA_K_MATVEC);
-                stencil<PT>(c, kMatvec, false, a);
-            }
-            {
-                KScope t(c, PA_K_REDUCE);
-                launch_pcg_alpha(c->part, mt, c->st, c->stream);
-            }
-            {
-                KScope t(c, PA_K_UPDATE);
-                launch_pcg_update<PT>(c->N, nc, c->Dbuf, c->u, r, p, q, c->st, c->part, &nparts,
-                                      c->stream);
-            }
-            {
-                KScope t(c, PA_K_REDUCE);
-                launch_pcg_beta(c->part, nparts, c->st, c->stream);
-            }
-            KScope t(c, PA_K_DIR);
-            launch_pcg_dir<PT>(c->N, nc, c->Dbuf, r, p, c->st, c->stream);
+    for (int b = 0; b < n; ++b) {
+        KArgs<PT> a = base_args<PT>(c, 0, nr);
+        a.u = p;
+        a.out = q;
+        a.affine = 0;
+        a.dt = dtc;
+        a.done = &c->st->done;
+        {
+            KScope t(c, PA_K_MATVEC);
+            stencil<PT>(c, kMatvec, false, a);
         }
+        {
+            KScope t(c, PA_K_REDUCE);
+            launch_pcg_alpha(c->part, mt, c->st, c->stream);
+        }
+        {
+            KScope t(c, PA_K_UPDATE);
+            launch_pcg_update<PT>(c->N, nc, c->Dbuf, c->u, r, p, q, c->st, c->part, &nparts,
+                                  c->stream);
+        }
+        {
+            KScope t(c, PA_K_REDUCE);
+            launch_pcg_beta(c->part, nparts, c->st, c->stream);
+        }
+        KScope t(c, PA_K_DIR);
+        launch_pcg_dir<PT>(c->N, nc, c->Dbuf, r, p, c->st, c->stream);
+    }
+}
+
+// One PCG solve of M d = r0 from the state queued by launch_pcg_init /
+// launch_pcg_resid + launch_pcg_start: iterations are queued in batches of
+// pcg_batch and the host reads the device state after each batch.
+template <class PT>
+pa_status pcg_loop(pa_ctx* c, double dtc, double* r, PT* p, PT* q)
+{
+    while (true) {
+        pcg_queue<PT>(c, dtc, r, p, q, c->opt.pcg_batch);
         pa_status s = sync_state(c);
         if (s) return s;
         if (c->hst->done) return PA_OK;
@@ -911,6 +946,232 @@ void boundary_data(pa_ctx* c, double* q)
     }
 }
 
+
+// ---------------------------------------------------------------- learned PC
+
+constexpr int kMaxPairs = 64;
+
+void dev_free(pa_ctx* c, void* p)
+{
+    if (!p) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (size_t i = 0; i < c->allocs.size(); ++i)
+        if (c->allocs[i] == p) {
+            c->allocs.erase(c->allocs.begin() + (long)i);
+            break;
+        }
+    if (c->d.free) c->d.free(p, c->d.alloc_user);
+    else (void)hipFree(p);
+}
+
+template <class T>
+bool need(pa_ctx* c, T*& p, size_t bytes)
+{
+    if (!p) p = (T*)dev_alloc(c, bytes);
+    return p != nullptr;
+}
+
+// parameters, Adam moments, BF16 operand tables, scalars
+bool nn_alloc_base(pa_ctx* c)
+{
+    const size_t np = sizeof(float) * NN_NPARAM;
+    return need(c, c->nn_th, np) && need(c, c->nn_m, np) && need(c, c->nn_v, np) &&
+           need(c, c->nn_grad, np) && need(c, c->nn_w.f1, 2 * 16 * 224) &&
+           need(c, c->nn_w.f2, 2 * 16 * 448) && need(c, c->nn_w.f3, 2 * 16 * 448) &&
+           need(c, c->nn_w.d2, 2 * 16 * 448) && need(c, c->nn_w.d3, 2 * 16 * 32) &&
+           need(c, c->nn_scal, sizeof(double) * (2 + kMaxPairs)) &&
+           need(c, c->nn_flag, sizeof(int));
+}
+
+// whole-grid buffers: couplings, input channels, z, b
+bool nn_alloc_grid(pa_ctx* c)
+{
+    const size_t N = c->N;
+    return need(c, c->nn_cpl, sizeof(double) * 6 * N) && need(c, c->nn_xs, 2 * 8 * N) &&
+           need(c, c->nn_z, sizeof(double) * N) && need(c, c->nn_b, sizeof(double) * N);
+}
+
+bool nn_fwd_work(pa_ctx* c, size_t pts)
+{
+    if (pts <= c->nn_fcap) return true;
+    dev_free(c, c->nn_a1);
+    dev_free(c, c->nn_a2);
+    dev_free(c, c->nn_out);
+    c->nn_a1 = c->nn_a2 = nullptr;
+    c->nn_out = nullptr;
+    c->nn_fcap = 0;
+    if (!need(c, c->nn_a1, 2 * 16 * pts) || !need(c, c->nn_a2, 2 * 16 * pts) ||
+        !need(c, c->nn_out, sizeof(float) * pts))
+        return false;
+    c->nn_fcap = pts;
+    return true;
+}
+
+bool nn_bwd_work(pa_ctx* c, size_t pts)
+{
+    if (pts <= c->nn_bcap) return true;
+    dev_free(c, c->nn_ga);
+    dev_free(c, c->nn_gb);
+    dev_free(c, c->nn_g1);
+    dev_free(c, c->nn_wpart);
+    c->nn_ga = c->nn_gb = c->nn_g1 = nullptr;
+    c->nn_wpart = nullptr;
+    c->nn_bcap = 0;
+    const size_t wp = (size_t)nn_wgrad_blocks((long)pts) * 16 * 433;
+    if (!need(c, c->nn_ga, 2 * 16 * pts) || !need(c, c->nn_gb, 2 * 16 * pts) ||
+        !need(c, c->nn_g1, 2 * pts) || !need(c, c->nn_wpart, sizeof(float) * wp))
+        return false;
+    c->nn_bcap = pts;
+    return true;
+}
+
+// Static input channels c1..c7 of the system at step dt into nn_xs; also
+// D = V + dt diag(L) into Dbuf when make_D
+void nn_static(pa_ctx* c, double dt, bool make_D)
+{
+    const Geo<double> g = geo(c, c->m64);
+    if (!c->nn_cpl_ok) {
+        launch_couplings(g, c->d.op, c->coef_var ? c->coef64 : nullptr, c->cscale, c->e64,
+                         c->d.bc_in, c->d.bc_out, c->nn_cpl, c->stream);
+        c->nn_cpl_ok = true;
+    }
+    if (make_D) launch_jacobi_D(g, dt, c->diagL, c->Dbuf, c->stream);
+    launch_nn_static(g, dt, c->Dbuf, c->nn_cpl, c->nn_xs, c->stream);
+}
+
+// out = N(x) on nb elements of nr x nt x np cells (activations kept in a1, a2)
+void nn_forward(pa_ctx* c, int nb, int nr, int nt, int np, int per, const int* done,
+                const __bf16* x)
+{
+    launch_nn_conv(1, 0, nb, nr, nt, np, per, done, x, c->nn_w, c->nn_th, nullptr, c->nn_a1,
+                   c->stream);
+    launch_nn_conv(2, 0, nb, nr, nt, np, per, done, c->nn_a1, c->nn_w, c->nn_th, nullptr, c->nn_a2,
+                   c->stream);
+    launch_nn_conv(3, 0, nb, nr, nt, np, per, done, c->nn_a2, c->nn_w, c->nn_th, nullptr, c->nn_out,
+                   c->stream);
+}
+
+// grad += d(sum g1 * out)/dtheta for the last forward pass on input x
+void nn_backward(pa_ctx* c, int nb, int nr, int nt, int np, int per, const __bf16* x)
+{
+    launch_nn_wgrad(3, nb, nr, nt, np, per, c->nn_a2, c->nn_g1, c->nn_wpart, c->nn_grad, c->stream);
+    launch_nn_conv(3, 1, nb, nr, nt, np, per, nullptr, c->nn_g1, c->nn_w, c->nn_th, c->nn_a2,
+                   c->nn_ga, c->stream);
+    launch_nn_wgrad(2, nb, nr, nt, np, per, c->nn_a1, c->nn_ga, c->nn_wpart, c->nn_grad, c->stream);
+    launch_nn_conv(2, 1, nb, nr, nt, np, per, nullptr, c->nn_ga, c->nn_w, c->nn_th, c->nn_a1,
+                   c->nn_gb, c->stream);
+    launch_nn_wgrad(1, nb, nr, nt, np, per, x, c->nn_gb, c->nn_wpart, c->nn_grad, c->stream);
+}
+
+// sigma = RMS(r/D) into nn_scal[0], c0 into nn_xs, network output into nn_out
+void nn_precond(pa_ctx* c, const double* r, const int* done)
+{
+    launch_nn_sigma(c->N, r, c->Dbuf, done, c->part, c->nn_scal, c->stream);
+    launch_nn_c0(c->N, r, c->Dbuf, c->nn_scal, done, c->nn_xs, c->stream);
+    nn_forward(c, 1, c->d.nr, c->d.nt, c->d.np, 1, done, c->nn_xs);
+}
+
+// FCG(1) with the learned preconditioner from the state queued by
+// launch_pcg_init (Dbuf, r0, b in nn_b) and launch_pcg_start; less than 10%
+// reduction of ||r|| over 20 iterations restarts as Jacobi PCG from the
+// current iterate.  *its: iterations; *fallbacks += Jacobi steps + restarts.
+pa_status fcg_solve(pa_ctx* c, double dtc, double tol, double* r, double* p, double* q, int* its,
+                    int* fallbacks)
+{
+    const int nr = c->d.nr;
+    const size_t N = c->N;
+    const int mt = ntiles(c, nr);
+    const int* done = &c->st->done;
+    hipStream_t S = c->stream;
+    int nparts = 0;
+    launch_fill_zero(&c->st->nonfinite, sizeof(int), S);
+    {
+        KScope t(c, PA_K_NN);
+        nn_static(c, dtc, false);
+        nn_precond(c, r, done);
+        const int nb = launch_fcg_combine(N, 1, r, r, c->Dbuf, c->nn_out, c->nn_scal, done, c->nn_z,
+                                          c->part, S);
+        launch_fcg_first(c->part, nb, c->st, c->nn_flag, S);
+        const int nd = launch_fcg_dir(N, 1, c->nn_z, r, c->Dbuf, c->nn_flag, c->st, p, c->part, S);
+        launch_fcg_pr(c->part, nd, c->st, S);
+    }
+    pa_status s = sync_state(c);
+    if (s) return s;
+    const int batch = 10, window = 20;
+    int ref_it = 0;
+    double ref_rr = c->hst->rr;
+    bool restart = false;
+    while (!c->hst->done) {
+        for (int b = 0; b < batch; ++b) {
+            KArgs<double> a = base_args<double>(c, 0, nr);
+            a.u = p;
+            a.out = q;
+            a.affine = 0;
+            a.dt = dtc;
+            a.done = done;
+            {
+                KScope t(c, PA_K_MATVEC);
+                stencil<double>(c, kMatvec, false, a);
+            }
+            {
+                KScope t(c, PA_K_REDUCE);
+                launch_fcg_alpha(c->part, mt, c->st, S);
+            }
+            {
+                KScope t(c, PA_K_UPDATE);
+                launch_pcg_update<double>(N, 1, c->Dbuf, c->u, r, p, q, c->st, c->part, &nparts, S);
+            }
+            {
+                KScope t(c, PA_K_REDUCE);
+                launch_fcg_check(c->part, nparts, c->st, S);
+            }
+            KScope t(c, PA_K_NN);
+            nn_precond(c, r, done);
+            const int nb = launch_fcg_combine(N, 1, r, q, c->Dbuf, c->nn_out, c->nn_scal, done,
+                                              c->nn_z, c->part, S);
+            launch_fcg_beta(c->part, nb, c->st, c->nn_flag, S);
+            const int nd = launch_fcg_dir(N, 1, c->nn_z, r, c->Dbuf, c->nn_flag, c->st, p, c->part, S);
+            launch_fcg_pr(c->part, nd, c->st, S);
+        }
+        s = sync_state(c);
+        if (s) return s;
+        if (c->hst->done) break;
+        if (c->hst->iters - ref_it >= window) {
+            if (sqrt(c->hst->rr) > 0.9 * sqrt(ref_rr)) {
+                restart = true;
+                break;
+            }
+            ref_it = c->hst->iters;
+            ref_rr = c->hst->rr;
+        }
+    }
+    *fallbacks += c->hst->nonfinite;
+    *its = c->hst->iters;
+    if (!restart) return PA_OK;
+    ++*fallbacks;
+    const int used = c->hst->iters;
+    KArgs<double> a = base_args<double>(c, 0, nr);
+    a.u = c->u;
+    a.out = q;
+    a.affine = 0;
+    a.dt = dtc;
+    {
+        KScope t(c, PA_K_INIT);
+        stencil<double>(c, kMatvec, false, a);
+        launch_pcg_resid<double>(N, 1, c->nn_b, q, c->Dbuf, r, p, c->part, &nparts, S);
+    }
+    {
+        KScope t(c, PA_K_REDUCE);
+        const int left = c->opt.max_iter - used;
+        const int fleft = c->opt.force_iters > 0 ? std::max(1, c->opt.force_iters - used) : 0;
+        launch_pcg_start(c->part, nparts, c->st, tol, std::max(1, left), fleft, 0, 0.0, S);
+    }
+    s = pcg_loop<double>(c, dtc, r, p, q);
+    if (s) return s;
+    *its = used + c->hst->iters;
+    return PA_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -922,6 +1183,13 @@ pa_status pa_advance_be_pcg(pa_ctx* c, double dt, double tol, int32_t cycles, pa
     if (s) return s;
     if (cycles < 0) return fail(c, PA_ERR_ARG, "cycles must be >= 0");
     if (!(tol >= 0.0) || !isfinite(tol)) return fail(c, PA_ERR_ARG, "tol must be finite and >= 0");
+    const bool learned = c->opt.pc == PA_PC_LEARNED;
+    if (learned) {
+        if (!c->nn_ready || c->d.ncomp != 1 || c->fp32)
+            return fail(c, PA_ERR_STATE, "learned preconditioner not available on this context");
+        if (!nn_alloc_grid(c) || !nn_fwd_work(c, c->N))
+            return fail(c, PA_ERR_ALLOC, "learned preconditioner: out of device memory");
+    }
     pa_stats local;
     pa_stats* st = user ? user : &local;
     init_stats(st);
@@ -948,7 +1216,23 @@ pa_status pa_advance_be_pcg(pa_ctx* c, double dt, double tol, int32_t cycles, pa
         s = next_cycle(c, dt, cycles, ncyc, t_rem, st, &dtc, &last);
         if (s) break;
         int nparts = 0, its = 0;
-        if (!c->fp32) {
+        if (learned) {
+            {
+                KScope t(c, PA_K_INIT);
+                if (any_dir) boundary_data(c, q);
+                launch_pcg_init<double>(g, nc, dtc, c->u, y0, any_dir ? q : nullptr, c->diagL,
+                                        c->Dbuf, r, p, c->nn_b, c->part, &nparts, c->stream);
+            }
+            {
+                KScope t(c, PA_K_REDUCE);
+                launch_pcg_start(c->part, nparts, c->st, tol, c->opt.max_iter,
+                                 c->opt.force_iters, 0, 0.0, c->stream);
+            }
+            int fb = 0;
+            s = fcg_solve(c, dtc, tol, r, p, q, &its, &fb);
+            if (s) break;
+            st->fallbacks += fb;
+        } else if (!c->fp32) {
             {
                 KScope t(c, PA_K_INIT);
                 if (any_dir) boundary_data(c, q);
@@ -1025,6 +1309,340 @@ pa_status pa_advance_be_pcg(pa_ctx* c, double dt, double tol, int32_t cycles, pa
     st->status = s;
     if (!s) c->err.clear();
     return s;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- learned PC ABI
+
+namespace {
+
+// splitmix64 (Steele, Lea & Flood, OOPSLA 2014): crop positions and batch order
+struct SplitMix {
+    uint64_t x;
+    uint64_t next()
+    {
+        uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    }
+    int below(int n) { return n <= 1 ? 0 : (int)(next() % (uint64_t)n); }
+};
+
+pa_status lpc_ready(pa_ctx* c, double dt, bool weights)
+{
+    if (!c->have_coef) return fail(c, PA_ERR_STATE, "coefficients not set");
+    if (c->d.ncomp != 1 || c->fp32)
+        return fail(c, PA_ERR_ARG, "learned preconditioner: single-component FP64 contexts only");
+    if (weights && !c->nn_ready) return fail(c, PA_ERR_STATE, "learned preconditioner: no weights set");
+    if (!(dt > 0.0) || !isfinite(dt)) return fail(c, PA_ERR_ARG, "dt must be finite and > 0");
+    if (!nn_alloc_base(c) || !nn_alloc_grid(c))
+        return fail(c, PA_ERR_ALLOC, "learned preconditioner: out of device memory");
+    return PA_OK;
+}
+
+// temporary device buffers released on scope exit
+struct Temps {
+    pa_ctx* c;
+    std::vector<void*> v;
+    explicit Temps(pa_ctx* c_) : c(c_) {}
+    template <class T>
+    T* get(size_t n)
+    {
+        T* p = (T*)dev_alloc(c, sizeof(T) * (n ? n : 1));
+        if (p) v.push_back(p);
+        return p;
+    }
+    ~Temps()
+    {
+        for (void* p : v) dev_free(c, p);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+void pa_lpc_default_train_opts(pa_lpc_train_opts* o)
+{
+    if (!o) return;
+    memset(o, 0, sizeof *o);
+    o->npairs = 2000;
+    o->crop_r = o->crop_t = o->crop_p = 32;
+    o->batch = 16;
+    o->epochs = 30;
+    o->nsnap = 16;
+    o->seed = 4300;
+    o->lr = 1e-3;
+    o->tol_star = 1e-12;
+}
+
+pa_status pa_lpc_set_weights(pa_ctx* c, const float* theta)
+{
+    if (!c) return PA_ERR_ARG;
+    if (!theta) return fail(c, PA_ERR_ARG, "null weights");
+    for (int i = 0; i < NN_NPARAM; ++i)
+        if (!isfinite(theta[i])) return fail(c, PA_ERR_NONFINITE, "weight %d is not finite", i);
+    if (!nn_alloc_base(c)) return fail(c, PA_ERR_ALLOC, "learned preconditioner: out of device memory");
+    HIPCHK(c, hipMemcpyAsync(c->nn_th, theta, sizeof(float) * NN_NPARAM, hipMemcpyHostToDevice,
+                             c->stream));
+    launch_fill_zero(c->nn_m, sizeof(float) * NN_NPARAM, c->stream);
+    launch_fill_zero(c->nn_v, sizeof(float) * NN_NPARAM, c->stream);
+    launch_nn_prep_weights(c->nn_th, c->nn_w, c->stream);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->nn_adam_t = 0;
+    c->nn_ready = true;
+    c->err.clear();
+    return PA_OK;
+}
+
+pa_status pa_lpc_get_weights(pa_ctx* c, float* theta)
+{
+    if (!c) return PA_ERR_ARG;
+    if (!theta) return fail(c, PA_ERR_ARG, "null output");
+    if (!c->nn_ready) return fail(c, PA_ERR_STATE, "learned preconditioner: no weights set");
+    HIPCHK(c, hipMemcpyAsync(theta, c->nn_th, sizeof(float) * NN_NPARAM, hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PA_OK;
+}
+
+pa_status pa_lpc_features(pa_ctx* c, double dt, const double* r, float* feat)
+{
+    if (!c) return PA_ERR_ARG;
+    if (!r || !feat) return fail(c, PA_ERR_ARG, "null array");
+    pa_status s = lpc_ready(c, dt, false);
+    if (s) return s;
+    nn_static(c, dt, true);
+    launch_nn_sigma(c->N, r, c->Dbuf, nullptr, c->part, c->nn_scal, c->stream);
+    launch_nn_c0(c->N, r, c->Dbuf, c->nn_scal, nullptr, c->nn_xs, c->stream);
+    launch_nn_unpack(c->N, c->nn_xs, feat, c->stream);
+    HIPCHK(c, hipGetLastError());
+    return PA_OK;
+}
+
+pa_status pa_lpc_apply(pa_ctx* c, double dt, const double* r, double* z)
+{
+    if (!c) return PA_ERR_ARG;
+    if (!r || !z) return fail(c, PA_ERR_ARG, "null array");
+    pa_status s = lpc_ready(c, dt, true);
+    if (s) return s;
+    if (!nn_fwd_work(c, c->N)) return fail(c, PA_ERR_ALLOC, "learned preconditioner: out of device memory");
+    nn_static(c, dt, true);
+    nn_precond(c, r, nullptr);
+    launch_nn_apply(c->N, r, c->Dbuf, c->nn_out, c->nn_scal, z, c->stream);
+    HIPCHK(c, hipGetLastError());
+    return PA_OK;
+}
+
+pa_status pa_lpc_loss_grad(pa_ctx* c, double dt, int32_t npairs, const double* r, const double* e,
+                           int32_t periodic_phi, double* loss, float* grad)
+{
+    if (!c) return PA_ERR_ARG;
+    if (!r || !e || !loss || !grad) return fail(c, PA_ERR_ARG, "null array");
+    if (npairs < 1 || npairs > kMaxPairs) return fail(c, PA_ERR_ARG, "npairs must be in [1, %d]", kMaxPairs);
+    pa_status s = lpc_ready(c, dt, true);
+    if (s) return s;
+    const int nr = c->d.nr, nt = c->d.nt, np = c->d.np;
+    const size_t N = c->N, tot = N * (size_t)npairs;
+    const int per = periodic_phi ? 1 : 0;
+    Temps tmp(c);
+    __bf16* xb = tmp.get<__bf16>(8 * tot);
+    double* zj = tmp.get<double>(tot);
+    double* eb = tmp.get<double>(tot);
+    double* Db = tmp.get<double>(tot);
+    double* sig = tmp.get<double>(npairs);
+    double* den = tmp.get<double>(npairs);
+    int* off = tmp.get<int>(3);
+    if (!xb || !zj || !eb || !Db || !sig || !den || !off || !nn_fwd_work(c, tot) || !nn_bwd_work(c, tot))
+        return fail(c, PA_ERR_ALLOC, "learned preconditioner: out of device memory");
+    launch_fill_zero(off, 3 * sizeof(int), c->stream);
+    nn_static(c, dt, true);
+    for (int b = 0; b < npairs; ++b) {
+        launch_nn_sigma(N, r + b * N, c->Dbuf, nullptr, c->part, c->nn_scal + 2 + b, c->stream);
+        launch_pair_gather(nt, np, nr, nt, np, 1, off, b, 1, c->nn_xs, r + b * N, c->Dbuf, e + b * N,
+                           nullptr, c->nn_scal + 2 + b, xb, zj, eb, Db, sig, c->stream);
+    }
+    launch_batch_scalars(npairs, N, zj, eb, Db, 0, nullptr, den, c->stream);
+    nn_forward(c, npairs, nr, nt, np, per, nullptr, xb);
+    const int nl = launch_nn_lossgrad(tot, N, zj, eb, Db, c->nn_out, sig, den, c->nn_g1, c->part,
+                                      c->stream);
+    launch_loss_finish(c->part, nl, 1.0 / npairs, c->nn_scal + 1, c->stream);
+    launch_fill_zero(c->nn_grad, sizeof(float) * NN_NPARAM, c->stream);
+    nn_backward(c, npairs, nr, nt, np, per, xb);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(grad, c->nn_grad, sizeof(float) * NN_NPARAM, hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipMemcpyAsync(loss, c->nn_scal + 1, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->err.clear();
+    return PA_OK;
+}
+
+pa_status pa_lpc_train(pa_ctx* c, double dt, const pa_lpc_train_opts* oin, pa_lpc_report* rep)
+{
+    if (!c) return PA_ERR_ARG;
+    pa_lpc_train_opts o;
+    if (oin) o = *oin;
+    else pa_lpc_default_train_opts(&o);
+    if (!c->u) return fail(c, PA_ERR_STATE, "no field bound");
+    pa_status s = lpc_ready(c, dt, true);
+    if (s) return s;
+    if (o.npairs < 1 || o.batch < 1 || o.batch > o.npairs || o.epochs < 1 || o.nsnap < 1 ||
+        o.crop_r < 1 || o.crop_t < 1 || o.crop_p < 1 || !(o.lr > 0.0) || !isfinite(o.lr) ||
+        !(o.tol_star >= 0.0) || !isfinite(o.tol_star))
+        return fail(c, PA_ERR_ARG, "invalid training option");
+    const int nr = c->d.nr, nt = c->d.nt, np = c->d.np;
+    const int cr = std::min(o.crop_r, nr), ct = std::min(o.crop_t, nt), cp = std::min(o.crop_p, np);
+    const int per = cp == np ? 1 : 0;
+    const size_t N = c->N, Nc = (size_t)cr * ct * cp, ncrop = (size_t)o.npairs;
+    const size_t bpts = Nc * (size_t)o.batch;
+    hipStream_t S = c->stream;
+    pa_lpc_report R;
+    memset(&R, 0, sizeof R);
+    std::vector<float> th0(NN_NPARAM);
+    HIPCHK(c, hipMemcpy(th0.data(), c->nn_th, sizeof(float) * NN_NPARAM, hipMemcpyDeviceToHost));
+
+    Temps tmp(c);
+    double* bak = tmp.get<double>(N);
+    double* xst = tmp.get<double>(N);
+    double* snap = tmp.get<double>(N * (size_t)o.nsnap);
+    if (!bak || !xst || !snap || !nn_fwd_work(c, bpts) || !nn_bwd_work(c, bpts))
+        return fail(c, PA_ERR_ALLOC, "training: out of device memory");
+    double* y0 = c->w[0];
+    double* r = c->w[1];
+    double* p = c->w[2];
+    double* q = c->w[3];
+    const Geo<double> g = geo(c, c->m64);
+    const bool any_dir = c->d.bc_in == PA_BC_DIRICHLET || c->d.bc_out == PA_BC_DIRICHLET;
+
+    // reference solve x* by Jacobi PCG from x0 = u, keeping iterates x_k
+    Timer t_pairs(S);
+    launch_copy(c->u, bak, sizeof(double) * N, S);
+    launch_fill_zero(c->flag, sizeof(int), S);
+    first_pass<double>(c, c->u, y0);
+    int nparts = 0;
+    if (any_dir) boundary_data(c, q);
+    launch_pcg_init<double>(g, 1, dt, c->u, y0, any_dir ? q : nullptr, c->diagL, c->Dbuf, r, p,
+                            c->nn_b, c->part, &nparts, S);
+    launch_pcg_start(c->part, nparts, c->st, o.tol_star, c->opt.max_iter, 0, 0, 0.0, S);
+    s = sync_state(c);
+    int taken = 0;
+    for (int j = 0, k = 0; !s && j < o.nsnap; ++j) {
+        if (c->hst->done) break;
+        const int todo = k - c->hst->iters;
+        if (todo > 0) {
+            pcg_queue<double>(c, dt, r, p, q, todo);
+            s = sync_state(c);
+            if (s || c->hst->done) break;
+        }
+        launch_copy(c->u, snap + (size_t)taken * N, sizeof(double) * N, S);
+        ++taken;
+        k = std::max(k + 1, k * 3 / 2);
+    }
+    if (!s) s = pcg_loop<double>(c, dt, r, p, q);
+    const int pst = c->hst->status;
+    R.ref_iters = c->hst->iters;
+    launch_copy(c->u, xst, sizeof(double) * N, S);
+    launch_copy(bak, c->u, sizeof(double) * N, S);
+    if (s) return s;
+    if (pst == 4) return fail(c, PA_ERR_NOCONV, "training: reference solve did not reach tol_star");
+    if (pst == 5) return fail(c, PA_ERR_BREAKDOWN, "training: reference solve broke down");
+    if (pst == 6) return fail(c, PA_ERR_NONFINITE, "training: non-finite residual");
+    if (taken == 0) return fail(c, PA_ERR_ARG, "training: the bound field already solves the system");
+
+    // crops: crop n belongs to snapshot n % taken; offsets grouped by snapshot
+    SplitMix rng{(uint64_t)(uint32_t)o.seed};
+    std::vector<int> offs(3 * ncrop);
+    std::vector<size_t> start(taken + 1, 0);
+    for (int j = 0; j < taken; ++j)
+        start[j + 1] = start[j] + (ncrop > (size_t)j ? (ncrop - j + taken - 1) / taken : 0);
+    for (size_t n = 0; n < ncrop; ++n) {
+        const int j = (int)(n % taken);
+        const size_t slot = start[j] + n / taken;
+        offs[3 * slot] = rng.below(nr - cr + 1);
+        offs[3 * slot + 1] = rng.below(nt - ct + 1);
+        offs[3 * slot + 2] = per ? 0 : rng.below(np);
+    }
+    __bf16* xc = tmp.get<__bf16>(8 * Nc * ncrop);
+    double* zjc = tmp.get<double>(Nc * ncrop);
+    double* ec = tmp.get<double>(Nc * ncrop);
+    double* Dc = tmp.get<double>(Nc * ncrop);
+    double* sigc = tmp.get<double>(ncrop);
+    double* denc = tmp.get<double>(ncrop);
+    int* doff = tmp.get<int>(3 * ncrop);
+    if (!xc || !zjc || !ec || !Dc || !sigc || !denc || !doff)
+        return fail(c, PA_ERR_ALLOC, "training: out of device memory for the crops");
+    HIPCHK(c, hipMemcpy(doff, offs.data(), sizeof(int) * 3 * ncrop, hipMemcpyHostToDevice));
+    nn_static(c, dt, false);
+    for (int j = 0; j < taken; ++j) {
+        const int nj = (int)(start[j + 1] - start[j]);
+        if (nj == 0) continue;
+        const double* xk = snap + (size_t)j * N;
+        KArgs<double> a = base_args<double>(c, 0, nr);
+        a.u = xk;
+        a.out = q;
+        a.affine = 0;
+        a.dt = dt;
+        stencil<double>(c, kMatvec, false, a);
+        launch_pcg_resid<double>(N, 1, c->nn_b, q, c->Dbuf, r, p, c->part, &nparts, S);
+        launch_nn_sigma(N, r, c->Dbuf, nullptr, c->part, c->nn_scal, S);
+        launch_pair_gather(nt, np, cr, ct, cp, nj, doff + 3 * start[j], j, taken, c->nn_xs, r,
+                           c->Dbuf, xst, xk, c->nn_scal, xc, zjc, ec, Dc, sigc, S);
+    }
+    launch_batch_scalars((int)ncrop, Nc, zjc, ec, Dc, 0, nullptr, denc, S);
+    HIPCHK(c, hipGetLastError());
+    R.ms_pairs = t_pairs.stop();
+    R.pairs = (int)ncrop;
+    R.snapshots = taken;
+
+    // Adam over batches of crops
+    Timer t_train(S);
+    const int nbatch = (int)(ncrop / o.batch);
+    const int steps = nbatch * o.epochs;
+    double* lossv = tmp.get<double>(steps);
+    if (!lossv) return fail(c, PA_ERR_ALLOC, "training: out of device memory");
+    std::vector<int> perm(nbatch);
+    for (int i = 0; i < nbatch; ++i) perm[i] = i;
+    int step = 0;
+    for (int ep = 0; ep < o.epochs; ++ep) {
+        for (int i = nbatch - 1; i > 0; --i) std::swap(perm[i], perm[rng.below(i + 1)]);
+        for (int bi = 0; bi < nbatch; ++bi) {
+            const size_t el = (size_t)perm[bi] * o.batch;
+            const __bf16* x = xc + el * Nc * 8;
+            launch_fill_zero(c->nn_grad, sizeof(float) * NN_NPARAM, S);
+            nn_forward(c, o.batch, cr, ct, cp, per, nullptr, x);
+            const int nl = launch_nn_lossgrad(bpts, Nc, zjc + el * Nc, ec + el * Nc, Dc + el * Nc,
+                                              c->nn_out, sigc + el, denc + el, c->nn_g1, c->part, S);
+            launch_loss_finish(c->part, nl, 1.0 / o.batch, lossv + step, S);
+            nn_backward(c, o.batch, cr, ct, cp, per, x);
+            launch_nn_adam(c->nn_th, c->nn_grad, c->nn_m, c->nn_v, (float)o.lr, ++c->nn_adam_t, S);
+            launch_nn_prep_weights(c->nn_th, c->nn_w, S);
+            ++step;
+        }
+        HIPCHK(c, hipGetLastError());
+    }
+    std::vector<double> lh(steps);
+    HIPCHK(c, hipMemcpyAsync(lh.data(), lossv, sizeof(double) * steps, hipMemcpyDeviceToHost, S));
+    R.ms_train = t_train.stop();
+    R.steps = steps;
+    for (int i = 0; i < nbatch; ++i) {
+        R.loss_first += lh[i] / nbatch;
+        R.loss_last += lh[steps - nbatch + i] / nbatch;
+    }
+    std::vector<float> th(NN_NPARAM);
+    HIPCHK(c, hipMemcpy(th.data(), c->nn_th, sizeof(float) * NN_NPARAM, hipMemcpyDeviceToHost));
+    bool finite = true;
+    for (float v : th) finite = finite && isfinite(v);
+    if (rep) *rep = R;
+    if (!finite) {
+        (void)pa_lpc_set_weights(c, th0.data());
+        return fail(c, PA_ERR_NONFINITE, "training diverged; previous weights restored");
+    }
+    c->err.clear();
+    return PA_OK;
 }
 
 }  // extern "C"

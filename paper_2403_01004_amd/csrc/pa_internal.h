@@ -69,8 +69,10 @@ void launch_iso7(int mode, bool virt, const Geo<T>& g, const KArgs<T>& a, hipStr
 template <class T>
 void launch_aligned(int mode, bool virt, const Geo<T>& g, const KArgs<T>& a, hipStream_t s);
 
-// number of logical tiles of a stencil launch (== entries of a.part)
-int stencil_tiles(int P, int nr_levels, int rch, int nc);
+// tiles of one radial level, and logical tiles of a stencil launch over
+// nlev levels (== entries of a.part)
+int tiles_per_plane(int nt, int np);
+int stencil_tiles(int nt, int np, int nlev, int rch, int nc);
 
 // setup kernels
 void launch_coef(const double* T0, double scale, double expo, int n, double* c64, float* c32,
@@ -121,6 +123,66 @@ void launch_pcg_beta(const double* part, int n, DevState* st, hipStream_t s);
 template <class PT>
 void launch_pcg_dir(size_t N, int nc, const double* D, const double* r, PT* p, const DevState* st,
                     hipStream_t s);
+// face couplings L_{m,nb} for nb = r-, r+, t-, t+, p-, p+ into out[6][N]
+// (zero where the neighbour does not exist) (pa_setup.hip)
+void launch_couplings(const Geo<double>& g, int op, const double* coef, double cs, const double* e,
+                      int bc_in, int bc_out, double* out, hipStream_t s);
+
+// learned preconditioner network (pa_nn.hip).  Flat FP32 parameter vector:
+// W1[16][8][27], b1[16], W2[16][16][27], b2[16], W3[1][16][27]
+constexpr int NN_OFF_W1 = 0, NN_OFF_B1 = 3456, NN_OFF_W2 = 3472, NN_OFF_B2 = 10384,
+              NN_OFF_W3 = 10400, NN_NPARAM = 10832;
+struct NNWeights {
+    __bf16 *f1, *f2, *f3, *d3, *d2;  // BF16 MFMA operand tables
+};
+void launch_nn_prep_weights(const float* theta, NNWeights& w, hipStream_t s);
+// Network launches run on nb elements of nr x nt x np cells stacked along r
+// (zero padding in r and theta per element; phi periodic when per != 0).
+// dir 0: forward of `layer` (1: 8->16, 2: 16->16, 3: 16->1 FP32 out);
+// dir 1: input gradient of `layer` (3 or 2), masked by mask[p][16] > 0.
+// Skipped when *done != 0 (done may be null).
+void launch_nn_conv(int layer, int dir, int nb, int nr, int nt, int np, int per, const int* done,
+                    const __bf16* x, const NNWeights& w, const float* theta, const __bf16* mask,
+                    void* out, hipStream_t s);
+// grad[layer's weights and bias] += sum_p G[p][co] X[p + tap][ci];
+// part holds nn_wgrad_blocks(points) * 16 * 433 floats
+int nn_wgrad_blocks(long npoints);
+void launch_nn_wgrad(int layer, int nb, int nr, int nt, int np, int per, const __bf16* X,
+                     const __bf16* G, float* part, float* grad, hipStream_t s);
+void launch_nn_static(const Geo<double>& g, double dt, const double* D, const double* cpl,
+                      __bf16* x, hipStream_t s);
+void launch_nn_c0(size_t N, const double* r, const double* D, const double* sigma, const int* done,
+                  __bf16* x, hipStream_t s);
+int launch_nn_lossgrad(size_t N, size_t nc, const double* zj, const double* e, const double* D,
+                       const float* out, const double* sigma, const double* den, __bf16* gout,
+                       double* part, hipStream_t s);
+void launch_batch_scalars(int nb, size_t nc, const double* zj, const double* e, const double* D,
+                          int want_sig, double* sig, double* den, hipStream_t s);
+void launch_pair_gather(int nt, int np, int cr, int ct, int cp, int ncrop, const int* off, int b0,
+                        int bs, const __bf16* xs, const double* r, const double* D,
+                        const double* xstar, const double* xk, const double* sig, __bf16* x,
+                        double* zj, double* e, double* Dw, double* sigo, hipStream_t s);
+void launch_loss_finish(const double* part, int n, double scale, double* out, hipStream_t s);
+void launch_jacobi_D(const Geo<double>& g, double dt, const double* dL, double* D, hipStream_t s);
+void launch_nn_unpack(size_t N, const __bf16* x, float* f, hipStream_t s);
+void launch_nn_apply(size_t N, const double* r, const double* D, const float* out,
+                     const double* sigma, double* z, hipStream_t s);
+void launch_nn_adam(float* th, const float* grad, float* m, float* v, float lr, int t, hipStream_t s);
+int launch_fcg_combine(size_t N, int nc, const double* r, const double* q, const double* D,
+                       const float* out, const double* sigma, const int* done, double* z,
+                       double* part, hipStream_t s);
+void launch_nn_sigma(size_t N, const double* r, const double* D, const int* done, double* part,
+                     double* sigma, hipStream_t s);
+void launch_sum_finish(const double* part, int n, double* out, hipStream_t s);
+void launch_fcg_first(const double* part, int n, DevState* st, int* use_jacobi, hipStream_t s);
+void launch_fcg_alpha(const double* part, int n, DevState* st, hipStream_t s);
+void launch_fcg_check(const double* part, int n, DevState* st, hipStream_t s);
+void launch_fcg_beta(const double* part, int n, DevState* st, int* use_jacobi, hipStream_t s);
+int launch_fcg_dir(size_t N, int nc, const double* z, const double* r, const double* D,
+                   const int* use_jacobi, const DevState* st, double* p, double* part,
+                   hipStream_t s);
+void launch_fcg_pr(const double* part, int n, DevState* st, hipStream_t s);
+
 void launch_f64_to_f32(const double* a, float* b, size_t n, hipStream_t s);
 void launch_f32_to_f64(const float* a, double* b, size_t n, hipStream_t s);
 void launch_copy(const void* a, void* b, size_t bytes, hipStream_t s);

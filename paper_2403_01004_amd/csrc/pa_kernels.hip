@@ -6,28 +6,36 @@
 //                 + mu~ dt F(u_{k-1}) + gamma~ dt y0     (STS stage, App. A)
 //   kMatvec q = V p + dt L p, per-tile <p, q>          (BE system matvec)
 //
-// Work decomposition: one thread per (theta, phi) cell of a radial level,
-// 256 consecutive plane cells per workgroup (phi fastest, so loads are
-// coalesced along phi and the ragged tail of a plane is a partial last
-// block), each workgroup marching over a chunk of radial levels.  Radial
-// neighbours live in registers (each level is loaded once per chunk); the
-// in-plane neighbours come through L1/L2 (the rows j-1 and j+1 are loaded by
-// neighbouring waves of the same or the adjacent workgroup).  The logical
-// tile order is remapped so that each of the 8 XCDs gets a contiguous range
-// of tiles (workgroups are dispatched round-robin over XCDs), keeping a
-// tile's theta-neighbour rows in the same XCD's L2.
+// Work decomposition.  A workgroup of 256 threads owns a 32 (phi) x 8
+// (theta) tile of cells and marches over a chunk of radial levels.  Each
+// thread owns one tile cell and (threads 0..83) one cell of the one-cell
+// halo ring; per level it loads just those values -- plus, for the
+// field-aligned operator, the three coefficients of at most two corners, and
+// for a stage the pointwise streams u_{k-2}, u0, y0 -- and it issues them two
+// levels ahead of their use, so every wave keeps several levels of
+// independent HBM loads in flight at the cost of a few registers.  The
+// tile's planes are staged in LDS, where the in-plane neighbours are read.
+// The logical tile order puts phi tiles fastest and gives each of the 8 XCDs
+// a contiguous range (workgroups are dispatched round-robin over XCDs), so
+// the halo rows shared by neighbouring tiles are found in that XCD's L2.
 //
-// Field-aligned operator: L = sum_c v_c v_c^T over cell corners c, v_c the
+// Field-aligned operator: L = sum_c v_c v_c^T over cell corners, v_c the
 // corner's (ghost-folded) scatter weights; with per-corner coefficients
-// e = sqrt(W kappa) bhat / h (three per corner, computed once per
-// coefficient update), a corner's flux is t = e . D where D holds the four
-// averaged differences per direction, and a cell gathers sum_c w_c t_c over
-// its eight corners.  The march computes each corner plane once per thread
-// (the four corners around the thread's cell) and carries the upper-cell
-// part of the scatter to the next level, so no corner flux goes to memory.
+// e = sqrt(W kappa) bhat / h (three per corner), a corner's flux is
+// t = e . D, D the averaged differences over its 2x2x2 cells, and a cell
+// gathers sum_c w_c t_c over its eight corners.  Each corner of a plane is
+// computed once per tile (9 x 33 corners for 256 cells) into LDS; the upper
+// cell's share of a corner plane is carried in a register to the next level.
 #include "pa_internal.h"
 
 namespace pa {
+
+constexpr int TX = 32, TY = 8;          // tile (phi x theta)
+constexpr int HX = TX + 2, HY = TY + 2;  // tile plus halo ring
+constexpr int HN = HX * HY;              // 340 plane slots
+constexpr int NHALO = HN - TX * TY;      // 84 halo slots
+constexpr int CX = TX + 1, CY = TY + 1;  // corners of a tile plane
+constexpr int NCOR = CX * CY;            // 297
 
 __device__ __forceinline__ int xcd_tile()
 {
@@ -37,11 +45,12 @@ __device__ __forceinline__ int xcd_tile()
 
 static inline int grid_for_tiles(int ntiles) { return ((ntiles + 7) / 8) * 8; }
 
-int stencil_tiles(int P, int nlev, int rch, int nc)
+int tiles_per_plane(int nt, int np) { return ((np + TX - 1) / TX) * ((nt + TY - 1) / TY); }
+
+int stencil_tiles(int nt, int np, int nlev, int rch, int nc)
 {
-    const int nbx = (P + kBlock - 1) / kBlock;
     const int nrc = (nlev + rch - 1) / rch;
-    return nbx * nrc * nc;
+    return tiles_per_plane(nt, np) * nrc * nc;
 }
 
 // ------------------------------------------------------------ reductions
@@ -90,6 +99,59 @@ __device__ void block_argmax(double& v, long long& idx, double* ldsv, long long*
             if (better(ldsv[i], ldsi[i], v, idx)) { v = ldsv[i]; idx = ldsi[i]; }
 }
 
+// ------------------------------------------------------------ tile geometry
+
+// Where a thread's two plane slots live: its own cell (slot (ty+1, tx+1))
+// and, for threads below NHALO, one halo slot.  Global rows are clamped at
+// the poles (those neighbours carry zero coupling) and columns wrap.
+struct TileMap {
+    int k0, j0;     // tile origin
+    int tx, ty;     // thread's cell in the tile
+    int j, k;       // thread's global cell (may lie outside the mesh)
+    bool valid;     // the thread's cell exists
+    int own_off;    // in-plane offset of the own cell (clamped / wrapped)
+    int own_slot;   // LDS slot of the own cell
+    bool has_h;     // the thread owns a halo slot
+    int h_off, h_slot;
+};
+
+__device__ __forceinline__ int wrapk(int k, int np)
+{
+    k %= np;
+    return k < 0 ? k + np : k;
+}
+
+__device__ __forceinline__ int slot_offset(int hy, int hx, int j0, int k0, int nt, int np)
+{
+    const int j = min(max(j0 - 1 + hy, 0), nt - 1);
+    return j * np + wrapk(k0 - 1 + hx, np);
+}
+
+__device__ __forceinline__ TileMap tile_map(int bxk, int bxj, int nt, int np)
+{
+    TileMap m;
+    const int t = threadIdx.x;
+    m.k0 = bxk * TX;
+    m.j0 = bxj * TY;
+    m.tx = t % TX;
+    m.ty = t / TX;
+    m.j = m.j0 + m.ty;
+    m.k = m.k0 + m.tx;
+    m.valid = m.j < nt && m.k < np;
+    m.own_slot = (m.ty + 1) * HX + (m.tx + 1);
+    m.own_off = slot_offset(m.ty + 1, m.tx + 1, m.j0, m.k0, nt, np);
+    m.has_h = t < NHALO;
+    int hy, hx;
+    if (t < HX) { hy = 0; hx = t; }
+    else if (t < 2 * HX) { hy = HY - 1; hx = t - HX; }
+    else if (t < 2 * HX + TY) { hy = 1 + (t - 2 * HX); hx = 0; }
+    else { hy = 1 + (t - 2 * HX - TY); hx = HX - 1; }
+    if (!m.has_h) { hy = 1; hx = 1; }
+    m.h_slot = hy * HX + hx;
+    m.h_off = slot_offset(hy, hx, m.j0, m.k0, nt, np);
+    return m;
+}
+
 // ------------------------------------------------------------ epilogue
 
 template <class T, int MODE>
@@ -100,7 +162,7 @@ struct Acc {
     int bad = 0;
 };
 
-// pointwise streams an STS stage combines with F (prefetched one level ahead)
+// pointwise streams an STS stage combines with F
 template <class T>
 struct Streams {
     T u0 = 0, y0 = 0, km2 = 0;
@@ -162,6 +224,7 @@ __device__ void finish(const KArgs<T>& a, int L, Acc<T, MODE>& acc)
     }
 }
 
+// stencil input value: u, or the virtual first stage u0 + a1 y0
 template <class T, bool VIRT>
 __device__ __forceinline__ T ldu(const KArgs<T>& a, const T* u, const T* y, size_t q)
 {
@@ -170,89 +233,96 @@ __device__ __forceinline__ T ldu(const KArgs<T>& a, const T* u, const T* y, size
 }
 
 // ------------------------------------------------------------ 7-point
-//
-// Registers per thread: the centre column at levels i-1, i, i+1 and the
-// four in-plane neighbours at level i; the loads for level i+1 (centre i+2,
-// neighbours, coefficients, stage streams) are issued before level i is
-// computed, so every wave keeps two levels of loads in flight.
 
+// one radial level's loads of a thread (own cell, halo slot, coefficients,
+// stage streams of the own cell)
 template <class T>
-struct Ring7 {
-    T up, w, e, s, n, cp, cw, ce, cs, cn;
+struct Lev7 {
+    T u, h, c, ch;
+    Streams<T> s;
 };
+
+template <class T, int MODE, bool VIRT>
+__device__ __forceinline__ void fetch7(const KArgs<T>& a, const T* u, const T* y, const T* cf,
+                                       const TileMap& tm, size_t cb, int P, int lv, bool plane,
+                                       Lev7<T>& R)
+{
+    const size_t lb = (size_t)lv * P;
+    R.u = ldu<T, VIRT>(a, u, y, lb + tm.own_off);
+    if (cf) R.c = cf[lb + tm.own_off];
+    if (plane) {
+        if (tm.has_h) {
+            R.h = ldu<T, VIRT>(a, u, y, lb + tm.h_off);
+            if (cf) R.ch = cf[lb + tm.h_off];
+        }
+        load_streams<T, MODE>(a, cb + lb + tm.own_off, R.s);
+    }
+}
 
 template <class T, int MODE, bool VIRT>
 __global__ __launch_bounds__(kBlock) void k_iso7(Geo<T> g, KArgs<T> a)
 {
+    __shared__ T su[2][HN];
+    __shared__ T sc[2][HN];
     const int L = xcd_tile();
     if (L >= a.nbx * a.nrc * a.nc) return;
     if (a.done && *a.done) return;
-    const int bx = L % a.nbx, rest = L / a.nbx, rc = rest % a.nrc, c = rest / a.nrc;
     const int np = g.np, nt = g.nt, nr = g.nr, P = g.P;
-    const int p = bx * kBlock + threadIdx.x;
-    const bool valid = p < P;
-    const int pp = valid ? p : P - 1;
-    const int j = pp / np, k = pp - j * np;
-    const int km = (k == 0) ? np - 1 : k - 1, kp = (k == np - 1) ? 0 : k + 1;
-    const bool hs = j > 0, hn = j < nt - 1;
+    const int ntk = (np + TX - 1) / TX;
+    const int bx = L % a.nbx, rest = L / a.nbx, rc = rest % a.nrc, c = rest / a.nrc;
+    const TileMap tm = tile_map(bx % ntk, bx / ntk, nt, np);
     const size_t cb = (size_t)c * nr * P;
     const T* u = a.u + cb;
     const T* y = VIRT ? a.y0 + cb : nullptr;
-    const bool varc = a.coef != nullptr;
-    const T* cf = a.coef;
+    const T* cf = a.coef;  // null: constant coefficient a.cs
     const int i0 = a.r_lo + rc * a.rch;
     const int i1 = min(a.r_hi, i0 + a.rch);
+    const int j = min(tm.j, nt - 1), k = tm.valid ? tm.k : 0;
+    const int kp = (k == np - 1) ? 0 : k + 1;
     const T vtj = g.vt[j], vpk = g.vp[k];
     const T gts = g.gtt[j], gtn = g.gtt[j + 1], gpj = g.gpt[j], gpw = g.gpp[k], gpe = g.gpp[kp];
-    const size_t ob = (size_t)c * P + pp;  // boundary data offset
-    const int rowo = j * np;
+    const size_t ob = (size_t)c * P + tm.own_off;  // boundary data of the own cell
+    const int so = tm.own_slot;
     Acc<T, MODE> acc;
 
-    // loads of level lv+1's centre and level lv's in-plane data.  Every load
-    // is unconditional at an in-bounds address: across a pole the row is
-    // clamped to the cell's own row (the colatitude coupling there is exactly
-    // zero), above the outer level the centre is clamped to the last level
-    // (the boundary closure replaces it).
-    const int rs = hs ? rowo - np : rowo, rn = hn ? rowo + np : rowo;
-    auto fetch = [&](int lv, Ring7<T>& R) {
-        const size_t lvb = (size_t)lv * P;
-        const size_t lup = (lv + 1 < nr) ? lvb + P : lvb;
-        R.up = ldu<T, VIRT>(a, u, y, lup + pp);
-        R.w = ldu<T, VIRT>(a, u, y, lvb + rowo + km);
-        R.e = ldu<T, VIRT>(a, u, y, lvb + rowo + kp);
-        R.s = ldu<T, VIRT>(a, u, y, lvb + rs + k);
-        R.n = ldu<T, VIRT>(a, u, y, lvb + rn + k);
-        if (varc) {
-            R.cp = cf[lup + pp];
-            R.cw = cf[lvb + rowo + km];
-            R.ce = cf[lvb + rowo + kp];
-            R.cs = cf[lvb + rs + k];
-            R.cn = cf[lvb + rn + k];
-        } else {
-            R.cp = R.cw = R.ce = R.cs = R.cn = a.cs;
-        }
-    };
-
-    T um = 0, uc = 0, cm = a.cs, cc = a.cs;
-    Ring7<T> cur = {};
-    Streams<T> scur;
+    // ring R[q] = loads of level i + q; level i + DEPTH is issued while
+    // level i is computed (DEPTH levels of loads in flight per thread)
+    constexpr int DEPTH = 2;
+    Lev7<T> R[DEPTH + 1] = {};
+    T um = 0, cm = a.cs;
     if (i0 < i1) {
-        uc = ldu<T, VIRT>(a, u, y, (size_t)i0 * P + pp);
-        if (varc) cc = cf[(size_t)i0 * P + pp];
         if (i0 > 0) {
-            um = ldu<T, VIRT>(a, u, y, (size_t)(i0 - 1) * P + pp);
-            if (varc) cm = cf[(size_t)(i0 - 1) * P + pp];
+            um = ldu<T, VIRT>(a, u, y, (size_t)(i0 - 1) * P + tm.own_off);
+            if (cf) cm = cf[(size_t)(i0 - 1) * P + tm.own_off];
         }
-        fetch(i0, cur);
-        load_streams<T, MODE>(a, cb + (size_t)i0 * P + pp, scur);
+#pragma unroll
+        for (int q = 0; q < DEPTH; ++q)
+            if (i0 + q < nr && i0 + q <= i1)
+                fetch7<T, MODE, VIRT>(a, u, y, cf, tm, cb, P, i0 + q, i0 + q < i1, R[q]);
     }
     for (int i = i0; i < i1; ++i) {
-        Ring7<T> nxt = {};
-        Streams<T> snxt;
-        const bool more = i + 1 < i1;
-        if (more) {
-            fetch(i + 1, nxt);
-            load_streams<T, MODE>(a, cb + (size_t)(i + 1) * P + pp, snxt);
+        const int b = i & 1;
+        const Lev7<T>& R0 = R[0];
+        const Lev7<T>& R1 = R[1];
+        su[b][so] = R0.u;
+        if (tm.has_h) su[b][tm.h_slot] = R0.h;
+        if (cf) {
+            sc[b][so] = R0.c;
+            if (tm.has_h) sc[b][tm.h_slot] = R0.ch;
+        }
+        // loads for level i+DEPTH (its own value is a radial neighbour later)
+        if (i + DEPTH < nr && i + DEPTH <= i1)
+            fetch7<T, MODE, VIRT>(a, u, y, cf, tm, cb, P, i + DEPTH, i + DEPTH < i1, R[DEPTH]);
+        __syncthreads();
+        const T uc = R0.u;
+        const T cc = cf ? R0.c : a.cs;
+        const T us = su[b][so - HX], un = su[b][so + HX], uw = su[b][so - 1], ue = su[b][so + 1];
+        T cs_ = a.cs, cn = a.cs, cw = a.cs, ce = a.cs;
+        if (cf) {
+            cs_ = sc[b][so - HX];
+            cn = sc[b][so + HX];
+            cw = sc[b][so - 1];
+            ce = sc[b][so + 1];
         }
         const T half = T(0.5);
         const T gtri = g.gtr[i];
@@ -266,105 +336,72 @@ __global__ __launch_bounds__(kBlock) void k_iso7(Geo<T> g, KArgs<T> a)
             ul = a.affine ? a.ub_in[ob] : T(0);
         }
         if (i < nr - 1) {
-            Cu = half * (cc + cur.cp) * (g.gr[i + 1] * vtj * vpk);
-            uu = cur.up;
+            Cu = half * (cc + (cf ? R1.c : a.cs)) * (g.gr[i + 1] * vtj * vpk);
+            uu = R1.u;
         } else {
             Cu = (a.bc_out == 0) ? cc * (g.gr[nr] * vtj * vpk) : T(0);
             uu = a.affine ? a.ub_out[ob] : T(0);
         }
         T Lu = Cl * (uc - ul);
         Lu += Cu * (uc - uu);
-        Lu += half * (cc + cur.cs) * (gtri * gts * vpk) * (uc - cur.s);
-        Lu += half * (cc + cur.cn) * (gtri * gtn * vpk) * (uc - cur.n);
-        Lu += half * (cc + cur.cw) * (gtri * gpj * gpw) * (uc - cur.w);
-        Lu += half * (cc + cur.ce) * (gtri * gpj * gpe) * (uc - cur.e);
+        Lu += half * (cc + cs_) * (gtri * gts * vpk) * (uc - us);
+        Lu += half * (cc + cn) * (gtri * gtn * vpk) * (uc - un);
+        Lu += half * (cc + cw) * (gtri * gpj * gpw) * (uc - uw);
+        Lu += half * (cc + ce) * (gtri * gpj * gpe) * (uc - ue);
         const T V = g.vr[i] * vtj * vpk;
-        if (valid) epilogue<T, MODE>(a, cb + (size_t)i * P + pp, Lu, V, uc, scur, acc);
-        um = uc; uc = cur.up; cm = cc; cc = cur.cp;
-        cur = nxt;
-        scur = snxt;
+        if (tm.valid) epilogue<T, MODE>(a, cb + (size_t)i * P + tm.own_off, Lu, V, uc, R0.s, acc);
+        um = uc;
+        cm = cc;
+#pragma unroll
+        for (int q = 0; q < DEPTH; ++q) R[q] = R[q + 1];
     }
     finish<T, MODE>(a, L, acc);
 }
 
 // ------------------------------------------------------------ field-aligned
-//
-// Per thread and level: the 3x3 (theta, phi) neighbourhood of the thread's
-// cell (rows j-1, j+1 only when the corners that use them exist) and the
-// three coefficients of the four corners A(j,k) B(j,k+1) C(j+1,k) D(j+1,k+1)
-// of the corner plane above.  Level i+2 and corner plane i+2 are fetched
-// while level i is computed.
 
+// one corner plane ic's loads of a thread: its own / halo cell of level ic,
+// the coefficients of corners t and t + 256, and the stage streams of the
+// own cell at level ic - 1 (the level that plane completes)
 template <class T>
-struct Nb9 {
-    T x00, x01, x02, x10, x11, x12, x20, x21, x22;
-};
-template <class T>
-struct E12 {
-    T ar, at, ap, br, bt, bp, cr, ct, cp, dr, dt, dp;
+struct LevA {
+    T u, h;
+    T e0r, e0t, e0p, e1r, e1t, e1p;
+    Streams<T> s;
 };
 
-// rows r0/r2 are clamped to the cell's own row at the poles, where the
-// corners that use them have zero coefficients
-template <class T, bool VIRT>
-__device__ __forceinline__ void load9(const KArgs<T>& a, const T* u, const T* y, size_t lv, int r0,
-                                      int r1, int r2, int c0, int c1, int c2, Nb9<T>& x)
+template <class T, int MODE, bool VIRT>
+__device__ __forceinline__ void fetchA(const KArgs<T>& a, const T* u, const T* y, const TileMap& tm,
+                                       size_t cb, int P, int nr, int nt, int np, size_t nco,
+                                       int ic, int i0, int i1, int cq0, int cq1, bool has_c1,
+                                       LevA<T>& R)
 {
-    x.x00 = ldu<T, VIRT>(a, u, y, lv + r0 + c0);
-    x.x01 = ldu<T, VIRT>(a, u, y, lv + r0 + c1);
-    x.x02 = ldu<T, VIRT>(a, u, y, lv + r0 + c2);
-    x.x10 = ldu<T, VIRT>(a, u, y, lv + r1 + c0);
-    x.x11 = ldu<T, VIRT>(a, u, y, lv + r1 + c1);
-    x.x12 = ldu<T, VIRT>(a, u, y, lv + r1 + c2);
-    x.x20 = ldu<T, VIRT>(a, u, y, lv + r2 + c0);
-    x.x21 = ldu<T, VIRT>(a, u, y, lv + r2 + c1);
-    x.x22 = ldu<T, VIRT>(a, u, y, lv + r2 + c2);
+    if (ic < nr) {
+        const size_t lb = (size_t)ic * P;
+        R.u = ldu<T, VIRT>(a, u, y, lb + tm.own_off);
+        if (tm.has_h) R.h = ldu<T, VIRT>(a, u, y, lb + tm.h_off);
+    }
+    const size_t qb = (size_t)ic * (nt + 1) * np;
+    R.e0r = a.e[qb + cq0];
+    R.e0t = a.e[nco + qb + cq0];
+    R.e0p = a.e[2 * nco + qb + cq0];
+    if (has_c1) {
+        R.e1r = a.e[qb + cq1];
+        R.e1t = a.e[nco + qb + cq1];
+        R.e1p = a.e[2 * nco + qb + cq1];
+    }
+    if (ic - 1 >= i0 && ic - 1 < i1)
+        load_streams<T, MODE>(a, cb + (size_t)(ic - 1) * P + tm.own_off, R.s);
 }
 
-template <class T>
-__device__ __forceinline__ void load_e(const T* e, size_t nco, size_t q0, size_t q1, int k, int kp,
-                                       E12<T>& E)
-{
-    E.ar = e[q0 + k]; E.at = e[nco + q0 + k]; E.ap = e[2 * nco + q0 + k];
-    E.br = e[q0 + kp]; E.bt = e[nco + q0 + kp]; E.bp = e[2 * nco + q0 + kp];
-    E.cr = e[q1 + k]; E.ct = e[nco + q1 + k]; E.cp = e[2 * nco + q1 + k];
-    E.dr = e[q1 + kp]; E.dt = e[nco + q1 + kp]; E.dp = e[2 * nco + q1 + kp];
-}
-
-// mirror ghost level across a radial boundary: Dirichlet 2 u_b - u (u_b = 0
-// in linear mode), no-flux u
-template <class T>
-__device__ __forceinline__ T ghost1(T x, const T* ub, size_t o, int bc, int affine)
-{
-    if (bc != 0) return x;
-    const T b = affine ? ub[o] : T(0);
-    return T(2) * b - x;
-}
-
-template <class T>
-__device__ __forceinline__ void ghost9(const Nb9<T>& x, const T* ub, int bc, int affine,
-                                       size_t ob, int r0, int r1, int r2, int c0, int c1, int c2,
-                                       Nb9<T>& gx)
-{
-    gx.x00 = ghost1(x.x00, ub, ob + r0 + c0, bc, affine);
-    gx.x01 = ghost1(x.x01, ub, ob + r0 + c1, bc, affine);
-    gx.x02 = ghost1(x.x02, ub, ob + r0 + c2, bc, affine);
-    gx.x10 = ghost1(x.x10, ub, ob + r1 + c0, bc, affine);
-    gx.x11 = ghost1(x.x11, ub, ob + r1 + c1, bc, affine);
-    gx.x12 = ghost1(x.x12, ub, ob + r1 + c2, bc, affine);
-    gx.x20 = ghost1(x.x20, ub, ob + r2 + c0, bc, affine);
-    gx.x21 = ghost1(x.x21, ub, ob + r2 + c1, bc, affine);
-    gx.x22 = ghost1(x.x22, ub, ob + r2 + c2, bc, affine);
-}
-
-// Scatter weights of the thread's cell for one corner plane: as the upper
-// cell (wu) and the lower cell (wd) of a corner with coefficients (er, et, ep)
-// where st, sp = +1 when the cell is the corner's upper row / column.
+// Scatter weights for one corner plane: the cell's weight as the upper cell
+// is ru*er + tu*(st*et + sp*ep), as the lower cell rd*er + td*(...), with
+// st, sp = +1 when the cell is the corner's upper row / column.
 // kind 0: interior plane; 1: inner radial boundary (real cells above);
 // 2: outer radial boundary (real cells below).
 template <class T>
 struct PlaneW {
-    T ru, rd, tu, td;  // wu = ru*er + tu*tang, wd = rd*er + td*tang
+    T ru, rd, tu, td;
 };
 
 template <class T>
@@ -381,118 +418,159 @@ __device__ __forceinline__ PlaneW<T> plane_weights(int kind, int bc)
     return w;
 }
 
-// one corner: flux t = e . D, D the averaged differences over its 2x2x2
-// cells (lower level l*, upper level h*: 00 = (row0,col0), 01 = (row0,col1),
-// 10 = (row1,col0), 11 = (row1,col1)); accumulates the cell's weight times t
+// mirror ghost across a radial boundary: Dirichlet 2 u_b - u (u_b = 0 in
+// linear mode), no-flux u
 template <class T>
-__device__ __forceinline__ void corner1(T l00, T l01, T l10, T l11, T h00, T h01, T h10, T h11,
-                                        T er, T et, T ep, T st, T sp, const PlaneW<T>& w, T& up,
-                                        T& dn)
+__device__ __forceinline__ T ghost(T x, const T* ub, size_t o, int bc, int affine)
 {
-    const T qt = T(0.25);
-    const T s00 = l00 + h00, s01 = l01 + h01, s10 = l10 + h10, s11 = l11 + h11;
-    const T Dr = qt * ((h00 - l00) + (h01 - l01) + (h10 - l10) + (h11 - l11));
-    const T Dt = qt * (s10 + s11 - s00 - s01);
-    const T Dp = qt * (s01 + s11 - s00 - s10);
-    const T t = er * Dr + et * Dt + ep * Dp;
-    const T tang = st * et + sp * ep;
-    up += (w.ru * er + w.tu * tang) * t;
-    dn += (w.rd * er + w.td * tang) * t;
+    if (bc != 0) return x;
+    const T b = affine ? ub[o] : T(0);
+    return T(2) * b - x;
 }
 
+// flux t = e . D of tile corner (cy, cx) between the LDS planes lo and hi;
+// gside 1: lo is the mirror ghost of hi, 2: hi is the ghost of lo
 template <class T>
-__device__ __forceinline__ void corner_plane(const Nb9<T>& lo, const Nb9<T>& hi, const E12<T>& E,
-                                             const PlaneW<T>& w, T& up, T& dn)
+__device__ __forceinline__ T corner_flux(const T* lo, const T* hi, int cy, int cx, T er, T et,
+                                         T ep, int gside, const T* ub, int bc, int affine,
+                                         size_t ubo, int j0, int k0, int nt, int np)
 {
-    up = 0;
-    dn = 0;
-    // A: rows (j-1, j), columns (k-1, k): the cell is row 1, column 1
-    corner1<T>(lo.x00, lo.x01, lo.x10, lo.x11, hi.x00, hi.x01, hi.x10, hi.x11, E.ar, E.at, E.ap,
-               T(1), T(1), w, up, dn);
-    // B: rows (j-1, j), columns (k, k+1)
-    corner1<T>(lo.x01, lo.x02, lo.x11, lo.x12, hi.x01, hi.x02, hi.x11, hi.x12, E.br, E.bt, E.bp,
-               T(1), T(-1), w, up, dn);
-    // C: rows (j, j+1), columns (k-1, k)
-    corner1<T>(lo.x10, lo.x11, lo.x20, lo.x21, hi.x10, hi.x11, hi.x20, hi.x21, E.cr, E.ct, E.cp,
-               T(-1), T(1), w, up, dn);
-    // D: rows (j, j+1), columns (k, k+1)
-    corner1<T>(lo.x11, lo.x12, lo.x21, lo.x22, hi.x11, hi.x12, hi.x21, hi.x22, E.dr, E.dt, E.dp,
-               T(-1), T(-1), w, up, dn);
+    const int s00 = cy * HX + cx, s01 = s00 + 1, s10 = s00 + HX, s11 = s10 + 1;
+    T l00, l01, l10, l11, h00, h01, h10, h11;
+    if (gside == 1) {
+        h00 = hi[s00]; h01 = hi[s01]; h10 = hi[s10]; h11 = hi[s11];
+        l00 = ghost(h00, ub, ubo + slot_offset(cy, cx, j0, k0, nt, np), bc, affine);
+        l01 = ghost(h01, ub, ubo + slot_offset(cy, cx + 1, j0, k0, nt, np), bc, affine);
+        l10 = ghost(h10, ub, ubo + slot_offset(cy + 1, cx, j0, k0, nt, np), bc, affine);
+        l11 = ghost(h11, ub, ubo + slot_offset(cy + 1, cx + 1, j0, k0, nt, np), bc, affine);
+    } else if (gside == 2) {
+        l00 = lo[s00]; l01 = lo[s01]; l10 = lo[s10]; l11 = lo[s11];
+        h00 = ghost(l00, ub, ubo + slot_offset(cy, cx, j0, k0, nt, np), bc, affine);
+        h01 = ghost(l01, ub, ubo + slot_offset(cy, cx + 1, j0, k0, nt, np), bc, affine);
+        h10 = ghost(l10, ub, ubo + slot_offset(cy + 1, cx, j0, k0, nt, np), bc, affine);
+        h11 = ghost(l11, ub, ubo + slot_offset(cy + 1, cx + 1, j0, k0, nt, np), bc, affine);
+    } else {
+        l00 = lo[s00]; l01 = lo[s01]; l10 = lo[s10]; l11 = lo[s11];
+        h00 = hi[s00]; h01 = hi[s01]; h10 = hi[s10]; h11 = hi[s11];
+    }
+    const T qt = T(0.25);
+    const T a00 = l00 + h00, a01 = l01 + h01, a10 = l10 + h10, a11 = l11 + h11;
+    const T Dr = qt * ((h00 - l00) + (h01 - l01) + (h10 - l10) + (h11 - l11));
+    const T Dt = qt * (a10 + a11 - a00 - a01);
+    const T Dp = qt * (a01 + a11 - a00 - a10);
+    return er * Dr + et * Dt + ep * Dp;
 }
 
 template <class T, int MODE, bool VIRT>
 __global__ __launch_bounds__(kBlock) void k_aligned(Geo<T> g, KArgs<T> a)
 {
+    __shared__ T su[3][HN];                        // cell planes (ring of three levels)
+    __shared__ T sr[NCOR], sth[NCOR], sph[NCOR];   // t e_r, t e_t, t e_p per tile corner
     const int L = xcd_tile();
     if (L >= a.nbx * a.nrc * a.nc) return;
     if (a.done && *a.done) return;
-    const int bx = L % a.nbx, rest = L / a.nbx, rc = rest % a.nrc, c = rest / a.nrc;
     const int np = g.np, nt = g.nt, nr = g.nr, P = g.P;
-    const int p = bx * kBlock + threadIdx.x;
-    const bool valid = p < P;
-    const int pp = valid ? p : P - 1;
-    const int j = pp / np, k = pp - j * np;
-    const int km = (k == 0) ? np - 1 : k - 1, kp = (k == np - 1) ? 0 : k + 1;
-    const int r1 = j * np;
-    const int r0 = (j >= 1) ? r1 - np : r1, r2 = (j + 1 <= nt - 1) ? r1 + np : r1;
+    const int ntk = (np + TX - 1) / TX;
+    const int bx = L % a.nbx, rest = L / a.nbx, rc = rest % a.nrc, c = rest / a.nrc;
+    const TileMap tm = tile_map(bx % ntk, bx / ntk, nt, np);
     const size_t cb = (size_t)c * nr * P;
     const T* u = a.u + cb;
     const T* y = VIRT ? a.y0 + cb : nullptr;
-    const size_t ob = (size_t)c * P;
+    const size_t ubo = (size_t)c * P;
     const size_t nco = (size_t)(nr + 1) * (nt + 1) * np;
-    const size_t cplane = (size_t)(nt + 1) * np;
-    const size_t qa = (size_t)j * np, qc = (size_t)(j + 1) * np;  // corner rows j, j+1 (<= nt)
     const int i0 = a.r_lo + rc * a.rch;
     const int i1 = min(a.r_hi, i0 + a.rch);
+    const int j = min(tm.j, nt - 1), k = tm.valid ? tm.k : 0;
     const T vtj = g.vt[j], vpk = g.vp[k];
+    const int t = threadIdx.x;
+    // the thread's corners of a tile plane: t and t + 256 (< NCOR); corner
+    // rows beyond the last pole row read the (zero) pole row
+    const bool has_c1 = t + kBlock < NCOR;
+    const int ci1 = has_c1 ? t + kBlock : t;
+    const int cy0 = t / CX, cx0 = t % CX, cy1 = ci1 / CX, cx1 = ci1 % CX;
+    const int cq0 = min(tm.j0 + cy0, nt) * np + wrapk(tm.k0 + cx0, np);
+    const int cq1 = min(tm.j0 + cy1, nt) * np + wrapk(tm.k0 + cx1, np);
+    // the own cell's corners A (ty, tx), B (ty, tx+1), C (ty+1, tx), D (ty+1, tx+1)
+    const int cA = tm.ty * CX + tm.tx;
     Acc<T, MODE> acc;
-    Nb9<T> lo = {}, hi = {}, nx = {};
-    E12<T> E = {}, En = {};
-    Streams<T> scur, snxt;
+    // ring R[q] = loads of corner plane ic + q; plane ic + DEPTH is issued
+    // while plane ic is computed
+    constexpr int DEPTH = 2;
+    LevA<T> R[DEPTH + 1] = {};
     T carry = 0;
     if (i0 < i1) {
-        load9<T, VIRT>(a, u, y, (size_t)i0 * P, r0, r1, r2, km, k, kp, hi);
-        if (i0 == 0)
-            ghost9<T>(hi, a.ub_in, a.bc_in, a.affine, ob, r0, r1, r2, km, k, kp, lo);
-        else
-            load9<T, VIRT>(a, u, y, (size_t)(i0 - 1) * P, r0, r1, r2, km, k, kp, lo);
-        load_e<T>(a.e, nco, (size_t)i0 * cplane + qa, (size_t)i0 * cplane + qc, k, kp, E);
-        T up, dn;
-        corner_plane<T>(lo, hi, E, plane_weights<T>(i0 == 0 ? 1 : 0, a.bc_in), up, dn);
-        carry = up;
-        // level i0+1 and corner plane i0+1 for the first iteration
-        load9<T, VIRT>(a, u, y, (size_t)min(i0 + 1, nr - 1) * P, r0, r1, r2, km, k, kp, nx);
-        load_e<T>(a.e, nco, (size_t)(i0 + 1) * cplane + qa, (size_t)(i0 + 1) * cplane + qc, k, kp,
-                  E);
-        load_streams<T, MODE>(a, cb + (size_t)i0 * P + pp, scur);
+        if (i0 > 0) {
+            const size_t lb = (size_t)(i0 - 1) * P;
+            su[(i0 - 1) % 3][tm.own_slot] = ldu<T, VIRT>(a, u, y, lb + tm.own_off);
+            if (tm.has_h) su[(i0 - 1) % 3][tm.h_slot] = ldu<T, VIRT>(a, u, y, lb + tm.h_off);
+        }
+#pragma unroll
+        for (int q = 0; q < DEPTH; ++q)
+            if (i0 + q <= i1)
+                fetchA<T, MODE, VIRT>(a, u, y, tm, cb, P, nr, nt, np, nco, i0 + q, i0, i1, cq0, cq1,
+                                      has_c1, R[q]);
     }
-    for (int i = i0; i < i1; ++i) {
-        const int ic = i + 1;
-        lo = hi;
-        int kind = 0, bc = 0;
+    // corner plane ic completes cell level ic-1 and starts level ic
+    for (int ic = i0; ic <= i1 && i0 < i1; ++ic) {
+        const int bh = ic % 3, bl = (ic + 2) % 3;
+        const LevA<T>& R0 = R[0];
         if (ic < nr) {
-            hi = nx;
-        } else {
-            ghost9<T>(lo, a.ub_out, a.bc_out, a.affine, ob, r0, r1, r2, km, k, kp, hi);
-            kind = 2;
-            bc = a.bc_out;
+            su[bh][tm.own_slot] = R0.u;
+            if (tm.has_h) su[bh][tm.h_slot] = R0.h;
         }
-        // prefetch level i+2 and corner plane i+2 for the next iteration
-        const bool more = i + 1 < i1;
-        if (more) {
-            load9<T, VIRT>(a, u, y, (size_t)min(ic + 1, nr - 1) * P, r0, r1, r2, km, k, kp, nx);
-            load_e<T>(a.e, nco, (size_t)(ic + 1) * cplane + qa, (size_t)(ic + 1) * cplane + qc, k,
-                      kp, En);
-            load_streams<T, MODE>(a, cb + (size_t)(i + 1) * P + pp, snxt);
+        if (ic + DEPTH <= i1)
+            fetchA<T, MODE, VIRT>(a, u, y, tm, cb, P, nr, nt, np, nco, ic + DEPTH, i0, i1, cq0, cq1,
+                                  has_c1, R[DEPTH]);
+        __syncthreads();
+        int kind = 0, gside = 0, bc = 0;
+        const T* ub = nullptr;
+        if (ic == 0) { kind = 1; gside = 1; bc = a.bc_in; ub = a.ub_in; }
+        else if (ic == nr) { kind = 2; gside = 2; bc = a.bc_out; ub = a.ub_out; }
+        const T* lo = su[bl];
+        const T* hi = su[bh];
+        {
+            const T f0 = corner_flux<T>(lo, hi, cy0, cx0, R0.e0r, R0.e0t, R0.e0p, gside, ub, bc,
+                                        a.affine, ubo, tm.j0, tm.k0, nt, np);
+            sr[t] = f0 * R0.e0r;
+            sth[t] = f0 * R0.e0t;
+            sph[t] = f0 * R0.e0p;
+            if (has_c1) {
+                const T f1 = corner_flux<T>(lo, hi, cy1, cx1, R0.e1r, R0.e1t, R0.e1p, gside, ub,
+                                            bc, a.affine, ubo, tm.j0, tm.k0, nt, np);
+                sr[ci1] = f1 * R0.e1r;
+                sth[ci1] = f1 * R0.e1t;
+                sph[ci1] = f1 * R0.e1p;
+            }
         }
-        T up, dn;
-        corner_plane<T>(lo, hi, E, plane_weights<T>(kind, bc), up, dn);
-        const T Lu = carry + dn;
+        __syncthreads();
+        const PlaneW<T> w = plane_weights<T>(kind, bc);
+        T up = 0, dn = 0;
+        {
+            // A: st=+1 sp=+1; B: st=+1 sp=-1; C: st=-1 sp=+1; D: st=-1 sp=-1
+            const T tA = sth[cA] + sph[cA];
+            const T tB = sth[cA + 1] - sph[cA + 1];
+            const T tC = -sth[cA + CX] + sph[cA + CX];
+            const T tD = -sth[cA + CX + 1] - sph[cA + CX + 1];
+            const T rA = sr[cA], rB = sr[cA + 1], rC = sr[cA + CX], rD = sr[cA + CX + 1];
+            up = w.ru * rA + w.tu * tA;
+            up += w.ru * rB + w.tu * tB;
+            up += w.ru * rC + w.tu * tC;
+            up += w.ru * rD + w.tu * tD;
+            dn = w.rd * rA + w.td * tA;
+            dn += w.rd * rB + w.td * tB;
+            dn += w.rd * rC + w.td * tC;
+            dn += w.rd * rD + w.td * tD;
+        }
+        if (ic - 1 >= i0) {
+            const int i = ic - 1;
+            const T Lu = carry + dn;
+            const T V = g.vr[i] * vtj * vpk;
+            const T uc = lo[tm.own_slot];
+            if (tm.valid) epilogue<T, MODE>(a, cb + (size_t)i * P + tm.own_off, Lu, V, uc, R0.s, acc);
+        }
         carry = up;
-        const T V = g.vr[i] * vtj * vpk;
-        if (valid) epilogue<T, MODE>(a, cb + (size_t)i * P + pp, Lu, V, lo.x11, scur, acc);
-        E = En;
-        scur = snxt;
+#pragma unroll
+        for (int q = 0; q < DEPTH; ++q) R[q] = R[q + 1];
     }
     finish<T, MODE>(a, L, acc);
 }
@@ -540,208 +618,5 @@ template void launch_iso7<double>(int, bool, const Geo<double>&, const KArgs<dou
 template void launch_iso7<float>(int, bool, const Geo<float>&, const KArgs<float>&, hipStream_t);
 template void launch_aligned<double>(int, bool, const Geo<double>&, const KArgs<double>&, hipStream_t);
 template void launch_aligned<float>(int, bool, const Geo<float>&, const KArgs<float>&, hipStream_t);
-
-// ------------------------------------------------------------ setup kernels
-
-__global__ void k_coef(const double* T0, double scale, double expo, int n, double* c64,
-                       float* c32, int* flag)
-{
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= n) return;
-    const double c = T0 ? scale * pow(T0[m], expo) : scale;
-    if (!isfinite(c) || c < 0.0) atomicOr(flag, 1);
-    c64[m] = c;
-    if (c32) c32[m] = (float)c;
-}
-
-void launch_coef(const double* T0, double scale, double expo, int n, double* c64, float* c32,
-                 int* flag, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_coef, dim3((n + 255) / 256), dim3(256), 0, s, T0, scale, expo, n, c64,
-                       c32, flag);
-}
-
-// per-corner coefficients e_d = sqrt(W kappa_c) bhat_d / h_d
-__global__ void k_corner_e(int nr, int nt, int np, CornerGeo cg, const double* coef,
-                           const double* B, double* e64, float* e32, int* flag)
-{
-    const size_t nco = (size_t)(nr + 1) * (nt + 1) * np;
-    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nco) return;
-    const int kc = (int)(q % np);
-    const int jc = (int)((q / np) % (nt + 1));
-    const int ic = (int)(q / ((size_t)np * (nt + 1)));
-    double er = 0.0, et = 0.0, ep = 0.0;
-    if (jc > 0 && jc < nt) {
-        const int kl = (kc == 0) ? np - 1 : kc - 1;
-        const size_t P = (size_t)nt * np;
-        double ks = 0.0;
-        int nk = 0;
-        for (int a = 0; a < 2; ++a) {
-            const int i = ic - 1 + a;
-            if (i < 0 || i >= nr) continue;
-            for (int b = 0; b < 2; ++b) {
-                const size_t rowo = (size_t)i * P + (size_t)(jc - 1 + b) * np;
-                ks += coef[rowo + kl] + coef[rowo + kc];
-                nk += 2;
-            }
-        }
-        const double kap = ks / nk;
-        const double bx = B[q], by = B[nco + q], bz = B[2 * nco + q];
-        const double mag = sqrt(bx * bx + by * by + bz * bz);
-        if (!isfinite(mag)) atomicOr(flag, 1);
-        if (mag > 0.0) {
-            const double Rc = cg.R[ic];
-            const double hr = cg.hr[ic];
-            const double ht = Rc * cg.htt[jc];
-            const double hp = Rc * cg.sT[jc] * cg.dpc[kc];
-            const double W = cg.wr[ic] * ht * hp;
-            const double sw = sqrt(W * kap) / mag;
-            er = sw * bx / hr;
-            et = sw * by / ht;
-            ep = sw * bz / hp;
-        }
-    }
-    e64[q] = er;
-    e64[nco + q] = et;
-    e64[2 * nco + q] = ep;
-    if (e32) {
-        e32[q] = (float)er;
-        e32[nco + q] = (float)et;
-        e32[2 * nco + q] = (float)ep;
-    }
-}
-
-void launch_corner_e(int nr, int nt, int np, const CornerGeo& cg, const double* coef,
-                     const double* B, double* e64, float* e32, int* flag, hipStream_t s)
-{
-    const size_t nco = (size_t)(nr + 1) * (nt + 1) * np;
-    hipLaunchKernelGGL(k_corner_e, dim3((unsigned)((nco + 255) / 256)), dim3(256), 0, s, nr, nt,
-                       np, cg, coef, B, e64, e32, flag);
-}
-
-// diag(L) and the Gershgorin row bound sum_n |L_mn| / V_m (per-block maxima)
-__global__ __launch_bounds__(kBlock) void k_diag_iso7(Geo<double> g, const double* coef,
-                                                      double cs, int bc_in, int bc_out,
-                                                      double* diag, double* part)
-{
-    __shared__ double lds[kBlock / 64];
-    const int nr = g.nr, nt = g.nt, np = g.np, P = g.P;
-    const size_t N = (size_t)nr * P;
-    const size_t m = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double rho = 0.0;
-    if (m < N) {
-        const int i = (int)(m / P), pp = (int)(m % P), j = pp / np, k = pp % np;
-        const int km = (k == 0) ? np - 1 : k - 1, kp = (k == np - 1) ? 0 : k + 1;
-        auto cf = [&](size_t q) { return coef ? coef[q] : cs; };
-        const double cc = cf(m);
-        const double vt = g.vt[j], vp = g.vp[k];
-        double d = 0.0, off = 0.0, C;
-        if (i > 0) { C = 0.5 * (cc + cf(m - P)) * (g.gr[i] * vt * vp); d += C; off += C; }
-        else if (bc_in == 0) d += cc * (g.gr[0] * vt * vp);
-        if (i < nr - 1) { C = 0.5 * (cc + cf(m + P)) * (g.gr[i + 1] * vt * vp); d += C; off += C; }
-        else if (bc_out == 0) d += cc * (g.gr[nr] * vt * vp);
-        if (j > 0) { C = 0.5 * (cc + cf(m - np)) * (g.gtr[i] * g.gtt[j] * vp); d += C; off += C; }
-        if (j < nt - 1) { C = 0.5 * (cc + cf(m + np)) * (g.gtr[i] * g.gtt[j + 1] * vp); d += C; off += C; }
-        const size_t rb = m - k;
-        C = 0.5 * (cc + cf(rb + km)) * (g.gtr[i] * g.gpt[j] * g.gpp[k]); d += C; off += C;
-        C = 0.5 * (cc + cf(rb + kp)) * (g.gtr[i] * g.gpt[j] * g.gpp[kp]); d += C; off += C;
-        diag[m] = d;
-        rho = (d + off) / (g.vr[i] * vt * vp);
-    }
-    // block maximum (values are >= 0)
-    double v = rho;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double b = lds[0];
-        for (int w = 1; w < kBlock / 64; ++w) b = fmax(b, lds[w]);
-        part[blockIdx.x] = b;
-    }
-}
-
-__global__ __launch_bounds__(kBlock) void k_diag_aligned(Geo<double> g, const double* e,
-                                                         int bc_in, int bc_out, double* diag,
-                                                         double* part)
-{
-    __shared__ double lds[kBlock / 64];
-    const int nr = g.nr, nt = g.nt, np = g.np, P = g.P;
-    const size_t N = (size_t)nr * P;
-    const size_t nco = (size_t)(nr + 1) * (nt + 1) * np;
-    const size_t m = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double rho = 0.0;
-    if (m < N) {
-        const int i = (int)(m / P), pp = (int)(m % P), j = pp / np, k = pp % np;
-        const int kp = (k == np - 1) ? 0 : k + 1;
-        double d = 0.0, s = 0.0;
-        for (int a = 0; a < 2; ++a) {        // corner plane ic = i + 1 - a
-            const int ic = i + 1 - a;
-            const double sr = a ? 1.0 : -1.0;  // a = 1: cell is above the plane
-            for (int b = 0; b < 2; ++b) {    // corner row jc = j + 1 - b
-                const int jc = j + 1 - b;
-                if (jc == 0 || jc == nt) continue;
-                const double st = b ? 1.0 : -1.0;
-                for (int c = 0; c < 2; ++c) {
-                    const int kc = c ? k : kp;
-                    const double sp = c ? 1.0 : -1.0;
-                    const size_t q = ((size_t)ic * (nt + 1) + jc) * np + kc;
-                    const double er = e[q], et = e[nco + q], ep = e[2 * nco + q];
-                    double w, wsum = 0.0;
-                    const bool bnd = (ic == 0) || (ic == nr);
-                    const int bc = (ic == 0) ? bc_in : bc_out;
-                    if (!bnd) {
-                        w = 0.25 * (sr * er + st * et + sp * ep);
-                        for (int x = 0; x < 8; ++x)
-                            wsum += fabs(0.25 * ((x & 4 ? 1.0 : -1.0) * er + (x & 2 ? 1.0 : -1.0) * et +
-                                                 (x & 1 ? 1.0 : -1.0) * ep));
-                    } else if (bc == 0) {
-                        w = 0.5 * sr * er;
-                        wsum = 4.0 * fabs(0.5 * er);
-                    } else {
-                        w = 0.5 * (st * et + sp * ep);
-                        for (int x = 0; x < 4; ++x)
-                            wsum += fabs(0.5 * ((x & 2 ? 1.0 : -1.0) * et + (x & 1 ? 1.0 : -1.0) * ep));
-                    }
-                    d += w * w;
-                    s += fabs(w) * wsum;
-                }
-            }
-        }
-        diag[m] = d;
-        rho = s / (g.vr[i] * g.vt[j] * g.vp[k]);
-    }
-    double v = rho;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double b = lds[0];
-        for (int w = 1; w < kBlock / 64; ++w) b = fmax(b, lds[w]);
-        part[blockIdx.x] = b;
-    }
-}
-
-void launch_diag_iso7(const Geo<double>& g, const double* coef, double cs, int bc_in, int bc_out,
-                      double* diag, double* part, hipStream_t s, int* nparts)
-{
-    const size_t N = (size_t)g.nr * g.P;
-    const int nb = (int)((N + kBlock - 1) / kBlock);
-    *nparts = nb;
-    hipLaunchKernelGGL(k_diag_iso7, dim3(nb), dim3(kBlock), 0, s, g, coef, cs, bc_in, bc_out, diag,
-                       part);
-}
-
-void launch_diag_aligned(const Geo<double>& g, const double* e, int bc_in, int bc_out,
-                         double* diag, double* part, hipStream_t s, int* nparts)
-{
-    const size_t N = (size_t)g.nr * g.P;
-    const int nb = (int)((N + kBlock - 1) / kBlock);
-    *nparts = nb;
-    hipLaunchKernelGGL(k_diag_aligned, dim3(nb), dim3(kBlock), 0, s, g, e, bc_in, bc_out, diag,
-                       part);
-}
 
 }  // namespace pa

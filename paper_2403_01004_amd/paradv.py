@@ -30,7 +30,11 @@ PRECS = {"fp64": 0, "fp32": 1}
 EXPORTS = ["pa_init", "pa_destroy", "pa_last_error", "pa_default_options", "pa_set_options",
            "pa_bind_field", "pa_set_coefficients", "pa_set_bc", "pa_dt_explicit", "pa_apply",
            "pa_diag", "pa_compute_ptl", "pa_advance_rkl2", "pa_advance_rkg2",
-           "pa_advance_be_pcg"]
+           "pa_advance_be_pcg", "pa_lpc_default_train_opts", "pa_lpc_set_weights",
+           "pa_lpc_get_weights", "pa_lpc_features", "pa_lpc_apply", "pa_lpc_loss_grad",
+           "pa_lpc_train"]
+PA_LPC_NPARAM = 10832
+PCS = {"jacobi": 0, "learned": 1}
 
 _ALLOC = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 _FREE = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
@@ -56,8 +60,8 @@ class pa_opts(ctypes.Structure):
                 ("timing", ctypes.c_int32)]
 
 
-PA_NKCLASS = 8
-KERNEL_CLASSES = ["first", "stage", "matvec", "update", "dir", "init", "reduce", "other"]
+PA_NKCLASS = 9
+KERNEL_CLASSES = ["first", "stage", "matvec", "update", "dir", "init", "reduce", "other", "nn"]
 
 
 class pa_stats(ctypes.Structure):
@@ -72,6 +76,21 @@ class pa_stats(ctypes.Structure):
                 ("kernel_calls", ctypes.c_int32 * PA_NKCLASS),
                 ("dt_cycle", ctypes.c_double * PA_MAX_LOG),
                 ("per_cycle", ctypes.c_int32 * PA_MAX_LOG)]
+
+
+class pa_lpc_train_opts(ctypes.Structure):
+    _fields_ = [("npairs", ctypes.c_int32), ("crop_r", ctypes.c_int32),
+                ("crop_t", ctypes.c_int32), ("crop_p", ctypes.c_int32),
+                ("batch", ctypes.c_int32), ("epochs", ctypes.c_int32),
+                ("nsnap", ctypes.c_int32), ("seed", ctypes.c_int32),
+                ("lr", ctypes.c_double), ("tol_star", ctypes.c_double)]
+
+
+class pa_lpc_report(ctypes.Structure):
+    _fields_ = [("pairs", ctypes.c_int32), ("snapshots", ctypes.c_int32),
+                ("steps", ctypes.c_int32), ("ref_iters", ctypes.c_int32),
+                ("loss_first", ctypes.c_double), ("loss_last", ctypes.c_double),
+                ("ms_pairs", ctypes.c_double), ("ms_train", ctypes.c_double)]
 
 
 _lib = None
@@ -104,6 +123,13 @@ def load(path: str = LIB_PATH):
         "pa_advance_rkl2": (I32, [V, D, I32, P(pa_stats)]),
         "pa_advance_rkg2": (I32, [V, D, I32, P(pa_stats)]),
         "pa_advance_be_pcg": (I32, [V, D, D, I32, P(pa_stats)]),
+        "pa_lpc_default_train_opts": (None, [P(pa_lpc_train_opts)]),
+        "pa_lpc_set_weights": (I32, [V, V]),
+        "pa_lpc_get_weights": (I32, [V, V]),
+        "pa_lpc_features": (I32, [V, D, V, V]),
+        "pa_lpc_apply": (I32, [V, D, V, V]),
+        "pa_lpc_loss_grad": (I32, [V, D, I32, V, V, I32, P(D), V]),
+        "pa_lpc_train": (I32, [V, D, P(pa_lpc_train_opts), P(pa_lpc_report)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -180,6 +206,54 @@ def pa_advance_rkg2(ctx, dt, cycles, stats=None):
 
 def pa_advance_be_pcg(ctx, dt, tol, cycles, stats=None):
     return load().pa_advance_be_pcg(ctx, dt, tol, cycles, ctypes.byref(stats) if stats else None)
+
+
+def pa_lpc_default_train_opts():
+    o = pa_lpc_train_opts()
+    load().pa_lpc_default_train_opts(ctypes.byref(o))
+    return o
+
+
+def pa_lpc_set_weights(ctx, theta_host_ptr):
+    return load().pa_lpc_set_weights(ctx, theta_host_ptr)
+
+
+def pa_lpc_get_weights(ctx, theta_host_ptr):
+    return load().pa_lpc_get_weights(ctx, theta_host_ptr)
+
+
+def pa_lpc_features(ctx, dt, r_ptr, feat_ptr):
+    return load().pa_lpc_features(ctx, dt, r_ptr, feat_ptr)
+
+
+def pa_lpc_apply(ctx, dt, r_ptr, z_ptr):
+    return load().pa_lpc_apply(ctx, dt, r_ptr, z_ptr)
+
+
+def pa_lpc_loss_grad(ctx, dt, npairs, r_ptr, e_ptr, periodic_phi, grad_host_ptr):
+    loss = ctypes.c_double()
+    st = load().pa_lpc_loss_grad(ctx, dt, npairs, r_ptr, e_ptr, int(periodic_phi),
+                                 ctypes.byref(loss), grad_host_ptr)
+    return st, loss.value
+
+
+def pa_lpc_train(ctx, dt, opts=None, report=None):
+    return load().pa_lpc_train(ctx, dt, ctypes.byref(opts) if opts else None,
+                               ctypes.byref(report) if report else None)
+
+
+def he_init(seed):
+    """He-normal initial parameters (std sqrt(2 / fan_in), zero biases) as a
+    flat float32 vector in the ABI's parameter order."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for layer, (ci, co) in enumerate(((8, 16), (16, 16), (16, 1))):
+        parts.append(rng.standard_normal(co * ci * 27) * math.sqrt(2.0 / (ci * 27)))
+        if layer < 2:
+            parts.append(np.zeros(co))
+    theta = np.concatenate(parts).astype(np.float32)
+    assert theta.size == PA_LPC_NPARAM
+    return theta
 
 
 # ---- convenience wrapper ---------------------------------------------------
@@ -351,6 +425,50 @@ class Operator:
 
     def advance_be(self, dt, tol=1e-10, cycles=0, check=True):
         return self._adv(pa_advance_be_pcg, float(dt), float(tol), int(cycles), check=check)
+
+    # ---- learned preconditioner
+    def lpc_set_weights(self, theta):
+        th = np.ascontiguousarray(theta, dtype=np.float32)
+        if th.size != PA_LPC_NPARAM:
+            raise ValueError(f"expected {PA_LPC_NPARAM} parameters")
+        self._check(pa_lpc_set_weights(self.ctx, th.ctypes.data_as(ctypes.c_void_p)))
+
+    def lpc_get_weights(self):
+        th = np.empty(PA_LPC_NPARAM, dtype=np.float32)
+        self._check(pa_lpc_get_weights(self.ctx, th.ctypes.data_as(ctypes.c_void_p)))
+        return th
+
+    def lpc_features(self, dt, r):
+        r = self._dev(r, (self.nr, self.nt, self.np))
+        f = self.torch.empty((8, self.nr, self.nt, self.np), dtype=self.torch.float32,
+                             device=self.device)
+        self._check(pa_lpc_features(self.ctx, float(dt), self._p(r), self._p(f)))
+        return f
+
+    def lpc_apply(self, dt, r):
+        r = self._dev(r, (self.nr, self.nt, self.np))
+        z = self.torch.empty_like(r)
+        self._check(pa_lpc_apply(self.ctx, float(dt), self._p(r), self._p(z)))
+        return z
+
+    def lpc_loss_grad(self, dt, r, e, periodic_phi=True):
+        r = self._dev(r).reshape(-1, self.nr, self.nt, self.np).contiguous()
+        e = self._dev(e).reshape(r.shape).contiguous()
+        g = np.empty(PA_LPC_NPARAM, dtype=np.float32)
+        st, loss = pa_lpc_loss_grad(self.ctx, float(dt), r.shape[0], self._p(r), self._p(e),
+                                    periodic_phi, g.ctypes.data_as(ctypes.c_void_p))
+        self._check(st)
+        return loss, g
+
+    def lpc_train(self, dt, **kw):
+        o = pa_lpc_default_train_opts()
+        for k, v in kw.items():
+            if not hasattr(o, k):
+                raise TypeError(f"unknown training option {k}")
+            setattr(o, k, v)
+        rep = pa_lpc_report()
+        self._check(pa_lpc_train(self.ctx, float(dt), o, rep))
+        return {f: getattr(rep, f) for f, _ in rep._fields_}
 
 
 def exported_symbols(path: str = LIB_PATH):

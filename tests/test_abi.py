@@ -53,10 +53,27 @@ def _struct_fields(name):
 
 
 @pytest.mark.parametrize("cname,pyname", [("pa_desc", "pa_desc"), ("pa_opts", "pa_opts"),
-                                          ("pa_stats", "pa_stats")])
+                                          ("pa_stats", "pa_stats"),
+                                          ("pa_lpc_train_opts", "pa_lpc_train_opts"),
+                                          ("pa_lpc_report", "pa_lpc_report")])
 def test_struct_layout_matches_header(lib, cname, pyname):
     py = [f[0] for f in getattr(lib, pyname)._fields_]
     assert py == _struct_fields(cname)
+
+
+def test_header_constants_match_binding(lib):
+    txt = open(HEADER).read()
+    assert int(re.search(r"#define PA_LPC_NPARAM (\d+)", txt).group(1)) == lib.PA_LPC_NPARAM
+    assert int(re.search(r"PA_NKCLASS = (\d+)", txt).group(1)) == lib.PA_NKCLASS
+    assert int(re.search(r"#define PA_MAX_LOG (\d+)", txt).group(1)) == lib.PA_MAX_LOG
+
+
+def test_he_init_layout(lib):
+    th = lib.he_init(4300)
+    assert th.dtype.name == "float32" and th.size == lib.PA_LPC_NPARAM
+    assert not th[3456:3472].any() and not th[10384:10400].any()   # biases
+    assert abs(th[:3456].std() - (2.0 / 216) ** 0.5) < 0.01
+    assert abs(th[10400:].std() - (2.0 / 432) ** 0.5) < 0.01
 
 
 def test_no_cpu_fallback(lib):

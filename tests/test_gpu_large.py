@@ -1,0 +1,95 @@
+"""The largest workload, 256 x 512 x 1024 (134 M cells, 1.07 GB per FP64
+field): transition-region conduction (T jump at i_tr = 20 + 4 S(501)) and
+three-component viscosity as on the 151 x 301 x 400 grid.
+
+Whole-field comparisons with the oracle: the operator (element-wise),
+Dt_E, the practical time step limit, one RKL2 cycle (1e-12), and the FP64
+true residual of a Backward Euler solve evaluated with the oracle's
+operator.  Launch shapes are the ones the advances use at this size
+(several radial chunks, 33 x 64 tile planes, more than 2^31 bytes per
+array)."""
+import numpy as np
+import pytest
+
+from paper_2403_01004_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+SHAPE = (256, 512, 1024)
+
+
+def _log(*a):
+    print(*a, flush=True)
+
+
+def rel_l2(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_01004_amd import paradv
+    paradv.load()
+    return paradv
+
+
+@pytest.fixture(scope="module")
+def cond5():
+    _log("building 256x512x1024 transition-region conduction")
+    return inputs.transition_region(*SHAPE, seed=501, i_tr0=20.0, i_amp=4.0)
+
+
+def test_large_conduction(dev, oracle_mod, cond5):
+    prob = cond5
+    g = dev.Operator.from_problem(prob)
+    o = oracle_mod.Oracle.from_problem(prob)
+    _log("large conduction: apply")
+    Fg = g.apply(prob.u).cpu().numpy()
+    Fo = o.apply(prob.u)
+    assert np.abs(Fg - Fo).max() <= 1e-13 * np.abs(Fo).max()
+    del Fg, Fo
+    dtE = o.dt_explicit()
+    assert abs(g.dt_explicit() - dtE) <= 1e-13 * dtE
+    g.bind(prob.u)
+    pg, po = g.ptl(), o.ptl(prob.u)
+    assert pg[1] == po[1] and abs(pg[0] - po[0]) <= 1e-12 * abs(po[0])
+    _log("large conduction: one RKL2 cycle, s = 5")
+    dt = 6.0 * dtE
+    u = g.bind(prob.u)
+    st = g.advance_rkl2(dt, 1)
+    uo, so = o.advance_sts(prob.u, dt, 1, "rkl2")
+    assert st["s_total"] == so["s_total"] == 5
+    assert rel_l2(u.cpu().numpy(), uo) <= 1e-12
+
+
+def test_large_conduction_be_true_residual(dev, oracle_mod, cond5):
+    prob = cond5
+    g = dev.Operator.from_problem(prob)
+    o = oracle_mod.Oracle.from_problem(prob)
+    dt = 50.0 * g.dt_explicit()
+    _log("large conduction: BE solve")
+    u = g.bind(prob.u)
+    st = g.advance_be(dt, 1e-10, 1)
+    x = u.cpu().numpy()
+    _log("  iterations", st["iters_total"])
+    V = o.volumes()[None]
+    b = V * prob.u + dt * V * o.apply(np.zeros_like(prob.u))
+    Mx = V * x - dt * V * o.apply(x, affine=False)
+    res = np.linalg.norm(b - Mx) / np.linalg.norm(b)
+    _log("  true residual", res)
+    assert res <= 1.001e-10
+
+
+def test_large_viscosity_apply(dev, oracle_mod):
+    _log("building 256x512x1024 viscosity")
+    prob = inputs.viscosity(*SHAPE, seed=202)
+    g = dev.Operator.from_problem(prob)
+    o = oracle_mod.Oracle.from_problem(prob)
+    for affine in (True, False):
+        Fg = g.apply(prob.u, affine).cpu().numpy()
+        Fo = o.apply(prob.u, affine)
+        assert np.abs(Fg - Fo).max() <= 1e-13 * np.abs(Fo).max()
+    assert abs(g.dt_explicit() - o.dt_explicit()) <= 1e-13 * o.dt_explicit()
