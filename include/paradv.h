@@ -127,7 +127,7 @@ enum {
 /* Per-advance statistics. */
 typedef struct {
     int32_t cycles, s_total, s_max, iters_total, iters_max;
-    int32_t fallbacks;        /* learned PC: Jacobi steps taken plus restarts as Jacobi PCG */
+    int32_t fallbacks;        /* learned PC: Jacobi steps taken plus hand-overs to Jacobi PCG */
     int32_t floored, status;
     int64_t k_first;          /* linear index of max |F| at the first limit evaluation */
     double dt_explicit;       /* explicit Euler limit used */
@@ -216,10 +216,12 @@ pa_status pa_advance_be_pcg(pa_ctx* ctx, double dt, double tol, int32_t cycles, 
  * and ReLU, on the matrix cores.  Because P is nonlinear the solve uses
  * flexible CG truncated to one previous direction (Notay, SIAM J. Sci.
  * Comput. 22 (2000)): beta = -<z, q_prev>/<p_prev, q_prev>, alpha =
- * <p, r>/<p, q>.  A step with <z, r> <= 0 takes z = r/D instead; less than
- * 10% reduction of ||r|| over 20 iterations restarts the solve as Jacobi
- * PCG from the current iterate.  Stopping rule and tolerance as
- * pa_advance_be_pcg.  Single-component FP64 contexts only.
+ * <p, r>/<p, q>.  A step with <z, r> <= 0 takes z = r/D instead.  The
+ * network's steps pay off while the error is dominated by local
+ * components; once ||r|| falls by less than 10x over 10 iterations the
+ * solve continues as Jacobi PCG from the current iterate.  Stopping rule
+ * and tolerance as pa_advance_be_pcg.  Single-component FP64 contexts
+ * only.
  *
  * Parameters: flat FP32 vector of PA_LPC_NPARAM values, in this order:
  * W1[16][8][3][3][3], b1[16], W2[16][16][3][3][3], b2[16], W3[1][16][3][3][3]
@@ -229,12 +231,10 @@ pa_status pa_advance_be_pcg(pa_ctx* ctx, double dt, double tol, int32_t cycles, 
 
 /* Training options (pa_lpc_default_train_opts fills defaults). */
 typedef struct {
-    int32_t npairs;      /* (residual, error) crops generated. default 2000 */
-    int32_t crop_r, crop_t, crop_p; /* crop size in cells (clipped to the grid). default 32 */
-    int32_t batch;       /* crops per Adam step. default 16 */
-    int32_t epochs;      /* passes over the crops. default 30 */
-    int32_t nsnap;       /* plain-PCG iterates sampled per solve. default 16 */
-    int32_t seed;        /* crop positions and batch order. default 4300 */
+    int32_t nsnap;       /* plain-PCG iterates kept as (residual, error) pairs. default 16 */
+    int32_t batch;       /* pairs per Adam step. default 2 */
+    int32_t epochs;      /* passes over the pairs. default 30 */
+    int32_t seed;        /* batch order. default 4300 */
     double lr;           /* Adam step (beta1 0.9, beta2 0.999, eps 1e-8). default 1e-3 */
     double tol_star;     /* tolerance of the reference solve x*. default 1e-12 */
 } pa_lpc_train_opts;
@@ -261,20 +261,21 @@ pa_status pa_lpc_features(pa_ctx* ctx, double dt, const double* r_dev, float* fe
 pa_status pa_lpc_apply(pa_ctx* ctx, double dt, const double* r_dev, double* z_dev);
 
 /* Training loss over npairs (r, e) pairs on the whole grid (device
- * double[npairs][nr][nt][np] each), mean over pairs of
- * |D^1/2 (P(r) - e)|^2 / |D^1/2 e|^2, and its gradient in the parameters
- * (host double *loss, host float grad[PA_LPC_NPARAM]).  periodic_phi = 0
- * evaluates the network with zero padding in phi (as on training crops). */
+ * double[npairs][nr][nt][np] each): the mean over pairs of the energy-norm
+ * error of the preconditioned residual, |P(r) - e|_M^2 / |e|_M^2 with
+ * M = V + dt L and |v|_M^2 = <v, M v> (the norm CG minimises), and its
+ * gradient in the parameters (host double *loss, host float
+ * grad[PA_LPC_NPARAM]).  npairs <= 64. */
 pa_status pa_lpc_loss_grad(pa_ctx* ctx, double dt, int32_t npairs, const double* r_dev,
-                           const double* e_dev, int32_t periodic_phi, double* loss, float* grad);
+                           const double* e_dev, double* loss, float* grad);
 
 /* Train the network on the system (V + dt L) x = V u + dt h of the bound
  * field: a Jacobi-PCG solve from x0 = u to tol_star gives x*; its iterates
- * x_k at nsnap iteration counts give pairs (r_k = b - M x_k, e_k = x* - x_k),
- * from which npairs crops are cut at seeded positions (c0 normalised by the
- * whole grid's sigma); Adam on the loss above over batches of crops, the
- * network zero-padded at crop faces.  The bound field is left unchanged.
- * report may be NULL. */
+ * x_k at up to nsnap iteration counts (0, 1, 2, 3, 4, 6, 9, 13, ...) give
+ * the pairs (r_k = b - M x_k, e_k = x* - x_k); Adam minimises the loss of
+ * pa_lpc_loss_grad over batches of pairs.  The bound field is left
+ * unchanged; on divergence the previous weights are restored
+ * (PA_ERR_NONFINITE).  report may be NULL. */
 pa_status pa_lpc_train(pa_ctx* ctx, double dt, const pa_lpc_train_opts* opts,
                        pa_lpc_report* report);
 

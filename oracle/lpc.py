@@ -15,7 +15,8 @@ reading of the task:
   c2..c7 = -M_{m,nb}/D_m for the six face neighbours (r-, r+, t-, t+, p-,
   p+; zero where the neighbour does not exist).  P is positively
   homogeneous: P(a r) = a P(r) for a > 0;
-* loss per (residual r, error e) pair: |D^1/2 (P(r) - e)|^2 / |D^1/2 e|^2;
+* loss per (residual r, error e) pair, in the energy norm of the system
+  matrix M that CG minimises: |P(r) - e|_M^2 / |e|_M^2;
 * flexible CG truncated to one previous direction (Notay 2000):
   beta = -<z, q_prev>/<p_prev, q_prev>, alpha = <p, r>/<p, q>.
 
@@ -213,8 +214,9 @@ def precondition(theta, r, D, static, bf16_mode=False):
     return zj + sigma * forward(theta, c, bf16_mode)
 
 
-def loss_and_grad(theta, pairs, D, static, bf16_mode=False, periodic=True):
-    """Mean over pairs (r, e) of |D^1/2 (P(r) - e)|^2 / |D^1/2 e|^2 and its
+def loss_and_grad(theta, pairs, D, static, matvec, bf16_mode=False):
+    """Mean over pairs (r, e) of the energy-norm loss
+    |P(r) - e|_M^2 / |e|_M^2 (|v|_M^2 = <v, M v>, matvec(v) = M v) and its
     gradient in theta (FP64; bf16_mode emulates the network's roundings)."""
     rd = bf16 if bf16_mode else (lambda v: v)
     L = 0.0
@@ -226,12 +228,14 @@ def loss_and_grad(theta, pairs, D, static, bf16_mode=False, periodic=True):
         c = np.concatenate([(zj / sigma)[None], static], axis=0)
         if bf16_mode:
             c = rd(c)
-        out, cache = forward(theta, c, bf16_mode, keep=True, periodic=periodic)
-        res = zj + sigma * out - e
-        den = np.sum(D * e * e)
-        L += np.sum(D * res * res) / den
-        gout = 2.0 * sigma * D * res / (den * n)
-        g += backward(theta, cache, gout, bf16_mode, periodic)
+        out, cache = forward(theta, c, bf16_mode, keep=True)
+        d = zj + sigma * out - e
+        Md = matvec(d)
+        den = np.vdot(e, matvec(e))
+        L += np.vdot(d, Md) / den
+        # d/d(out) of <d, M d> = 2 sigma M d (M symmetric)
+        gout = 2.0 * sigma * Md / (den * n)
+        g += backward(theta, cache, gout, bf16_mode)
     return L / n, g
 
 

@@ -1071,10 +1071,45 @@ void nn_precond(pa_ctx* c, const double* r, const int* done)
     nn_forward(c, 1, c->d.nr, c->d.nt, c->d.np, 1, done, c->nn_xs);
 }
 
+// M v for device v, Mv [N] (one component); per-tile partials of <v, M v>
+// into c->part; returns their count
+int nn_matvec(pa_ctx* c, double dt, const double* v, double* Mv)
+{
+    KArgs<double> a = base_args<double>(c, 0, c->d.nr);
+    a.u = v;
+    a.out = Mv;
+    a.affine = 0;
+    a.dt = dt;
+    stencil<double>(c, kMatvec, false, a);
+    return ntiles(c, c->d.nr);
+}
+
+// Energy-norm loss |P(r) - e|_M^2 / |e|_M^2 averaged over nb whole-grid
+// pairs and its gradient: inputs x [nb][N][8] and zj = r/D [nb][N] built,
+// e[b], sig[b] = RMS(r/D), den[b] = |e|_M^2 per pair.  The loss is added to
+// *lossacc (device) and the gradient to nn_grad; d, Md are [N] work arrays.
+void nn_energy_step(pa_ctx* c, double dt, int nb, const __bf16* x, const double* zj,
+                    const double* const* e, const double* const* sig, const double* const* den,
+                    double* d, double* Md, double* lossacc)
+{
+    const int nr = c->d.nr, nt = c->d.nt, np = c->d.np;
+    const size_t N = c->N;
+    hipStream_t S = c->stream;
+    nn_forward(c, nb, nr, nt, np, 1, nullptr, x);
+    for (int b = 0; b < nb; ++b) {
+        launch_nn_resid(N, zj + (size_t)b * N, c->nn_out + (size_t)b * N, sig[b], e[b], d, S);
+        const int mt = nn_matvec(c, dt, d, Md);
+        launch_scal_reduce(c->part, mt, den[b], 1.0 / nb, lossacc, S);
+        launch_energy_gout(N, Md, sig[b], den[b], 1.0 / nb, c->nn_g1 + (size_t)b * N, S);
+    }
+    nn_backward(c, nb, nr, nt, np, 1, x);
+}
+
 // FCG(1) with the learned preconditioner from the state queued by
-// launch_pcg_init (Dbuf, r0, b in nn_b) and launch_pcg_start; less than 10%
-// reduction of ||r|| over 20 iterations restarts as Jacobi PCG from the
-// current iterate.  *its: iterations; *fallbacks += Jacobi steps + restarts.
+// launch_pcg_init (Dbuf, r0, b in nn_b) and launch_pcg_start; less than a
+// 10x reduction of ||r|| over 10 iterations hands the solve over to Jacobi
+// PCG from the current iterate.  *its: iterations; *fallbacks += Jacobi
+// steps + hand-overs.
 pa_status fcg_solve(pa_ctx* c, double dtc, double tol, double* r, double* p, double* q, int* its,
                     int* fallbacks)
 {
@@ -1097,7 +1132,12 @@ pa_status fcg_solve(pa_ctx* c, double dtc, double tol, double* r, double* p, dou
     }
     pa_status s = sync_state(c);
     if (s) return s;
-    const int batch = 10, window = 20;
+    // hand-over rule: the network's steps pay off while they cut ||r|| by at
+    // least kGain over kWindow iterations (faster than Jacobi PCG's typical
+    // rate on stiff systems); after a slower window the solve continues as
+    // Jacobi PCG from the current iterate
+    constexpr int batch = 10, kWindow = 10;
+    constexpr double kGain = 10.0;
     int ref_it = 0;
     double ref_rr = c->hst->rr;
     bool restart = false;
@@ -1136,8 +1176,8 @@ pa_status fcg_solve(pa_ctx* c, double dtc, double tol, double* r, double* p, dou
         s = sync_state(c);
         if (s) return s;
         if (c->hst->done) break;
-        if (c->hst->iters - ref_it >= window) {
-            if (sqrt(c->hst->rr) > 0.9 * sqrt(ref_rr)) {
+        if (c->hst->iters - ref_it >= kWindow) {
+            if (kGain * sqrt(c->hst->rr) > sqrt(ref_rr)) {
                 restart = true;
                 break;
             }
@@ -1317,7 +1357,7 @@ pa_status pa_advance_be_pcg(pa_ctx* c, double dt, double tol, int32_t cycles, pa
 
 namespace {
 
-// splitmix64 (Steele, Lea & Flood, OOPSLA 2014): crop positions and batch order
+// splitmix64 (Steele, Lea & Flood, OOPSLA 2014): the training batch order
 struct SplitMix {
     uint64_t x;
     uint64_t next()
@@ -1368,11 +1408,9 @@ void pa_lpc_default_train_opts(pa_lpc_train_opts* o)
 {
     if (!o) return;
     memset(o, 0, sizeof *o);
-    o->npairs = 2000;
-    o->crop_r = o->crop_t = o->crop_p = 32;
-    o->batch = 16;
-    o->epochs = 30;
     o->nsnap = 16;
+    o->batch = 2;
+    o->epochs = 30;
     o->seed = 4300;
     o->lr = 1e-3;
     o->tol_star = 1e-12;
@@ -1438,45 +1476,43 @@ pa_status pa_lpc_apply(pa_ctx* c, double dt, const double* r, double* z)
 }
 
 pa_status pa_lpc_loss_grad(pa_ctx* c, double dt, int32_t npairs, const double* r, const double* e,
-                           int32_t periodic_phi, double* loss, float* grad)
+                           double* loss, float* grad)
 {
     if (!c) return PA_ERR_ARG;
     if (!r || !e || !loss || !grad) return fail(c, PA_ERR_ARG, "null array");
     if (npairs < 1 || npairs > kMaxPairs) return fail(c, PA_ERR_ARG, "npairs must be in [1, %d]", kMaxPairs);
     pa_status s = lpc_ready(c, dt, true);
     if (s) return s;
-    const int nr = c->d.nr, nt = c->d.nt, np = c->d.np;
     const size_t N = c->N, tot = N * (size_t)npairs;
-    const int per = periodic_phi ? 1 : 0;
+    hipStream_t S = c->stream;
     Temps tmp(c);
     __bf16* xb = tmp.get<__bf16>(8 * tot);
     double* zj = tmp.get<double>(tot);
-    double* eb = tmp.get<double>(tot);
-    double* Db = tmp.get<double>(tot);
-    double* sig = tmp.get<double>(npairs);
-    double* den = tmp.get<double>(npairs);
-    int* off = tmp.get<int>(3);
-    if (!xb || !zj || !eb || !Db || !sig || !den || !off || !nn_fwd_work(c, tot) || !nn_bwd_work(c, tot))
+    double* d = tmp.get<double>(N);
+    double* Md = tmp.get<double>(N);
+    double* sd = tmp.get<double>(2 * (size_t)npairs + 1);
+    if (!xb || !zj || !d || !Md || !sd || !nn_fwd_work(c, tot) || !nn_bwd_work(c, tot))
         return fail(c, PA_ERR_ALLOC, "learned preconditioner: out of device memory");
-    launch_fill_zero(off, 3 * sizeof(int), c->stream);
+    double* lossacc = sd + 2 * npairs;
+    std::vector<const double*> ep(npairs), sp(npairs), dp(npairs);
     nn_static(c, dt, true);
     for (int b = 0; b < npairs; ++b) {
-        launch_nn_sigma(N, r + b * N, c->Dbuf, nullptr, c->part, c->nn_scal + 2 + b, c->stream);
-        launch_pair_gather(nt, np, nr, nt, np, 1, off, b, 1, c->nn_xs, r + b * N, c->Dbuf, e + b * N,
-                           nullptr, c->nn_scal + 2 + b, xb, zj, eb, Db, sig, c->stream);
+        const double* rb = r + (size_t)b * N;
+        ep[b] = e + (size_t)b * N;
+        sp[b] = sd + b;
+        dp[b] = sd + npairs + b;
+        launch_nn_sigma(N, rb, c->Dbuf, nullptr, c->part, sd + b, S);
+        launch_pair_build(N, c->nn_xs, rb, c->Dbuf, sd + b, xb + 8 * (size_t)b * N, zj + (size_t)b * N, S);
+        const int mt = nn_matvec(c, dt, ep[b], Md);
+        launch_scal_reduce(c->part, mt, nullptr, 0.0, sd + npairs + b, S);
     }
-    launch_batch_scalars(npairs, N, zj, eb, Db, 0, nullptr, den, c->stream);
-    nn_forward(c, npairs, nr, nt, np, per, nullptr, xb);
-    const int nl = launch_nn_lossgrad(tot, N, zj, eb, Db, c->nn_out, sig, den, c->nn_g1, c->part,
-                                      c->stream);
-    launch_loss_finish(c->part, nl, 1.0 / npairs, c->nn_scal + 1, c->stream);
-    launch_fill_zero(c->nn_grad, sizeof(float) * NN_NPARAM, c->stream);
-    nn_backward(c, npairs, nr, nt, np, per, xb);
+    launch_fill_zero(lossacc, sizeof(double), S);
+    launch_fill_zero(c->nn_grad, sizeof(float) * NN_NPARAM, S);
+    nn_energy_step(c, dt, npairs, xb, zj, ep.data(), sp.data(), dp.data(), d, Md, lossacc);
     HIPCHK(c, hipGetLastError());
-    HIPCHK(c, hipMemcpyAsync(grad, c->nn_grad, sizeof(float) * NN_NPARAM, hipMemcpyDeviceToHost,
-                             c->stream));
-    HIPCHK(c, hipMemcpyAsync(loss, c->nn_scal + 1, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpyAsync(grad, c->nn_grad, sizeof(float) * NN_NPARAM, hipMemcpyDeviceToHost, S));
+    HIPCHK(c, hipMemcpyAsync(loss, lossacc, sizeof(double), hipMemcpyDeviceToHost, S));
+    HIPCHK(c, hipStreamSynchronize(S));
     c->err.clear();
     return PA_OK;
 }
@@ -1490,15 +1526,11 @@ pa_status pa_lpc_train(pa_ctx* c, double dt, const pa_lpc_train_opts* oin, pa_lp
     if (!c->u) return fail(c, PA_ERR_STATE, "no field bound");
     pa_status s = lpc_ready(c, dt, true);
     if (s) return s;
-    if (o.npairs < 1 || o.batch < 1 || o.batch > o.npairs || o.epochs < 1 || o.nsnap < 1 ||
-        o.crop_r < 1 || o.crop_t < 1 || o.crop_p < 1 || !(o.lr > 0.0) || !isfinite(o.lr) ||
+    if (o.nsnap < 1 || o.batch < 1 || o.epochs < 1 || !(o.lr > 0.0) || !isfinite(o.lr) ||
         !(o.tol_star >= 0.0) || !isfinite(o.tol_star))
         return fail(c, PA_ERR_ARG, "invalid training option");
-    const int nr = c->d.nr, nt = c->d.nt, np = c->d.np;
-    const int cr = std::min(o.crop_r, nr), ct = std::min(o.crop_t, nt), cp = std::min(o.crop_p, np);
-    const int per = cp == np ? 1 : 0;
-    const size_t N = c->N, Nc = (size_t)cr * ct * cp, ncrop = (size_t)o.npairs;
-    const size_t bpts = Nc * (size_t)o.batch;
+    const int nr = c->d.nr;
+    const size_t N = c->N;
     hipStream_t S = c->stream;
     pa_lpc_report R;
     memset(&R, 0, sizeof R);
@@ -1508,8 +1540,10 @@ pa_status pa_lpc_train(pa_ctx* c, double dt, const pa_lpc_train_opts* oin, pa_lp
     Temps tmp(c);
     double* bak = tmp.get<double>(N);
     double* xst = tmp.get<double>(N);
-    double* snap = tmp.get<double>(N * (size_t)o.nsnap);
-    if (!bak || !xst || !snap || !nn_fwd_work(c, bpts) || !nn_bwd_work(c, bpts))
+    double* snap = tmp.get<double>(N * (size_t)o.nsnap);   // iterates, then errors
+    double* res = tmp.get<double>(N * (size_t)o.nsnap);    // residuals
+    double* sd = tmp.get<double>(2 * (size_t)o.nsnap);     // sigma, |e|_M^2 per pair
+    if (!bak || !xst || !snap || !res || !sd)
         return fail(c, PA_ERR_ALLOC, "training: out of device memory");
     double* y0 = c->w[0];
     double* r = c->w[1];
@@ -1518,7 +1552,8 @@ pa_status pa_lpc_train(pa_ctx* c, double dt, const pa_lpc_train_opts* oin, pa_lp
     const Geo<double> g = geo(c, c->m64);
     const bool any_dir = c->d.bc_in == PA_BC_DIRICHLET || c->d.bc_out == PA_BC_DIRICHLET;
 
-    // reference solve x* by Jacobi PCG from x0 = u, keeping iterates x_k
+    // reference solve x* by Jacobi PCG from x0 = u, keeping iterates x_k at
+    // k = 0, 1, 2, 3, 4, 6, 9, 13, 19, ... (k <- max(k + 1, 3k/2))
     Timer t_pairs(S);
     launch_copy(c->u, bak, sizeof(double) * N, S);
     launch_fill_zero(c->flag, sizeof(int), S);
@@ -1553,71 +1588,55 @@ pa_status pa_lpc_train(pa_ctx* c, double dt, const pa_lpc_train_opts* oin, pa_lp
     if (pst == 6) return fail(c, PA_ERR_NONFINITE, "training: non-finite residual");
     if (taken == 0) return fail(c, PA_ERR_ARG, "training: the bound field already solves the system");
 
-    // crops: crop n belongs to snapshot n % taken; offsets grouped by snapshot
-    SplitMix rng{(uint64_t)(uint32_t)o.seed};
-    std::vector<int> offs(3 * ncrop);
-    std::vector<size_t> start(taken + 1, 0);
-    for (int j = 0; j < taken; ++j)
-        start[j + 1] = start[j] + (ncrop > (size_t)j ? (ncrop - j + taken - 1) / taken : 0);
-    for (size_t n = 0; n < ncrop; ++n) {
-        const int j = (int)(n % taken);
-        const size_t slot = start[j] + n / taken;
-        offs[3 * slot] = rng.below(nr - cr + 1);
-        offs[3 * slot + 1] = rng.below(nt - ct + 1);
-        offs[3 * slot + 2] = per ? 0 : rng.below(np);
+    // pairs: r_k = b - M x_k, e_k = x* - x_k, sigma_k, |e_k|_M^2
+    std::vector<const double*> ep(taken), sp(taken), dp(taken);
+    for (int k = 0; k < taken; ++k) {
+        double* xk = snap + (size_t)k * N;
+        double* rk = res + (size_t)k * N;
+        nn_matvec(c, dt, xk, q);
+        launch_pcg_resid<double>(N, 1, c->nn_b, q, c->Dbuf, rk, p, c->part, &nparts, S);
+        launch_sub(N, xst, xk, xk, S);
+        launch_nn_sigma(N, rk, c->Dbuf, nullptr, c->part, sd + k, S);
+        const int mt = nn_matvec(c, dt, xk, q);
+        launch_scal_reduce(c->part, mt, nullptr, 0.0, sd + taken + k, S);
+        ep[k] = xk;
+        sp[k] = sd + k;
+        dp[k] = sd + taken + k;
     }
-    __bf16* xc = tmp.get<__bf16>(8 * Nc * ncrop);
-    double* zjc = tmp.get<double>(Nc * ncrop);
-    double* ec = tmp.get<double>(Nc * ncrop);
-    double* Dc = tmp.get<double>(Nc * ncrop);
-    double* sigc = tmp.get<double>(ncrop);
-    double* denc = tmp.get<double>(ncrop);
-    int* doff = tmp.get<int>(3 * ncrop);
-    if (!xc || !zjc || !ec || !Dc || !sigc || !denc || !doff)
-        return fail(c, PA_ERR_ALLOC, "training: out of device memory for the crops");
-    HIPCHK(c, hipMemcpy(doff, offs.data(), sizeof(int) * 3 * ncrop, hipMemcpyHostToDevice));
     nn_static(c, dt, false);
-    for (int j = 0; j < taken; ++j) {
-        const int nj = (int)(start[j + 1] - start[j]);
-        if (nj == 0) continue;
-        const double* xk = snap + (size_t)j * N;
-        KArgs<double> a = base_args<double>(c, 0, nr);
-        a.u = xk;
-        a.out = q;
-        a.affine = 0;
-        a.dt = dt;
-        stencil<double>(c, kMatvec, false, a);
-        launch_pcg_resid<double>(N, 1, c->nn_b, q, c->Dbuf, r, p, c->part, &nparts, S);
-        launch_nn_sigma(N, r, c->Dbuf, nullptr, c->part, c->nn_scal, S);
-        launch_pair_gather(nt, np, cr, ct, cp, nj, doff + 3 * start[j], j, taken, c->nn_xs, r,
-                           c->Dbuf, xst, xk, c->nn_scal, xc, zjc, ec, Dc, sigc, S);
-    }
-    launch_batch_scalars((int)ncrop, Nc, zjc, ec, Dc, 0, nullptr, denc, S);
     HIPCHK(c, hipGetLastError());
     R.ms_pairs = t_pairs.stop();
-    R.pairs = (int)ncrop;
-    R.snapshots = taken;
+    R.pairs = R.snapshots = taken;
 
-    // Adam over batches of crops
-    Timer t_train(S);
-    const int nbatch = (int)(ncrop / o.batch);
+    // Adam over batches of pairs, order shuffled every epoch
+    const int B = std::min(o.batch, taken);
+    const int nbatch = taken / B;
     const int steps = nbatch * o.epochs;
+    __bf16* xb = tmp.get<__bf16>(8 * N * (size_t)B);
+    double* zjb = tmp.get<double>(N * (size_t)B);
     double* lossv = tmp.get<double>(steps);
-    if (!lossv) return fail(c, PA_ERR_ALLOC, "training: out of device memory");
-    std::vector<int> perm(nbatch);
-    for (int i = 0; i < nbatch; ++i) perm[i] = i;
+    if (!xb || !zjb || !lossv || !nn_fwd_work(c, N * B) || !nn_bwd_work(c, N * B))
+        return fail(c, PA_ERR_ALLOC, "training: out of device memory");
+    launch_fill_zero(lossv, sizeof(double) * steps, S);
+    Timer t_train(S);
+    SplitMix rng{(uint64_t)(uint32_t)o.seed};
+    std::vector<int> perm(taken);
+    for (int i = 0; i < taken; ++i) perm[i] = i;
+    std::vector<const double*> be(B), bs(B), bd(B);
     int step = 0;
-    for (int ep = 0; ep < o.epochs; ++ep) {
-        for (int i = nbatch - 1; i > 0; --i) std::swap(perm[i], perm[rng.below(i + 1)]);
+    for (int ep_i = 0; ep_i < o.epochs; ++ep_i) {
+        for (int i = taken - 1; i > 0; --i) std::swap(perm[i], perm[rng.below(i + 1)]);
         for (int bi = 0; bi < nbatch; ++bi) {
-            const size_t el = (size_t)perm[bi] * o.batch;
-            const __bf16* x = xc + el * Nc * 8;
+            for (int b = 0; b < B; ++b) {
+                const int k = perm[bi * B + b];
+                launch_pair_build(N, c->nn_xs, res + (size_t)k * N, c->Dbuf, sp[k],
+                                  xb + 8 * (size_t)b * N, zjb + (size_t)b * N, S);
+                be[b] = ep[k];
+                bs[b] = sp[k];
+                bd[b] = dp[k];
+            }
             launch_fill_zero(c->nn_grad, sizeof(float) * NN_NPARAM, S);
-            nn_forward(c, o.batch, cr, ct, cp, per, nullptr, x);
-            const int nl = launch_nn_lossgrad(bpts, Nc, zjc + el * Nc, ec + el * Nc, Dc + el * Nc,
-                                              c->nn_out, sigc + el, denc + el, c->nn_g1, c->part, S);
-            launch_loss_finish(c->part, nl, 1.0 / o.batch, lossv + step, S);
-            nn_backward(c, o.batch, cr, ct, cp, per, x);
+            nn_energy_step(c, dt, B, xb, zjb, be.data(), bs.data(), bd.data(), p, q, lossv + step);
             launch_nn_adam(c->nn_th, c->nn_grad, c->nn_m, c->nn_v, (float)o.lr, ++c->nn_adam_t, S);
             launch_nn_prep_weights(c->nn_th, c->nn_w, S);
             ++step;

@@ -153,16 +153,16 @@ void launch_nn_static(const Geo<double>& g, double dt, const double* D, const do
                       __bf16* x, hipStream_t s);
 void launch_nn_c0(size_t N, const double* r, const double* D, const double* sigma, const int* done,
                   __bf16* x, hipStream_t s);
-int launch_nn_lossgrad(size_t N, size_t nc, const double* zj, const double* e, const double* D,
-                       const float* out, const double* sigma, const double* den, __bf16* gout,
-                       double* part, hipStream_t s);
-void launch_batch_scalars(int nb, size_t nc, const double* zj, const double* e, const double* D,
-                          int want_sig, double* sig, double* den, hipStream_t s);
-void launch_pair_gather(int nt, int np, int cr, int ct, int cp, int ncrop, const int* off, int b0,
-                        int bs, const __bf16* xs, const double* r, const double* D,
-                        const double* xstar, const double* xk, const double* sig, __bf16* x,
-                        double* zj, double* e, double* Dw, double* sigo, hipStream_t s);
-void launch_loss_finish(const double* part, int n, double scale, double* out, hipStream_t s);
+// energy-norm training loss |P(r) - e|_M^2 / |e|_M^2 pieces
+void launch_pair_build(size_t N, const __bf16* xs, const double* r, const double* D,
+                       const double* sig, __bf16* x, double* zj, hipStream_t s);
+void launch_nn_resid(size_t N, const double* zj, const float* out, const double* sig,
+                     const double* e, double* d, hipStream_t s);
+void launch_energy_gout(size_t N, const double* Md, const double* sig, const double* den,
+                        double scale, __bf16* gout, hipStream_t s);
+void launch_scal_reduce(const double* part, int n, const double* den, double scale, double* out,
+                        hipStream_t s);
+void launch_sub(size_t N, const double* a, const double* b, double* out, hipStream_t s);
 void launch_jacobi_D(const Geo<double>& g, double dt, const double* dL, double* D, hipStream_t s);
 void launch_nn_unpack(size_t N, const __bf16* x, float* f, hipStream_t s);
 void launch_nn_apply(size_t N, const double* r, const double* D, const float* out,

@@ -367,131 +367,66 @@ void launch_jacobi_D(const Geo<double>& g, double dt, const double* dL, double* 
                        dim3(256), 0, s, g, dt, dL, D);
 }
 
-// Batch of nb (r, e) pairs of nc cells each, pair b = m / nc:
-// res = zj + sigma_b out - e (zj = r/D); partials of sum_m D res^2 / den_b;
-// gout[m] = 2 sigma_b D res / (den_b * nb).
-__global__ __launch_bounds__(256) void k_nn_lossgrad(unsigned N, unsigned nc, const double* zj,
-                                                     const double* e, const double* D,
-                                                     const float* out, const double* sig,
-                                                     const double* den, __bf16* gout,
-                                                     double* part)
+// Network input of one pair on the whole grid: x[.][0] = bf16((r/D)/sigma),
+// x[.][1..7] = xs[.][1..7] (static channels), zj = r/D
+__global__ void k_pair_build(unsigned N, const __bf16* xs, const double* r, const double* D,
+                             const double* sig, __bf16* x, double* zj)
 {
-    __shared__ double lds[4];
-    const double inv_nb = 1.0 / (double)(N / nc);
-    double acc = 0.0;
-    for (unsigned m = blockIdx.x * blockDim.x + threadIdx.x; m < N; m += gridDim.x * blockDim.x) {
-        const unsigned b = m / nc;
-        const double s = sig[b], inv = den[b] > 0.0 ? 1.0 / den[b] : 0.0;
-        const double d = D[m];
-        const double res = zj[m] + s * (double)out[m] - e[m];
-        acc += d * res * res * inv;
-        gout[m] = (__bf16)(float)(2.0 * s * d * res * inv * inv_nb);
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) part[blockIdx.x] = lds[0] + lds[1] + lds[2] + lds[3];
-}
-
-int launch_nn_lossgrad(size_t N, size_t nc, const double* zj, const double* e, const double* D,
-                       const float* out, const double* sigma, const double* den, __bf16* gout,
-                       double* part, hipStream_t s)
-{
-    const int nb = (int)((N + 255) / 256 > 1024 ? 1024 : (N + 255) / 256);
-    hipLaunchKernelGGL(k_nn_lossgrad, dim3(nb), dim3(256), 0, s, (unsigned)N, (unsigned)nc, zj, e, D,
-                       out, sigma, den, gout, part);
-    return nb;
-}
-
-// Per pair b of a batch: sig[b] = sqrt(mean zj^2) when want_sig, den[b] =
-// sum D e^2 (one workgroup per pair, fixed summation order)
-__global__ __launch_bounds__(1024) void k_batch_scalars(unsigned nc, const double* zj,
-                                                        const double* e, const double* D,
-                                                        int want_sig, double* sig, double* den)
-{
-    __shared__ double lds[2][16];
-    const size_t base = (size_t)blockIdx.x * nc;
-    double a0 = 0.0, a1 = 0.0;
-    for (unsigned m = threadIdx.x; m < nc; m += blockDim.x) {
-        const double z = zj[base + m], ev = e[base + m];
-        a0 += z * z;
-        a1 += D[base + m] * ev * ev;
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        a0 += __shfl_xor(a0, o, 64);
-        a1 += __shfl_xor(a1, o, 64);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        lds[0][threadIdx.x >> 6] = a0;
-        lds[1][threadIdx.x >> 6] = a1;
-    }
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    double s0 = 0.0, s1 = 0.0;
-    for (int w = 0; w < 16; ++w) {
-        s0 += lds[0][w];
-        s1 += lds[1][w];
-    }
-    if (want_sig) sig[blockIdx.x] = sqrt(s0 / (double)nc);
-    den[blockIdx.x] = s1;
-}
-
-void launch_batch_scalars(int nb, size_t nc, const double* zj, const double* e, const double* D,
-                          int want_sig, double* sig, double* den, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_batch_scalars, dim3(nb), dim3(1024), 0, s, (unsigned)nc, zj, e, D, want_sig,
-                       sig, den);
-}
-
-// Pair inputs from full-grid data: x[.][0] = bf16((r/D)/sigma), x[.][1..7] =
-// xs[.][1..7], zj = r/D, e = xstar - xk (xstar when xk is null), Dw = D,
-// sigo[element] = sigma.  Crop b of this launch (offsets off[b] = (i0, j0,
-// k0), dims cr x ct x cp) is the sub-box i0..i0+cr-1, j0..j0+ct-1,
-// (k0 + k) mod np, written as batch element b0 + b*bs.
-__global__ void k_pair_gather(int nt, int np, int cr, int ct, int cp, const int* off, int b0, int bs,
-                              const __bf16* xs, const double* r, const double* D,
-                              const double* xstar, const double* xk, const double* sig,
-                              __bf16* x, double* zj, double* e, double* Dw, double* sigo)
-{
-    const unsigned nc = (unsigned)cr * ct * cp;
-    const int b = blockIdx.y;
-    const int i0 = off[3 * b], j0 = off[3 * b + 1], k0 = off[3 * b + 2];
     const double s = *sig;
     const double inv = s > 0.0 ? 1.0 / s : 0.0;
-    const size_t el = (size_t)b0 + (size_t)b * bs;
-    if (blockIdx.x == 0 && threadIdx.x == 0) sigo[el] = s;
-    for (unsigned m = blockIdx.x * blockDim.x + threadIdx.x; m < nc; m += gridDim.x * blockDim.x) {
-        const int k = (int)(m % cp), j = (int)((m / cp) % ct), i = (int)(m / ((unsigned)cp * ct));
-        int kk = k0 + k;
-        if (kk >= np) kk -= np;
-        const size_t src = ((size_t)(i0 + i) * nt + (j0 + j)) * np + kk;
-        const size_t dst = el * nc + m;
-        const double z = r[src] / D[src];
-        zj[dst] = z;
-        e[dst] = xk ? xstar[src] - xk[src] : xstar[src];
-        Dw[dst] = D[src];
-        x[dst * 8] = (__bf16)(float)(z * inv);
+    for (unsigned m = blockIdx.x * blockDim.x + threadIdx.x; m < N; m += gridDim.x * blockDim.x) {
+        const double z = r[m] / D[m];
+        zj[m] = z;
+        x[(size_t)m * 8] = (__bf16)(float)(z * inv);
 #pragma unroll
-        for (int c = 1; c < 8; ++c) x[dst * 8 + c] = xs[src * 8 + c];
+        for (int c = 1; c < 8; ++c) x[(size_t)m * 8 + c] = xs[(size_t)m * 8 + c];
     }
 }
 
-void launch_pair_gather(int nt, int np, int cr, int ct, int cp, int ncrop, const int* off, int b0,
-                        int bs, const __bf16* xs, const double* r, const double* D,
-                        const double* xstar, const double* xk, const double* sig, __bf16* x,
-                        double* zj, double* e, double* Dw, double* sigo, hipStream_t s)
+void launch_pair_build(size_t N, const __bf16* xs, const double* r, const double* D,
+                       const double* sig, __bf16* x, double* zj, hipStream_t s)
 {
-    const size_t nc = (size_t)cr * ct * cp;
-    unsigned gx = (unsigned)((nc + 255) / 256);
-    if (gx > 1024) gx = 1024;
-    hipLaunchKernelGGL(k_pair_gather, dim3(gx, (unsigned)ncrop), dim3(256), 0, s, nt, np, cr, ct, cp,
-                       off, b0, bs, xs, r, D, xstar, xk, sig, x, zj, e, Dw, sigo);
+    hipLaunchKernelGGL(k_pair_build, dim3((unsigned)((N + 255) / 256 > 4096 ? 4096 : (N + 255) / 256)),
+                       dim3(256), 0, s, (unsigned)N, xs, r, D, sig, x, zj);
 }
 
-// Sum of the loss partials (times 1/nb) into *out
-__global__ void k_loss_finish(const double* part, int n, double scale, double* out)
+// d = zj + sigma out - e: the error of the preconditioned residual
+__global__ void k_nn_resid(unsigned N, const double* zj, const float* out, const double* sig,
+                           const double* e, double* d)
+{
+    const double s = *sig;
+    for (unsigned m = blockIdx.x * blockDim.x + threadIdx.x; m < N; m += gridDim.x * blockDim.x)
+        d[m] = zj[m] + s * (double)out[m] - e[m];
+}
+
+void launch_nn_resid(size_t N, const double* zj, const float* out, const double* sig,
+                     const double* e, double* d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_nn_resid, dim3((unsigned)((N + 255) / 256 > 4096 ? 4096 : (N + 255) / 256)),
+                       dim3(256), 0, s, (unsigned)N, zj, out, sig, e, d);
+}
+
+// gout = 2 sigma (M d) scale / den, the output gradient of
+// scale * <d, M d> / den (M symmetric)
+__global__ void k_energy_gout(unsigned N, const double* Md, const double* sig, const double* den,
+                              double scale, __bf16* gout)
+{
+    const double f = 2.0 * (*sig) * scale / (*den);
+    for (unsigned m = blockIdx.x * blockDim.x + threadIdx.x; m < N; m += gridDim.x * blockDim.x)
+        gout[m] = (__bf16)(float)(f * Md[m]);
+}
+
+void launch_energy_gout(size_t N, const double* Md, const double* sig, const double* den,
+                        double scale, __bf16* gout, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_energy_gout, dim3((unsigned)((N + 255) / 256 > 4096 ? 4096 : (N + 255) / 256)),
+                       dim3(256), 0, s, (unsigned)N, Md, sig, den, scale, gout);
+}
+
+// t = sum of n partials (fixed order); *out = t when den is null, else
+// *out += t * scale / *den
+__global__ void k_scal_reduce(const double* part, int n, const double* den, double scale,
+                              double* out)
 {
     __shared__ double lds[16];
     double v = 0.0;
@@ -500,16 +435,30 @@ __global__ void k_loss_finish(const double* part, int n, double scale, double* o
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += lds[w];
-        *out = t * scale;
-    }
+    if (threadIdx.x != 0) return;
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += lds[w];
+    if (den) *out += t * scale / *den;
+    else *out = t;
 }
 
-void launch_loss_finish(const double* part, int n, double scale, double* out, hipStream_t s)
+void launch_scal_reduce(const double* part, int n, const double* den, double scale, double* out,
+                        hipStream_t s)
 {
-    hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(1024), 0, s, part, n, scale, out);
+    hipLaunchKernelGGL(k_scal_reduce, dim3(1), dim3(1024), 0, s, part, n, den, scale, out);
+}
+
+// out = a - b
+__global__ void k_sub(unsigned N, const double* a, const double* b, double* out)
+{
+    for (unsigned m = blockIdx.x * blockDim.x + threadIdx.x; m < N; m += gridDim.x * blockDim.x)
+        out[m] = a[m] - b[m];
+}
+
+void launch_sub(size_t N, const double* a, const double* b, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sub, dim3((unsigned)((N + 255) / 256 > 4096 ? 4096 : (N + 255) / 256)),
+                       dim3(256), 0, s, (unsigned)N, a, b, out);
 }
 
 // FP32 [N][8] BF16 features -> FP32 [8][N] (for parity checks)

@@ -79,10 +79,8 @@ class pa_stats(ctypes.Structure):
 
 
 class pa_lpc_train_opts(ctypes.Structure):
-    _fields_ = [("npairs", ctypes.c_int32), ("crop_r", ctypes.c_int32),
-                ("crop_t", ctypes.c_int32), ("crop_p", ctypes.c_int32),
-                ("batch", ctypes.c_int32), ("epochs", ctypes.c_int32),
-                ("nsnap", ctypes.c_int32), ("seed", ctypes.c_int32),
+    _fields_ = [("nsnap", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("epochs", ctypes.c_int32), ("seed", ctypes.c_int32),
                 ("lr", ctypes.c_double), ("tol_star", ctypes.c_double)]
 
 
@@ -128,7 +126,7 @@ def load(path: str = LIB_PATH):
         "pa_lpc_get_weights": (I32, [V, V]),
         "pa_lpc_features": (I32, [V, D, V, V]),
         "pa_lpc_apply": (I32, [V, D, V, V]),
-        "pa_lpc_loss_grad": (I32, [V, D, I32, V, V, I32, P(D), V]),
+        "pa_lpc_loss_grad": (I32, [V, D, I32, V, V, P(D), V]),
         "pa_lpc_train": (I32, [V, D, P(pa_lpc_train_opts), P(pa_lpc_report)]),
     }
     for name, (res, args) in sig.items():
@@ -230,10 +228,10 @@ def pa_lpc_apply(ctx, dt, r_ptr, z_ptr):
     return load().pa_lpc_apply(ctx, dt, r_ptr, z_ptr)
 
 
-def pa_lpc_loss_grad(ctx, dt, npairs, r_ptr, e_ptr, periodic_phi, grad_host_ptr):
+def pa_lpc_loss_grad(ctx, dt, npairs, r_ptr, e_ptr, grad_host_ptr):
     loss = ctypes.c_double()
-    st = load().pa_lpc_loss_grad(ctx, dt, npairs, r_ptr, e_ptr, int(periodic_phi),
-                                 ctypes.byref(loss), grad_host_ptr)
+    st = load().pa_lpc_loss_grad(ctx, dt, npairs, r_ptr, e_ptr, ctypes.byref(loss),
+                                 grad_host_ptr)
     return st, loss.value
 
 
@@ -451,12 +449,12 @@ class Operator:
         self._check(pa_lpc_apply(self.ctx, float(dt), self._p(r), self._p(z)))
         return z
 
-    def lpc_loss_grad(self, dt, r, e, periodic_phi=True):
+    def lpc_loss_grad(self, dt, r, e):
         r = self._dev(r).reshape(-1, self.nr, self.nt, self.np).contiguous()
         e = self._dev(e).reshape(r.shape).contiguous()
         g = np.empty(PA_LPC_NPARAM, dtype=np.float32)
         st, loss = pa_lpc_loss_grad(self.ctx, float(dt), r.shape[0], self._p(r), self._p(e),
-                                    periodic_phi, g.ctypes.data_as(ctypes.c_void_p))
+                                    g.ctypes.data_as(ctypes.c_void_p))
         self._check(st)
         return loss, g
 
