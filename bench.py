@@ -86,6 +86,35 @@ def run_cpu_baseline(cond, budget_s=30.0):
                       f"field-aligned conduction advance; {t:.1f} s on the host"}
 
 
+# committed counter summaries: roofline kernel -> (summary, source file of the kernel)
+TRAFFIC_PROFILES = {
+    "be_viscosity/update": ("profiles/k_pcg_update_viscosity_151x301x400.md",
+                            "paper_2403_01004_amd/csrc/pa_vec.hip"),
+}
+
+
+def measured_traffic(kernel, shape):
+    """HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE summary of this
+    kernel and workload, or None when there is none or the kernel's source
+    changed since the counters were taken."""
+    import hashlib
+    import re
+    ent = TRAFFIC_PROFILES.get(kernel)
+    if ent is None or tuple(shape) != (151, 301, 400):
+        return None
+    prof, src = (os.path.join(ROOT, x) for x in ent)
+    try:
+        txt = open(prof).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m = re.search(r"traffic_bytes_per_launch: (\d+)", txt)
+    h = re.search(r"kernel_source_sha256 \([^)]*\): ([0-9a-f]+)", txt)
+    if not m or not h or h.group(1) != sha:
+        return None
+    return int(m.group(1))
+
+
 def rel_l2(a, b):
     import torch
     return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
@@ -326,7 +355,8 @@ def main():
         "s_per_advance": {k: round(v["s"], 4) for k, v in adv.items()},
         "advances": adv,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(f"{dname}/{dcls}", (nr, nt, np_)),
                      "kernel": f"{dname}/{dcls}", "avg_launch_us": round(1e3 * avg_ms, 2),
                      "bytes_per_launch": int(dbytes / dcalls)},
         "kernels": kernels,
