@@ -161,9 +161,9 @@ bool ensure_parts(pa_ctx* c, size_t n)
 // radial levels per workgroup: enough workgroups to fill 256 CUs several
 // times over, without making each chunk so short that the two halo levels
 // dominate
-int pick_rch(int nr, int nt, int np)
+int pick_rch(int op, int nr, int nt, int np)
 {
-    const int nbx = tiles_per_plane(nt, np);
+    const int nbx = blocks_per_plane(op, nt, np);
     int rch = 32;
     while (rch > 4 && (long long)nbx * ((nr + rch - 1) / rch) < 2048) rch /= 2;
     return rch;
@@ -180,7 +180,7 @@ KArgs<T> base_args(pa_ctx* c, int r_lo, int r_hi)
     a.r_lo = r_lo;
     a.r_hi = r_hi;
     a.rch = c->rch;
-    a.nbx = tiles_per_plane(c->d.nt, c->d.np);
+    a.nbx = blocks_per_plane(c->d.op, c->d.nt, c->d.np);
     a.nrc = (r_hi - r_lo + c->rch - 1) / c->rch;
     a.nc = c->d.ncomp;
     a.km2 = kKm2Array;
@@ -218,7 +218,7 @@ void stencil(pa_ctx* c, int mode, bool virt, const KArgs<T>& a)
 
 int ntiles(pa_ctx* c, int nlev)
 {
-    return stencil_tiles(c->d.nt, c->d.np, nlev, c->rch, c->d.ncomp);
+    return stencil_tiles(c->d.op, c->d.nt, c->d.np, nlev, c->rch, c->d.ncomp);
 }
 
 hipEvent_t get_event(pa_ctx* c)
@@ -468,7 +468,7 @@ pa_status pa_init(const pa_desc* d, void* stream, pa_ctx** out)
     c->NT = c->N * d->ncomp;
     c->NCO = (size_t)(nr + 1) * (nt + 1) * np;
     c->fp32 = d->prec == PA_FP32_STAGES;
-    c->rch = pick_rch(nr, nt, np);
+    c->rch = pick_rch(d->op, nr, nt, np);
 
     // 1-D metric factors (finite volume on the face mesh)
     std::vector<double> rc(nr), tc(nt), pc(np);
@@ -547,7 +547,7 @@ pa_status pa_init(const pa_desc* d, void* stream, pa_ctx** out)
             ok = ok && c->f[q];
         }
     }
-    const size_t tiles = (size_t)stencil_tiles(nt, np, nr, c->rch, d->ncomp);
+    const size_t tiles = (size_t)stencil_tiles(d->op, nt, np, nr, c->rch, d->ncomp);
     const size_t nblk = (N + kBlock - 1) / kBlock;
     ok = ok && ensure_parts(c, tiles > nblk ? (tiles > 4096 ? tiles : 4096) : (nblk > 4096 ? nblk : 4096));
     c->st = (DevState*)dev_alloc(c, sizeof(DevState));

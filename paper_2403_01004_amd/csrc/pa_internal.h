@@ -69,10 +69,11 @@ void launch_iso7(int mode, bool virt, const Geo<T>& g, const KArgs<T>& a, hipStr
 template <class T>
 void launch_aligned(int mode, bool virt, const Geo<T>& g, const KArgs<T>& a, hipStream_t s);
 
-// tiles of one radial level, and logical tiles of a stencil launch over
-// nlev levels (== entries of a.part)
-int tiles_per_plane(int nt, int np);
-int stencil_tiles(int nt, int np, int nlev, int rch, int nc);
+// workgroups covering one radial level (op: 0 7-point, 1 field-aligned),
+// and logical workgroups of a stencil launch over nlev levels (== entries
+// of a.part)
+int blocks_per_plane(int op, int nt, int np);
+int stencil_tiles(int op, int nt, int np, int nlev, int rch, int nc);
 
 // setup kernels
 void launch_coef(const double* T0, double scale, double expo, int n, double* c64, float* c32,

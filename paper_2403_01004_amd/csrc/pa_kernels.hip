@@ -47,10 +47,17 @@ static inline int grid_for_tiles(int ntiles) { return ((ntiles + 7) / 8) * 8; }
 
 int tiles_per_plane(int nt, int np) { return ((np + TX - 1) / TX) * ((nt + TY - 1) / TY); }
 
-int stencil_tiles(int nt, int np, int nlev, int rch, int nc)
+int iso7_blocks_per_plane(int nt, int np);
+
+int blocks_per_plane(int op, int nt, int np)
+{
+    return op == 0 ? iso7_blocks_per_plane(nt, np) : tiles_per_plane(nt, np);
+}
+
+int stencil_tiles(int op, int nt, int np, int nlev, int rch, int nc)
 {
     const int nrc = (nlev + rch - 1) / rch;
-    return tiles_per_plane(nt, np) * nrc * nc;
+    return blocks_per_plane(op, nt, np) * nrc * nc;
 }
 
 // ------------------------------------------------------------ reductions
@@ -233,127 +240,184 @@ __device__ __forceinline__ T ldu(const KArgs<T>& a, const T* u, const T* y, size
 }
 
 // ------------------------------------------------------------ 7-point
+//
+// Wave rows: each wave owns 64 consecutive cells of a radial level (phi
+// fastest, rows of theta following) and marches them over a chunk of
+// levels; the four in-plane neighbours are read straight from the caches
+// (neighbouring waves load them as their own cells), the radial neighbours
+// come from a register ring filled two levels ahead.  No LDS and no
+// barriers in the march, so every wave streams independently.  With a
+// variable coefficient (CV) the ring also carries the coefficient at the
+// five in-plane points.
 
-// one radial level's loads of a thread (own cell, halo slot, coefficients,
-// stage streams of the own cell)
-template <class T>
-struct Lev7 {
-    T u, h, c, ch;
-    Streams<T> s;
-};
+constexpr int W7 = 4;        // waves per workgroup
+constexpr int RCH_MAX = 32;  // radial levels per workgroup (at most)
 
-template <class T, int MODE, bool VIRT>
-__device__ __forceinline__ void fetch7(const KArgs<T>& a, const T* u, const T* y, const T* cf,
-                                       const TileMap& tm, size_t cb, int P, int lv, bool plane,
-                                       Lev7<T>& R)
+int iso7_blocks_per_plane(int nt, int np)
 {
-    const size_t lb = (size_t)lv * P;
-    R.u = ldu<T, VIRT>(a, u, y, lb + tm.own_off);
-    if (cf) R.c = cf[lb + tm.own_off];
-    if (plane) {
-        if (tm.has_h) {
-            R.h = ldu<T, VIRT>(a, u, y, lb + tm.h_off);
-            if (cf) R.ch = cf[lb + tm.h_off];
-        }
-        load_streams<T, MODE>(a, cb + lb + tm.own_off, R.s);
-    }
+    const int nseg = (nt * np + 63) / 64;
+    return (nseg + W7 - 1) / W7;
 }
 
-template <class T, int MODE, bool VIRT>
-__global__ __launch_bounds__(kBlock) void k_iso7(Geo<T> g, KArgs<T> a)
+template <class T, bool CV, int MODE>
+struct Lev7 {
+    T x, w, e, s, n;                  // u at own, phi-, phi+, theta-, theta+
+    T cx, cw, ce, cs, cn;             // coefficient at the same points (CV)
+    Streams<T> st;                    // stage streams of the own cell
+};
+
+template <class T, bool CV, int MODE, bool VIRT>
+__device__ __forceinline__ void fetch7(const KArgs<T>& a, const T* u, const T* y, size_t lb,
+                                       unsigned pp, unsigned ow, unsigned oe, unsigned os,
+                                       unsigned on, size_t sb, Lev7<T, CV, MODE>& R)
 {
-    __shared__ T su[2][HN];
-    __shared__ T sc[2][HN];
+    R.x = ldu<T, VIRT>(a, u, y, lb + pp);
+    R.w = ldu<T, VIRT>(a, u, y, lb + ow);
+    R.e = ldu<T, VIRT>(a, u, y, lb + oe);
+    R.s = ldu<T, VIRT>(a, u, y, lb + os);
+    R.n = ldu<T, VIRT>(a, u, y, lb + on);
+    if constexpr (CV) {
+        R.cx = a.coef[lb + pp];
+        R.cw = a.coef[lb + ow];
+        R.ce = a.coef[lb + oe];
+        R.cs = a.coef[lb + os];
+        R.cn = a.coef[lb + on];
+    }
+    load_streams<T, MODE>(a, sb, R.st);
+}
+
+// per-thread constants of the 7-point march
+template <class T>
+struct Pt7 {
+    unsigned pp, ow, oe, os, on;
+    bool valid;
+    T Ar, As, An, Aw, Ae;   // vt vp, gtt vp (theta- / theta+), gpt gpp (phi- / phi+)
+    T ubl, ubu;             // mirror data below level 0 / above level nr-1
+    T fin, fout;            // 1 for a Dirichlet face at r_in / r_out, else 0
+};
+
+// One level i of the march: issue the loads of level i + 2 into Rp
+// (clamped to the mesh and the chunk; values of levels past the chunk are
+// never used), then combine level i from Rc (own and in-plane values) and
+// Rn (the level above).  Levels at or past i1 are computed but not stored:
+// the body has no data-dependent branches, and with the ring's roles
+// rotating between calls no register copy waits on a load in flight.
+template <class T, int MODE, bool VIRT, bool CV>
+__device__ __forceinline__ void step7(const Geo<T>& g, const KArgs<T>& a, const T* u, const T* y,
+                                      size_t cb, const Pt7<T>& t, int i, int i0, int i1,
+                                      const T* lgr, const T* lgtr, const T* lvr,
+                                      const Lev7<T, CV, MODE>& Rc, const Lev7<T, CV, MODE>& Rn,
+                                      Lev7<T, CV, MODE>& Rp, T& um, T& cm, Acc<T, MODE>& acc)
+{
+    const int nr = g.nr;
+    const size_t P = (size_t)g.P;
+    {
+        const int lv = min(i + 2, nr - 1), ls = min(i + 2, i1 - 1);
+        fetch7<T, CV, MODE, VIRT>(a, u, y, (size_t)lv * P, t.pp, t.ow, t.oe, t.os, t.on,
+                                  cb + (size_t)ls * P + t.pp, Rp);
+    }
+    const int ic = min(i, nr - 1);
+    const T half = T(0.5);
+    const T uc = Rc.x;
+    const T cc = CV ? Rc.cx : a.cs;
+    const T cs_ = CV ? Rc.cs : a.cs, cn = CV ? Rc.cn : a.cs;
+    const T cw = CV ? Rc.cw : a.cs, ce = CV ? Rc.ce : a.cs;
+    const T cu = CV ? Rn.cx : a.cs;
+    const int il = ic - i0;
+    const T gtri = lgtr[il];
+    const bool lo = ic > 0, hi = ic < nr - 1;
+    const T Cl = lo ? half * (cc + cm) * (lgr[il] * t.Ar) : t.fin * cc * (lgr[il] * t.Ar);
+    const T ul = lo ? um : t.ubl;
+    const T Cu = hi ? half * (cc + cu) * (lgr[il + 1] * t.Ar) : t.fout * cc * (lgr[il + 1] * t.Ar);
+    const T uu = hi ? Rn.x : t.ubu;
+    T Lu = Cl * (uc - ul);
+    Lu += Cu * (uc - uu);
+    Lu += half * (cc + cs_) * (gtri * t.As) * (uc - Rc.s);
+    Lu += half * (cc + cn) * (gtri * t.An) * (uc - Rc.n);
+    Lu += half * (cc + cw) * (gtri * t.Aw) * (uc - Rc.w);
+    Lu += half * (cc + ce) * (gtri * t.Ae) * (uc - Rc.e);
+    const T V = lvr[il] * t.Ar;
+    if (t.valid && i < i1) epilogue<T, MODE>(a, cb + (size_t)ic * P + t.pp, Lu, V, uc, Rc.st, acc);
+    um = uc;
+    cm = cc;
+}
+
+template <class T, int MODE, bool VIRT, bool CV>
+__global__ __launch_bounds__(64 * W7) void k_iso7(Geo<T> g, KArgs<T> a)
+{
     const int L = xcd_tile();
     if (L >= a.nbx * a.nrc * a.nc) return;
     if (a.done && *a.done) return;
-    const int np = g.np, nt = g.nt, nr = g.nr, P = g.P;
-    const int ntk = (np + TX - 1) / TX;
+    const int nt = g.nt, np = g.np, nr = g.nr;
+    const unsigned P = (unsigned)g.P;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int bx = L % a.nbx, rest = L / a.nbx, rc = rest % a.nrc, c = rest / a.nrc;
-    const TileMap tm = tile_map(bx % ntk, bx / ntk, nt, np);
+    Pt7<T> t;
+    unsigned pp = (unsigned)(bx * W7 + wv) * 64u + (unsigned)lane;
+    t.valid = pp < P;
+    if (!t.valid) pp = P - 1;
+    const unsigned j = pp / (unsigned)np, k = pp - j * (unsigned)np;
+    const unsigned kp = (k == (unsigned)np - 1) ? 0u : k + 1;
+    // in-plane neighbour offsets: phi wraps; at the poles the missing row is
+    // replaced by the cell itself (its coupling is zero)
+    t.pp = pp;
+    t.ow = (k == 0) ? pp + np - 1 : pp - 1;
+    t.oe = pp - k + kp;
+    t.os = (j > 0) ? pp - np : pp;
+    t.on = (j + 1 < (unsigned)nt) ? pp + np : pp;
+    // per-cell metric products; the level factors gr, gtr, vr are uniform
+    t.Ar = g.vt[j] * g.vp[k];
+    t.As = g.gtt[j] * g.vp[k];
+    t.An = g.gtt[j + 1] * g.vp[k];
+    t.Aw = g.gpt[j] * g.gpp[k];
+    t.Ae = g.gpt[j] * g.gpp[kp];
     const size_t cb = (size_t)c * nr * P;
     const T* u = a.u + cb;
     const T* y = VIRT ? a.y0 + cb : nullptr;
-    const T* cf = a.coef;  // null: constant coefficient a.cs
     const int i0 = a.r_lo + rc * a.rch;
     const int i1 = min(a.r_hi, i0 + a.rch);
-    const int j = min(tm.j, nt - 1), k = tm.valid ? tm.k : 0;
-    const int kp = (k == np - 1) ? 0 : k + 1;
-    const T vtj = g.vt[j], vpk = g.vp[k];
-    const T gts = g.gtt[j], gtn = g.gtt[j + 1], gpj = g.gpt[j], gpw = g.gpp[k], gpe = g.gpp[kp];
-    const size_t ob = (size_t)c * P + tm.own_off;  // boundary data of the own cell
-    const int so = tm.own_slot;
-    Acc<T, MODE> acc;
-
-    // ring R[q] = loads of level i + q; level i + DEPTH is issued while
-    // level i is computed (DEPTH levels of loads in flight per thread)
-    constexpr int DEPTH = 2;
-    Lev7<T> R[DEPTH + 1] = {};
-    T um = 0, cm = a.cs;
-    if (i0 < i1) {
-        if (i0 > 0) {
-            um = ldu<T, VIRT>(a, u, y, (size_t)(i0 - 1) * P + tm.own_off);
-            if (cf) cm = cf[(size_t)(i0 - 1) * P + tm.own_off];
-        }
-#pragma unroll
-        for (int q = 0; q < DEPTH; ++q)
-            if (i0 + q < nr && i0 + q <= i1)
-                fetch7<T, MODE, VIRT>(a, u, y, cf, tm, cb, P, i0 + q, i0 + q < i1, R[q]);
+    const size_t ob = (size_t)c * P + pp;  // boundary data of the own cell
+    // mirror data across the radial boundaries (zero in linear mode); a
+    // Dirichlet face couples to it at half distance (gr[0], gr[nr]), a
+    // no-flux face is dropped
+    t.ubl = (a.affine && i0 == 0) ? a.ub_in[ob] : T(0);
+    t.ubu = (a.affine && i1 == nr) ? a.ub_out[ob] : T(0);
+    t.fin = (a.bc_in == 0) ? T(1) : T(0);
+    t.fout = (a.bc_out == 0) ? T(1) : T(0);
+    // the chunk's level factors gr (faces i0..), gtr, vr, staged in LDS: read
+    // there, they do not share the vector-memory counter with the prefetch
+    __shared__ T lgr[RCH_MAX + 3], lgtr[RCH_MAX + 3], lvr[RCH_MAX + 3];
+    for (int q = threadIdx.x; q < RCH_MAX + 3; q += blockDim.x) {
+        const int lv = min(i0 + q, nr - 1);
+        lgr[q] = g.gr[min(i0 + q, nr)];
+        lgtr[q] = g.gtr[lv];
+        lvr[q] = g.vr[lv];
     }
-    for (int i = i0; i < i1; ++i) {
-        const int b = i & 1;
-        const Lev7<T>& R0 = R[0];
-        const Lev7<T>& R1 = R[1];
-        su[b][so] = R0.u;
-        if (tm.has_h) su[b][tm.h_slot] = R0.h;
-        if (cf) {
-            sc[b][so] = R0.c;
-            if (tm.has_h) sc[b][tm.h_slot] = R0.ch;
+    __syncthreads();
+    Acc<T, MODE> acc;
+    if (i0 < i1) {
+        Lev7<T, CV, MODE> R0, R1, R2;
+        T um = 0, cm = a.cs;
+        if (i0 > 0) {
+            um = ldu<T, VIRT>(a, u, y, (size_t)(i0 - 1) * P + pp);
+            if constexpr (CV) cm = a.coef[(size_t)(i0 - 1) * P + pp];
         }
-        // loads for level i+DEPTH (its own value is a radial neighbour later)
-        if (i + DEPTH < nr && i + DEPTH <= i1)
-            fetch7<T, MODE, VIRT>(a, u, y, cf, tm, cb, P, i + DEPTH, i + DEPTH < i1, R[DEPTH]);
-        __syncthreads();
-        const T uc = R0.u;
-        const T cc = cf ? R0.c : a.cs;
-        const T us = su[b][so - HX], un = su[b][so + HX], uw = su[b][so - 1], ue = su[b][so + 1];
-        T cs_ = a.cs, cn = a.cs, cw = a.cs, ce = a.cs;
-        if (cf) {
-            cs_ = sc[b][so - HX];
-            cn = sc[b][so + HX];
-            cw = sc[b][so - 1];
-            ce = sc[b][so + 1];
+        fetch7<T, CV, MODE, VIRT>(a, u, y, (size_t)i0 * P, t.pp, t.ow, t.oe, t.os, t.on,
+                                  cb + (size_t)i0 * P + pp, R0);
+        {
+            const int lv = min(i0 + 1, nr - 1), ls = min(i0 + 1, i1 - 1);
+            fetch7<T, CV, MODE, VIRT>(a, u, y, (size_t)lv * P, t.pp, t.ow, t.oe, t.os, t.on,
+                                      cb + (size_t)ls * P + pp, R1);
         }
-        const T half = T(0.5);
-        const T gtri = g.gtr[i];
-        // radial faces (i is uniform across the workgroup)
-        T Cl, ul, Cu, uu;
-        if (i > 0) {
-            Cl = half * (cc + cm) * (g.gr[i] * vtj * vpk);
-            ul = um;
-        } else {
-            Cl = (a.bc_in == 0) ? cc * (g.gr[0] * vtj * vpk) : T(0);
-            ul = a.affine ? a.ub_in[ob] : T(0);
+        // three levels per trip with the ring's roles rotating
+        for (int i = i0; i < i1; i += 3) {
+            step7<T, MODE, VIRT, CV>(g, a, u, y, cb, t, i, i0, i1, lgr, lgtr, lvr, R0, R1, R2, um,
+                                     cm, acc);
+            step7<T, MODE, VIRT, CV>(g, a, u, y, cb, t, i + 1, i0, i1, lgr, lgtr, lvr, R1, R2, R0,
+                                     um, cm, acc);
+            step7<T, MODE, VIRT, CV>(g, a, u, y, cb, t, i + 2, i0, i1, lgr, lgtr, lvr, R2, R0, R1,
+                                     um, cm, acc);
         }
-        if (i < nr - 1) {
-            Cu = half * (cc + (cf ? R1.c : a.cs)) * (g.gr[i + 1] * vtj * vpk);
-            uu = R1.u;
-        } else {
-            Cu = (a.bc_out == 0) ? cc * (g.gr[nr] * vtj * vpk) : T(0);
-            uu = a.affine ? a.ub_out[ob] : T(0);
-        }
-        T Lu = Cl * (uc - ul);
-        Lu += Cu * (uc - uu);
-        Lu += half * (cc + cs_) * (gtri * gts * vpk) * (uc - us);
-        Lu += half * (cc + cn) * (gtri * gtn * vpk) * (uc - un);
-        Lu += half * (cc + cw) * (gtri * gpj * gpw) * (uc - uw);
-        Lu += half * (cc + ce) * (gtri * gpj * gpe) * (uc - ue);
-        const T V = g.vr[i] * vtj * vpk;
-        if (tm.valid) epilogue<T, MODE>(a, cb + (size_t)i * P + tm.own_off, Lu, V, uc, R0.s, acc);
-        um = uc;
-        cm = cc;
-#pragma unroll
-        for (int q = 0; q < DEPTH; ++q) R[q] = R[q + 1];
     }
     finish<T, MODE>(a, L, acc);
 }
@@ -362,7 +426,10 @@ __global__ __launch_bounds__(kBlock) void k_iso7(Geo<T> g, KArgs<T> a)
 
 // one corner plane ic's loads of a thread: its own / halo cell of level ic,
 // the coefficients of corners t and t + 256, and the stage streams of the
-// own cell at level ic - 1 (the level that plane completes)
+// own cell at level ic - 1 (the level that plane completes).  Indices are
+// clamped to the mesh and the chunk, so the loads are unconditional (a
+// thread without a halo cell or a second corner loads a duplicate); values
+// loaded for planes past the chunk are never used.
 template <class T>
 struct LevA {
     T u, h;
@@ -373,25 +440,20 @@ struct LevA {
 template <class T, int MODE, bool VIRT>
 __device__ __forceinline__ void fetchA(const KArgs<T>& a, const T* u, const T* y, const TileMap& tm,
                                        size_t cb, int P, int nr, int nt, int np, size_t nco,
-                                       int ic, int i0, int i1, int cq0, int cq1, bool has_c1,
-                                       LevA<T>& R)
+                                       int ic, int i0, int i1, int cq0, int cq1, LevA<T>& R)
 {
-    if (ic < nr) {
-        const size_t lb = (size_t)ic * P;
-        R.u = ldu<T, VIRT>(a, u, y, lb + tm.own_off);
-        if (tm.has_h) R.h = ldu<T, VIRT>(a, u, y, lb + tm.h_off);
-    }
-    const size_t qb = (size_t)ic * (nt + 1) * np;
+    const size_t lb = (size_t)min(ic, nr - 1) * P;
+    R.u = ldu<T, VIRT>(a, u, y, lb + tm.own_off);
+    R.h = ldu<T, VIRT>(a, u, y, lb + tm.h_off);
+    const size_t qb = (size_t)min(ic, nr) * (nt + 1) * np;
     R.e0r = a.e[qb + cq0];
     R.e0t = a.e[nco + qb + cq0];
     R.e0p = a.e[2 * nco + qb + cq0];
-    if (has_c1) {
-        R.e1r = a.e[qb + cq1];
-        R.e1t = a.e[nco + qb + cq1];
-        R.e1p = a.e[2 * nco + qb + cq1];
-    }
-    if (ic - 1 >= i0 && ic - 1 < i1)
-        load_streams<T, MODE>(a, cb + (size_t)(ic - 1) * P + tm.own_off, R.s);
+    R.e1r = a.e[qb + cq1];
+    R.e1t = a.e[nco + qb + cq1];
+    R.e1p = a.e[2 * nco + qb + cq1];
+    const int ls = min(max(ic - 1, i0), i1 - 1);
+    load_streams<T, MODE>(a, cb + (size_t)ls * P + tm.own_off, R.s);
 }
 
 // Scatter weights for one corner plane: the cell's weight as the upper cell
@@ -418,37 +480,35 @@ __device__ __forceinline__ PlaneW<T> plane_weights(int kind, int bc)
     return w;
 }
 
-// mirror ghost across a radial boundary: Dirichlet 2 u_b - u (u_b = 0 in
-// linear mode), no-flux u
+// mirror ghost across a radial boundary: Dirichlet 2 u_b - u (u_b is the
+// staged boundary value, 0 in linear mode), no-flux u
 template <class T>
-__device__ __forceinline__ T ghost(T x, const T* ub, size_t o, int bc, int affine)
+__device__ __forceinline__ T ghost(T x, T b, int bc)
 {
-    if (bc != 0) return x;
-    const T b = affine ? ub[o] : T(0);
-    return T(2) * b - x;
+    return bc != 0 ? x : T(2) * b - x;
 }
 
 // flux t = e . D of tile corner (cy, cx) between the LDS planes lo and hi;
-// gside 1: lo is the mirror ghost of hi, 2: hi is the ghost of lo
+// gside 1: lo is the mirror ghost of hi, 2: hi is the ghost of lo, with the
+// boundary values of the tile plane in ubp (LDS)
 template <class T>
 __device__ __forceinline__ T corner_flux(const T* lo, const T* hi, int cy, int cx, T er, T et,
-                                         T ep, int gside, const T* ub, int bc, int affine,
-                                         size_t ubo, int j0, int k0, int nt, int np)
+                                         T ep, int gside, const T* ubp, int bc)
 {
     const int s00 = cy * HX + cx, s01 = s00 + 1, s10 = s00 + HX, s11 = s10 + 1;
     T l00, l01, l10, l11, h00, h01, h10, h11;
     if (gside == 1) {
         h00 = hi[s00]; h01 = hi[s01]; h10 = hi[s10]; h11 = hi[s11];
-        l00 = ghost(h00, ub, ubo + slot_offset(cy, cx, j0, k0, nt, np), bc, affine);
-        l01 = ghost(h01, ub, ubo + slot_offset(cy, cx + 1, j0, k0, nt, np), bc, affine);
-        l10 = ghost(h10, ub, ubo + slot_offset(cy + 1, cx, j0, k0, nt, np), bc, affine);
-        l11 = ghost(h11, ub, ubo + slot_offset(cy + 1, cx + 1, j0, k0, nt, np), bc, affine);
+        l00 = ghost(h00, ubp[s00], bc);
+        l01 = ghost(h01, ubp[s01], bc);
+        l10 = ghost(h10, ubp[s10], bc);
+        l11 = ghost(h11, ubp[s11], bc);
     } else if (gside == 2) {
         l00 = lo[s00]; l01 = lo[s01]; l10 = lo[s10]; l11 = lo[s11];
-        h00 = ghost(l00, ub, ubo + slot_offset(cy, cx, j0, k0, nt, np), bc, affine);
-        h01 = ghost(l01, ub, ubo + slot_offset(cy, cx + 1, j0, k0, nt, np), bc, affine);
-        h10 = ghost(l10, ub, ubo + slot_offset(cy + 1, cx, j0, k0, nt, np), bc, affine);
-        h11 = ghost(l11, ub, ubo + slot_offset(cy + 1, cx + 1, j0, k0, nt, np), bc, affine);
+        h00 = ghost(l00, ubp[s00], bc);
+        h01 = ghost(l01, ubp[s01], bc);
+        h10 = ghost(l10, ubp[s10], bc);
+        h11 = ghost(l11, ubp[s11], bc);
     } else {
         l00 = lo[s00]; l01 = lo[s01]; l10 = lo[s10]; l11 = lo[s11];
         h00 = hi[s00]; h01 = hi[s01]; h10 = hi[s10]; h11 = hi[s11];
@@ -461,11 +521,88 @@ __device__ __forceinline__ T corner_flux(const T* lo, const T* hi, int cy, int c
     return er * Dr + et * Dt + ep * Dp;
 }
 
+// LDS of the field-aligned march
+template <class T>
+struct ShA {
+    T su[3][HN];                       // cell planes (ring of three levels)
+    T sr[NCOR], sth[NCOR], sph[NCOR];  // t e_r, t e_t, t e_p per tile corner
+    T ubi[HN], ubo[HN];                // boundary data of the tile plane (r_in, r_out)
+    T vr[RCH_MAX + 3];                 // chunk level factors
+};
+
+// per-thread constants of the field-aligned march
+struct PtA {
+    int t, ci1, cy0, cx0, cy1, cx1, cq0, cq1, cA;
+    bool has_c1;
+};
+
+// Corner plane ic: store its cell level into the LDS ring, issue the loads
+// of plane ic + 2 into Rp, compute the plane's corner fluxes, gather the
+// upper share into carry and complete level ic - 1.  Planes past i1 are
+// computed but complete nothing.
+template <class T, int MODE, bool VIRT>
+__device__ __forceinline__ void stepA(const Geo<T>& g, const KArgs<T>& a, const T* u, const T* y,
+                                      const TileMap& tm, const PtA& pt, ShA<T>& sh, size_t cb,
+                                      size_t nco, T Ar, int ic, int i0, int i1,
+                                      const LevA<T>& Rc, LevA<T>& Rp, T& carry, Acc<T, MODE>& acc)
+{
+    const int np = g.np, nt = g.nt, nr = g.nr, P = g.P;
+    const int bh = ic % 3, bl = (ic + 2) % 3;
+    if (ic < nr) {
+        sh.su[bh][tm.own_slot] = Rc.u;
+        if (tm.has_h) sh.su[bh][tm.h_slot] = Rc.h;
+    }
+    fetchA<T, MODE, VIRT>(a, u, y, tm, cb, P, nr, nt, np, nco, ic + 2, i0, i1, pt.cq0, pt.cq1, Rp);
+    __syncthreads();
+    int kind = 0, gside = 0, bc = 0;
+    const T* ubp = sh.ubi;
+    if (ic == 0) { kind = 1; gside = 1; bc = a.bc_in; }
+    else if (ic == nr) { kind = 2; gside = 2; bc = a.bc_out; ubp = sh.ubo; }
+    const T* lo = sh.su[bl];
+    const T* hi = sh.su[bh];
+    {
+        const T f0 = corner_flux<T>(lo, hi, pt.cy0, pt.cx0, Rc.e0r, Rc.e0t, Rc.e0p, gside, ubp, bc);
+        sh.sr[pt.t] = f0 * Rc.e0r;
+        sh.sth[pt.t] = f0 * Rc.e0t;
+        sh.sph[pt.t] = f0 * Rc.e0p;
+        if (pt.has_c1) {
+            const T f1 = corner_flux<T>(lo, hi, pt.cy1, pt.cx1, Rc.e1r, Rc.e1t, Rc.e1p, gside, ubp, bc);
+            sh.sr[pt.ci1] = f1 * Rc.e1r;
+            sh.sth[pt.ci1] = f1 * Rc.e1t;
+            sh.sph[pt.ci1] = f1 * Rc.e1p;
+        }
+    }
+    __syncthreads();
+    const PlaneW<T> w = plane_weights<T>(kind, bc);
+    const int cA = pt.cA;
+    // A: st=+1 sp=+1; B: st=+1 sp=-1; C: st=-1 sp=+1; D: st=-1 sp=-1
+    const T tA = sh.sth[cA] + sh.sph[cA];
+    const T tB = sh.sth[cA + 1] - sh.sph[cA + 1];
+    const T tC = -sh.sth[cA + CX] + sh.sph[cA + CX];
+    const T tD = -sh.sth[cA + CX + 1] - sh.sph[cA + CX + 1];
+    const T rA = sh.sr[cA], rB = sh.sr[cA + 1], rC = sh.sr[cA + CX], rD = sh.sr[cA + CX + 1];
+    T up = w.ru * rA + w.tu * tA;
+    up += w.ru * rB + w.tu * tB;
+    up += w.ru * rC + w.tu * tC;
+    up += w.ru * rD + w.tu * tD;
+    T dn = w.rd * rA + w.td * tA;
+    dn += w.rd * rB + w.td * tB;
+    dn += w.rd * rC + w.td * tC;
+    dn += w.rd * rD + w.td * tD;
+    const int i = ic - 1;
+    if (i >= i0 && i < i1) {
+        const T Lu = carry + dn;
+        const T V = sh.vr[i - i0] * Ar;
+        const T uc = lo[tm.own_slot];
+        if (tm.valid) epilogue<T, MODE>(a, cb + (size_t)i * P + tm.own_off, Lu, V, uc, Rc.s, acc);
+    }
+    carry = up;
+}
+
 template <class T, int MODE, bool VIRT>
 __global__ __launch_bounds__(kBlock) void k_aligned(Geo<T> g, KArgs<T> a)
 {
-    __shared__ T su[3][HN];                        // cell planes (ring of three levels)
-    __shared__ T sr[NCOR], sth[NCOR], sph[NCOR];   // t e_r, t e_t, t e_p per tile corner
+    __shared__ ShA<T> sh;
     const int L = xcd_tile();
     if (L >= a.nbx * a.nrc * a.nc) return;
     if (a.done && *a.done) return;
@@ -476,101 +613,58 @@ __global__ __launch_bounds__(kBlock) void k_aligned(Geo<T> g, KArgs<T> a)
     const size_t cb = (size_t)c * nr * P;
     const T* u = a.u + cb;
     const T* y = VIRT ? a.y0 + cb : nullptr;
-    const size_t ubo = (size_t)c * P;
     const size_t nco = (size_t)(nr + 1) * (nt + 1) * np;
     const int i0 = a.r_lo + rc * a.rch;
     const int i1 = min(a.r_hi, i0 + a.rch);
     const int j = min(tm.j, nt - 1), k = tm.valid ? tm.k : 0;
-    const T vtj = g.vt[j], vpk = g.vp[k];
-    const int t = threadIdx.x;
+    const T Ar = g.vt[j] * g.vp[k];
+    PtA pt;
+    pt.t = threadIdx.x;
     // the thread's corners of a tile plane: t and t + 256 (< NCOR); corner
     // rows beyond the last pole row read the (zero) pole row
-    const bool has_c1 = t + kBlock < NCOR;
-    const int ci1 = has_c1 ? t + kBlock : t;
-    const int cy0 = t / CX, cx0 = t % CX, cy1 = ci1 / CX, cx1 = ci1 % CX;
-    const int cq0 = min(tm.j0 + cy0, nt) * np + wrapk(tm.k0 + cx0, np);
-    const int cq1 = min(tm.j0 + cy1, nt) * np + wrapk(tm.k0 + cx1, np);
+    pt.has_c1 = pt.t + kBlock < NCOR;
+    pt.ci1 = pt.has_c1 ? pt.t + kBlock : pt.t;
+    pt.cy0 = pt.t / CX;
+    pt.cx0 = pt.t % CX;
+    pt.cy1 = pt.ci1 / CX;
+    pt.cx1 = pt.ci1 % CX;
+    pt.cq0 = min(tm.j0 + pt.cy0, nt) * np + wrapk(tm.k0 + pt.cx0, np);
+    pt.cq1 = min(tm.j0 + pt.cy1, nt) * np + wrapk(tm.k0 + pt.cx1, np);
     // the own cell's corners A (ty, tx), B (ty, tx+1), C (ty+1, tx), D (ty+1, tx+1)
-    const int cA = tm.ty * CX + tm.tx;
+    pt.cA = tm.ty * CX + tm.tx;
+    // LDS staging: level factors of the chunk, the boundary data of the tile
+    // plane (zero in linear mode), and the cell level below the chunk
+    for (int q = threadIdx.x; q < RCH_MAX + 3; q += blockDim.x) sh.vr[q] = g.vr[min(i0 + q, nr - 1)];
+    {
+        const size_t ob = (size_t)c * P;
+        const bool lin = !a.affine;
+        sh.ubi[tm.own_slot] = (lin || i0 != 0) ? T(0) : a.ub_in[ob + tm.own_off];
+        sh.ubo[tm.own_slot] = (lin || i1 != nr) ? T(0) : a.ub_out[ob + tm.own_off];
+        if (tm.has_h) {
+            sh.ubi[tm.h_slot] = (lin || i0 != 0) ? T(0) : a.ub_in[ob + tm.h_off];
+            sh.ubo[tm.h_slot] = (lin || i1 != nr) ? T(0) : a.ub_out[ob + tm.h_off];
+        }
+    }
     Acc<T, MODE> acc;
-    // ring R[q] = loads of corner plane ic + q; plane ic + DEPTH is issued
-    // while plane ic is computed
-    constexpr int DEPTH = 2;
-    LevA<T> R[DEPTH + 1] = {};
-    T carry = 0;
     if (i0 < i1) {
         if (i0 > 0) {
             const size_t lb = (size_t)(i0 - 1) * P;
-            su[(i0 - 1) % 3][tm.own_slot] = ldu<T, VIRT>(a, u, y, lb + tm.own_off);
-            if (tm.has_h) su[(i0 - 1) % 3][tm.h_slot] = ldu<T, VIRT>(a, u, y, lb + tm.h_off);
+            sh.su[(i0 - 1) % 3][tm.own_slot] = ldu<T, VIRT>(a, u, y, lb + tm.own_off);
+            if (tm.has_h) sh.su[(i0 - 1) % 3][tm.h_slot] = ldu<T, VIRT>(a, u, y, lb + tm.h_off);
         }
-#pragma unroll
-        for (int q = 0; q < DEPTH; ++q)
-            if (i0 + q <= i1)
-                fetchA<T, MODE, VIRT>(a, u, y, tm, cb, P, nr, nt, np, nco, i0 + q, i0, i1, cq0, cq1,
-                                      has_c1, R[q]);
-    }
-    // corner plane ic completes cell level ic-1 and starts level ic
-    for (int ic = i0; ic <= i1 && i0 < i1; ++ic) {
-        const int bh = ic % 3, bl = (ic + 2) % 3;
-        const LevA<T>& R0 = R[0];
-        if (ic < nr) {
-            su[bh][tm.own_slot] = R0.u;
-            if (tm.has_h) su[bh][tm.h_slot] = R0.h;
+        LevA<T> R0, R1, R2;
+        fetchA<T, MODE, VIRT>(a, u, y, tm, cb, P, nr, nt, np, nco, i0, i0, i1, pt.cq0, pt.cq1, R0);
+        fetchA<T, MODE, VIRT>(a, u, y, tm, cb, P, nr, nt, np, nco, i0 + 1, i0, i1, pt.cq0, pt.cq1, R1);
+        T carry = 0;
+        // corner plane ic completes cell level ic-1 and starts level ic;
+        // three planes per trip with the ring's roles rotating
+        for (int ic = i0; ic <= i1; ic += 3) {
+            stepA<T, MODE, VIRT>(g, a, u, y, tm, pt, sh, cb, nco, Ar, ic, i0, i1, R0, R2, carry, acc);
+            stepA<T, MODE, VIRT>(g, a, u, y, tm, pt, sh, cb, nco, Ar, ic + 1, i0, i1, R1, R0, carry,
+                                 acc);
+            stepA<T, MODE, VIRT>(g, a, u, y, tm, pt, sh, cb, nco, Ar, ic + 2, i0, i1, R2, R1, carry,
+                                 acc);
         }
-        if (ic + DEPTH <= i1)
-            fetchA<T, MODE, VIRT>(a, u, y, tm, cb, P, nr, nt, np, nco, ic + DEPTH, i0, i1, cq0, cq1,
-                                  has_c1, R[DEPTH]);
-        __syncthreads();
-        int kind = 0, gside = 0, bc = 0;
-        const T* ub = nullptr;
-        if (ic == 0) { kind = 1; gside = 1; bc = a.bc_in; ub = a.ub_in; }
-        else if (ic == nr) { kind = 2; gside = 2; bc = a.bc_out; ub = a.ub_out; }
-        const T* lo = su[bl];
-        const T* hi = su[bh];
-        {
-            const T f0 = corner_flux<T>(lo, hi, cy0, cx0, R0.e0r, R0.e0t, R0.e0p, gside, ub, bc,
-                                        a.affine, ubo, tm.j0, tm.k0, nt, np);
-            sr[t] = f0 * R0.e0r;
-            sth[t] = f0 * R0.e0t;
-            sph[t] = f0 * R0.e0p;
-            if (has_c1) {
-                const T f1 = corner_flux<T>(lo, hi, cy1, cx1, R0.e1r, R0.e1t, R0.e1p, gside, ub,
-                                            bc, a.affine, ubo, tm.j0, tm.k0, nt, np);
-                sr[ci1] = f1 * R0.e1r;
-                sth[ci1] = f1 * R0.e1t;
-                sph[ci1] = f1 * R0.e1p;
-            }
-        }
-        __syncthreads();
-        const PlaneW<T> w = plane_weights<T>(kind, bc);
-        T up = 0, dn = 0;
-        {
-            // A: st=+1 sp=+1; B: st=+1 sp=-1; C: st=-1 sp=+1; D: st=-1 sp=-1
-            const T tA = sth[cA] + sph[cA];
-            const T tB = sth[cA + 1] - sph[cA + 1];
-            const T tC = -sth[cA + CX] + sph[cA + CX];
-            const T tD = -sth[cA + CX + 1] - sph[cA + CX + 1];
-            const T rA = sr[cA], rB = sr[cA + 1], rC = sr[cA + CX], rD = sr[cA + CX + 1];
-            up = w.ru * rA + w.tu * tA;
-            up += w.ru * rB + w.tu * tB;
-            up += w.ru * rC + w.tu * tC;
-            up += w.ru * rD + w.tu * tD;
-            dn = w.rd * rA + w.td * tA;
-            dn += w.rd * rB + w.td * tB;
-            dn += w.rd * rC + w.td * tC;
-            dn += w.rd * rD + w.td * tD;
-        }
-        if (ic - 1 >= i0) {
-            const int i = ic - 1;
-            const T Lu = carry + dn;
-            const T V = g.vr[i] * vtj * vpk;
-            const T uc = lo[tm.own_slot];
-            if (tm.valid) epilogue<T, MODE>(a, cb + (size_t)i * P + tm.own_off, Lu, V, uc, R0.s, acc);
-        }
-        carry = up;
-#pragma unroll
-        for (int q = 0; q < DEPTH; ++q) R[q] = R[q + 1];
     }
     finish<T, MODE>(a, L, acc);
 }
@@ -581,12 +675,19 @@ template <class T, int MODE, bool VIRT>
 static void go_iso7(const Geo<T>& g, const KArgs<T>& a, hipStream_t s)
 {
     const int nt = a.nbx * a.nrc * a.nc;
-    hipLaunchKernelGGL((k_iso7<T, MODE, VIRT>), dim3(grid_for_tiles(nt)), dim3(kBlock), 0, s, g, a);
+    if (a.rch > RCH_MAX) return;  // the host never asks for longer chunks
+    if (a.coef)
+        hipLaunchKernelGGL((k_iso7<T, MODE, VIRT, true>), dim3(grid_for_tiles(nt)), dim3(64 * W7), 0,
+                           s, g, a);
+    else
+        hipLaunchKernelGGL((k_iso7<T, MODE, VIRT, false>), dim3(grid_for_tiles(nt)), dim3(64 * W7), 0,
+                           s, g, a);
 }
 template <class T, int MODE, bool VIRT>
 static void go_aligned(const Geo<T>& g, const KArgs<T>& a, hipStream_t s)
 {
     const int nt = a.nbx * a.nrc * a.nc;
+    if (a.rch > RCH_MAX) return;  // the host never asks for longer chunks
     hipLaunchKernelGGL((k_aligned<T, MODE, VIRT>), dim3(grid_for_tiles(nt)), dim3(kBlock), 0, s,
                        g, a);
 }
