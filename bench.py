@@ -362,6 +362,19 @@ def main():
         "kernels": kernels,
         "copy_GB_s": round(copy_gbs, 1),
     }
+    # the argmax form of the limit (Eq. ptl3, used by the advances) against
+    # the minimum of Eq. (ptl2) over every cell pair, on the step's fields
+    ptl = {}
+    for name, g, uw, u0 in (("conduction", gc, uc, uc0), ("viscosity", gv, uv, uv0)):
+        uw.copy_(u0)
+        g.bind(uw)
+        da, ka = g.ptl()
+        df, kf = g.ptl_full()
+        sig = lambda x: float(f"{x:.4g}")
+        ptl[name] = {"dt_argmax_over_dtE": sig(da / g.dt_explicit()),
+                     "dt_fullgrid_over_dtE": sig(df / g.dt_explicit()),
+                     "argmax_over_fullgrid": sig(da / df), "k_argmax": ka, "k_fullgrid": kf}
+    out["ptl_argmax_vs_fullgrid"] = ptl
     legs = [x for x in args.legs.split(",") if x and x != "none"]
     if "fp32" in legs:
         log("fp32 leg")

@@ -187,6 +187,14 @@ pa_status pa_diag(pa_ctx* ctx, double* diag_dev);
  * du*dF < 0 (Eq. ptl2); +inf when none constrains.  k_lin may be NULL. */
 pa_status pa_compute_ptl(pa_ctx* ctx, double* dt_ptl, int64_t* k_lin);
 
+/* Full-grid form of the limit (Sec. 2 takes Eq. ptl2 at the largest |F|
+ * only, assuming the most restrictive pair is found there): the minimum of
+ * Eq. (ptl2) over every cell and each of its face neighbours, for the bound
+ * field.  k_lin (may be NULL) receives the lowest linear cell index attaining
+ * it, -1 when no pair constrains (dt_full = +inf).  A diagnostic of that
+ * assumption; the advances use pa_compute_ptl's form. */
+pa_status pa_compute_ptl_full(pa_ctx* ctx, double* dt_full, int64_t* k_lin);
+
 /* Advance the bound field over dt with RKL2 (Meyer, Balsara & Aslam 2014,
  * the paper's RKL2 reference) or RKG2 (App. A).  cycles > 0: that many equal
  * cycles; cycles == 0: dynamic PTL cycling (Sec. 2): each cycle takes

@@ -716,6 +716,25 @@ pa_status pa_compute_ptl(pa_ctx* c, double* dt, int64_t* k)
     return PA_OK;
 }
 
+pa_status pa_compute_ptl_full(pa_ctx* c, double* dt, int64_t* k)
+{
+    if (!c) return PA_ERR_ARG;
+    if (!dt) return fail(c, PA_ERR_ARG, "null output");
+    if (!c->have_coef) return fail(c, PA_ERR_STATE, "coefficients not set");
+    if (!c->u) return fail(c, PA_ERR_STATE, "no field bound");
+    launch_fill_zero(c->flag, sizeof(int), c->stream);
+    first_pass<double>(c, c->u, c->w[0]);
+    launch_ptl_full<double>(c->u, c->w[0], c->d.ncomp, c->d.nr, c->d.nt, c->d.np, c->part,
+                            c->part_idx, c->st, c->stream);
+    HIPCHK(c, hipGetLastError());
+    pa_status s = sync_state(c);
+    if (s) return s;
+    if (*c->hflag) return fail(c, PA_ERR_NONFINITE, "non-finite F");
+    *dt = c->hst->dt_full;
+    if (k) *k = c->hst->kfull;
+    return PA_OK;
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------- drivers

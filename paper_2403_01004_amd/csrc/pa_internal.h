@@ -102,8 +102,16 @@ struct DevState {
     int done, iters, status, nonfinite;
     int max_iter, force_iters, mode;
     double tol;
+    double dt_full;    // full-grid limit (diagnostic)
+    long long kfull;
 };
 void launch_reduce_max(const double* part, int n, double* outp, hipStream_t s);
+// minimum of Eq. (ptl2) over every cell and face neighbour -> st->dt_full,
+// st->kfull (lowest cell index attaining it, -1 if none); pval / pidx hold
+// up to 4096 partials
+template <class T>
+void launch_ptl_full(const T* u, const T* F, int nc, int nr, int nt, int np, double* pval,
+                     long long* pidx, DevState* st, hipStream_t s);
 template <class T>
 void launch_ptl_finalize(const double* pval, const long long* pidx, int n, const T* u, const T* F,
                          int nc, int nr, int nt, int np, DevState* st, hipStream_t s);

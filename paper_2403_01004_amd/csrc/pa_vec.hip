@@ -132,6 +132,97 @@ template void launch_ptl_finalize<double>(const double*, const long long*, int, 
 template void launch_ptl_finalize<float>(const double*, const long long*, int, const float*,
                                          const float*, int, int, int, int, DevState*, hipStream_t);
 
+// Full-grid limit: the minimum of Eq. (ptl2) over every cell and each of
+// its face neighbours (same pairs as Eq. ptl3, at all cells instead of the
+// argmax of |F|).  Per-block partials (value, lowest cell index attaining it)
+// then a one-workgroup finish into st->dt_full / st->kfull.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_ptl_full(const T* u, const T* F, int nc, int nr, int nt,
+                                                     int np, double* pval, long long* pidx)
+{
+    __shared__ double lv[kBlock / 64];
+    __shared__ long long li[kBlock / 64];
+    const long long P = (long long)nt * np, N = (long long)nr * P, NT = N * nc;
+    double best = __builtin_inf();
+    long long bi = 0x7fffffffffffffffLL;
+    for (long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x; m < NT;
+         m += (long long)gridDim.x * blockDim.x) {
+        const long long cell = m % N;
+        const int i = (int)(cell / P);
+        const int pp = (int)(cell - (long long)i * P);
+        const int j = pp / np, k = pp - j * np;
+        long long nb[6];
+        int nn = 0;
+        if (i > 0) nb[nn++] = m - P;
+        if (i < nr - 1) nb[nn++] = m + P;
+        if (j > 0) nb[nn++] = m - np;
+        if (j < nt - 1) nb[nn++] = m + np;
+        nb[nn++] = m - k + (k == 0 ? np - 1 : k - 1);
+        nb[nn++] = m - k + (k == np - 1 ? 0 : k + 1);
+        const double um = (double)u[m], Fm = (double)F[m];
+        for (int q = 0; q < nn; ++q) {
+            const double du = um - (double)u[nb[q]];
+            const double dF = Fm - (double)F[nb[q]];
+            if (du != 0.0 && dF != 0.0 && du * dF < 0.0) {
+                const double c = -du / dF;
+                if (c < best || (c == best && m < bi)) { best = c; bi = m; }
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(best, o, 64);
+        const long long oi = __shfl_xor(bi, o, 64);
+        if (ov < best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+    }
+    if ((threadIdx.x & 63) == 0) { lv[threadIdx.x >> 6] = best; li[threadIdx.x >> 6] = bi; }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int w = 1; w < kBlock / 64; ++w)
+        if (lv[w] < best || (lv[w] == best && li[w] < bi)) { best = lv[w]; bi = li[w]; }
+    pval[blockIdx.x] = best;
+    pidx[blockIdx.x] = bi;
+}
+
+__global__ __launch_bounds__(kRedBlock) void k_ptl_full_finish(const double* pval,
+                                                               const long long* pidx, int n,
+                                                               DevState* st)
+{
+    __shared__ double lv[kRedBlock / 64];
+    __shared__ long long li[kRedBlock / 64];
+    double best = __builtin_inf();
+    long long bi = 0x7fffffffffffffffLL;
+    for (int q = threadIdx.x; q < n; q += blockDim.x)
+        if (pval[q] < best || (pval[q] == best && pidx[q] < bi)) { best = pval[q]; bi = pidx[q]; }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(best, o, 64);
+        const long long oi = __shfl_xor(bi, o, 64);
+        if (ov < best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+    }
+    if ((threadIdx.x & 63) == 0) { lv[threadIdx.x >> 6] = best; li[threadIdx.x >> 6] = bi; }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int w = 1; w < kRedBlock / 64; ++w)
+        if (lv[w] < best || (lv[w] == best && li[w] < bi)) { best = lv[w]; bi = li[w]; }
+    st->dt_full = best;
+    st->kfull = best < __builtin_inf() ? bi : -1;
+}
+
+template <class T>
+void launch_ptl_full(const T* u, const T* F, int nc, int nr, int nt, int np, double* pval,
+                     long long* pidx, DevState* st, hipStream_t s)
+{
+    const size_t NT = (size_t)nc * nr * nt * np;
+    size_t nb = (NT + kBlock - 1) / kBlock;
+    if (nb > 4096) nb = 4096;
+    hipLaunchKernelGGL((k_ptl_full<T>), dim3((unsigned)nb), dim3(kBlock), 0, s, u, F, nc, nr, nt, np,
+                       pval, pidx);
+    hipLaunchKernelGGL(k_ptl_full_finish, dim3(1), dim3(kRedBlock), 0, s, pval, pidx, (int)nb, st);
+}
+template void launch_ptl_full<double>(const double*, const double*, int, int, int, int, double*,
+                                      long long*, DevState*, hipStream_t);
+
 // ---------------------------------------------------------------- PCG
 
 static int vec_blocks(size_t n)

@@ -29,7 +29,7 @@ PRECS = {"fp64": 0, "fp32": 1}
 
 EXPORTS = ["pa_init", "pa_destroy", "pa_last_error", "pa_default_options", "pa_set_options",
            "pa_bind_field", "pa_set_coefficients", "pa_set_bc", "pa_dt_explicit", "pa_apply",
-           "pa_diag", "pa_compute_ptl", "pa_advance_rkl2", "pa_advance_rkg2",
+           "pa_diag", "pa_compute_ptl", "pa_compute_ptl_full", "pa_advance_rkl2", "pa_advance_rkg2",
            "pa_advance_be_pcg", "pa_lpc_default_train_opts", "pa_lpc_set_weights",
            "pa_lpc_get_weights", "pa_lpc_features", "pa_lpc_apply", "pa_lpc_loss_grad",
            "pa_lpc_train"]
@@ -118,6 +118,7 @@ def load(path: str = LIB_PATH):
         "pa_apply": (I32, [V, V, V, I32]),
         "pa_diag": (I32, [V, V]),
         "pa_compute_ptl": (I32, [V, P(D), P(I64)]),
+        "pa_compute_ptl_full": (I32, [V, P(D), P(I64)]),
         "pa_advance_rkl2": (I32, [V, D, I32, P(pa_stats)]),
         "pa_advance_rkg2": (I32, [V, D, I32, P(pa_stats)]),
         "pa_advance_be_pcg": (I32, [V, D, D, I32, P(pa_stats)]),
@@ -191,6 +192,12 @@ def pa_diag(ctx, d_ptr):
 def pa_compute_ptl(ctx):
     dt, k = ctypes.c_double(), ctypes.c_int64()
     st = load().pa_compute_ptl(ctx, ctypes.byref(dt), ctypes.byref(k))
+    return st, dt.value, k.value
+
+
+def pa_compute_ptl_full(ctx):
+    dt, k = ctypes.c_double(), ctypes.c_int64()
+    st = load().pa_compute_ptl_full(ctx, ctypes.byref(dt), ctypes.byref(k))
     return st, dt.value, k.value
 
 
@@ -399,6 +406,11 @@ class Operator:
 
     def ptl(self):
         st, dt, k = pa_compute_ptl(self.ctx)
+        self._check(st)
+        return dt, k
+
+    def ptl_full(self):
+        st, dt, k = pa_compute_ptl_full(self.ctx)
         self._check(st)
         return dt, k
 

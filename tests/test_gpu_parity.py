@@ -92,6 +92,29 @@ def test_ptl(dev, oracle_mod, shape, op, nc):
     assert dtg == dto or abs(dtg - dto) <= 1e-12 * dto
 
 
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("op,nc", CASES)
+def test_ptl_full(dev, oracle_mod, shape, op, nc):
+    """Full-grid limit: the oracle's minimum over every pair, evaluated on
+    the GPU's own F, is reproduced exactly (same divisions, order-free min);
+    against the oracle's F it agrees to the operator's rounding; it never
+    exceeds the argmax form."""
+    _log("ptl full", shape, op, nc)
+    prob = problem(op, shape, ncomp=nc)
+    g, o = pair(dev, oracle_mod, prob)
+    g.bind(prob.u)
+    dtg, kg = g.ptl_full()
+    Fg = g.apply(prob.u).cpu().numpy()
+    assert dtg == oracle_mod.ptl_fullgrid(prob.u, Fg)
+    dto = oracle_mod.ptl_fullgrid(prob.u, o.apply(prob.u))
+    if np.isinf(dto):
+        assert np.isinf(dtg) and kg == -1
+    else:
+        assert abs(dtg - dto) <= 1e-10 * dto
+        assert 0 <= kg < prob.u.size
+        assert dtg <= g.ptl()[0]
+
+
 @pytest.mark.parametrize("shape", [(9, 10, 13), (17, 24, 40)])
 @pytest.mark.parametrize("op,nc", CASES)
 @pytest.mark.parametrize("kind", ["rkl2", "rkg2"])
@@ -245,6 +268,10 @@ def test_fullsize_conduction(dev, oracle_mod, c2):
     assert abs(g.dt_explicit() - o.dt_explicit()) <= 1e-13 * o.dt_explicit()
     g.bind(prob.u)
     assert g.ptl() == o.ptl(prob.u) or abs(g.ptl()[0] - o.ptl(prob.u)[0]) <= 1e-12 * o.ptl(prob.u)[0]
+    _log("full conduction: full-grid limit")
+    dtf, kf = g.ptl_full()
+    assert dtf == oracle_mod.ptl_fullgrid(prob.u, Fg)
+    assert abs(dtf - oracle_mod.ptl_fullgrid(prob.u, Fo)) <= 1e-10 * dtf
     dt = 50 * o.dt_explicit()
     _log("full conduction: one RKL2 cycle")
     u = g.bind(prob.u)

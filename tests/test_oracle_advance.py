@@ -271,3 +271,18 @@ def test_pcg_errors(oracle_mod):
     assert st["status"] == 4
     _, st = o.advance_be(prob.u, dt, cycles=1, force_iters=3)
     assert st["status"] == 0 and st["iters_total"] == 3
+
+
+def test_ptl_fullgrid_hand_example(oracle_mod):
+    """Periodic ring of 4 cells, u = (0, 1, 0, 0.5), F = (1, -2, 1.5, -1).
+    Argmax |F| is cell 1: its pairs give 1/3 (cell 0) and 1/3.5 (cell 2), so
+    Eq. (ptl3) gives 1/3.5.  Over every pair the pair (2, 3) has du = -0.5,
+    dF = 2.5 -> 0.2, and (3, 0) gives 0.5/2 = 0.25: the full-grid minimum is
+    0.2."""
+    u = np.array([0.0, 1.0, 0.0, 0.5]).reshape(1, 1, 1, 4)
+    F = np.array([1.0, -2.0, 1.5, -1.0]).reshape(1, 1, 1, 4)
+    dt, k = oracle_mod.ptl_from(u, F)
+    assert k == 1 and abs(dt - 1 / 3.5) < 1e-16
+    assert abs(oracle_mod.ptl_fullgrid(u, F) - 0.2) < 1e-16
+    # no constraining pair at all
+    assert oracle_mod.ptl_fullgrid(np.ones_like(u), F) == np.inf
