@@ -63,6 +63,9 @@ def _load():
     lib.or_destroy.argtypes = [vp]
     lib.or_set_coefficients.restype = i
     lib.or_set_coefficients.argtypes = [vp, _D, d, d, _D]
+    lib.or_set_profile.restype = i
+    lib.or_set_profile.argtypes = [vp, _D, _D, d]
+    lib.or_volumes.argtypes = [vp, i, _D]
     lib.or_set_bc.argtypes = [vp, _D, _D]
     lib.or_volume.restype = d
     lib.or_volume.argtypes = [vp, i, i, i]
@@ -159,6 +162,8 @@ class Oracle:
     @classmethod
     def from_problem(cls, prob, bc_in=None, bc_out=None):
         o = cls(prob.mesh, prob.op, prob.ncomp, bc_in or prob.bc_in, bc_out or prob.bc_out)
+        if prob.w is not None or prob.fc is not None or prob.Tc > 0:
+            o.set_profile(prob.w, prob.fc, prob.Tc)
         o.set_coefficients(prob.T0, prob.scale, prob.expo, prob.B)
         o.set_bc(prob.ub_in, prob.ub_out)
         return o
@@ -181,13 +186,16 @@ class Oracle:
     def set_bc(self, ub_in=None, ub_out=None):
         _load().or_set_bc(self._h, _ptr(_c(ub_in)), _ptr(_c(ub_out)))
 
-    def volumes(self):
-        lib = _load()
+    def set_profile(self, w=None, fc=None, Tc=0.0):
+        """Weight w (cells) of F = (1/w) div(...), radial profile fc [nr] and
+        f_m threshold Tc; effective from the next set_coefficients."""
+        if _load().or_set_profile(self._h, _ptr(_c(w)), _ptr(_c(fc)), float(Tc)):
+            raise ValueError("non-positive weight or negative profile")
+
+    def volumes(self, weighted=False):
+        """Cell volumes V, or the weighted w V of the time derivative."""
         V = np.empty((self.nr, self.nt, self.np))
-        for i in range(self.nr):
-            for j in range(self.nt):
-                for k in range(self.np):
-                    V[i, j, k] = lib.or_volume(self._h, i, j, k)
+        _load().or_volumes(self._h, int(weighted), _ptr(V))
         return V
 
     def apply(self, u, affine=True):

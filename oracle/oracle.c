@@ -63,6 +63,9 @@ struct or_ctx {
     double *bhat;            /* corner unit field [3][(nr+1)(nt+1)np] */
     double *ub_in, *ub_out;  /* [nc][nt][np] */
     double *fbuf;            /* corner flux scratch [3][(nr+1)(nt+1)np] */
+    double *wgt;             /* cell weight w of F = (1/w) div(...), NULL: 1 */
+    double *fc;              /* radial profile f_c [nr], NULL: 1 */
+    double Tc;               /* f_m threshold, <= 0: f_m = 1 */
 };
 
 static size_t cell_ix(const or_ctx* o, int c, int i, int j, int k)
@@ -182,18 +185,72 @@ void or_destroy(or_ctx* o)
     if (!o) return;
     free(o->R); free(o->TH); free(o->PH); free(o->rc); free(o->tc); free(o->pc);
     free(o->coef); free(o->bhat); free(o->ub_in); free(o->ub_out); free(o->fbuf);
+    free(o->wgt); free(o->fc);
     free(o);
 }
 
-/* Lagged diffusivity (Eq. tc, T0 = previous temperature): c = scale*T0^expo,
- * or the constant `scale` when T0 is NULL.  B: corner field, normalised here
- * to bhat = B/|B| (zero where |B| = 0).  Returns 0, or -1 on a non-finite
- * or negative coefficient. */
+/* Full forms of Eqs. (visc) and (tc): the weight w of F = (1/w) div(...)
+ * (Eq. visc: rho; Eq. tc: 2 k rho / ((gamma - 1) m_p)), the radial profile
+ * f_c(r) and the threshold Tc of f_m (the conductivity is held at its Tc
+ * value below Tc: f_m(T0) T0^expo = Tc^expo there).  NULL / Tc <= 0: 1.
+ * Copied; used from the next or_set_coefficients on.  Returns -1 on a
+ * non-positive weight or a negative / non-finite profile value. */
+int or_set_profile(or_ctx* o, const double* w, const double* fc, double Tc)
+{
+    const size_t n = ncell(o);
+    free(o->wgt);
+    free(o->fc);
+    o->wgt = NULL;
+    o->fc = NULL;
+    o->Tc = Tc > 0.0 ? Tc : 0.0;
+    if (w) {
+        for (size_t m = 0; m < n; ++m)
+            if (!(w[m] > 0.0) || !isfinite(w[m])) return -1;
+        o->wgt = (double*)malloc(n * sizeof(double));
+        memcpy(o->wgt, w, n * sizeof(double));
+    }
+    if (fc) {
+        for (int i = 0; i < o->nr; ++i)
+            if (!(fc[i] >= 0.0) || !isfinite(fc[i])) return -1;
+        o->fc = (double*)malloc(o->nr * sizeof(double));
+        memcpy(o->fc, fc, o->nr * sizeof(double));
+    }
+    return 0;
+}
+
+/* weighted cell volume w V: the factor of dF in the time derivative */
+static double wvol(const or_ctx* o, int i, int j, int k)
+{
+    const double V = or_volume(o, i, j, k);
+    return o->wgt ? V * o->wgt[cell_ix(o, 0, i, j, k)] : V;
+}
+
+double or_wvolume(const or_ctx* o, int i, int j, int k) { return wvol(o, i, j, k); }
+
+/* all cell volumes V (weighted: w V) into out[nr][nt][np] */
+void or_volumes(const or_ctx* o, int weighted, double* out)
+{
+    for (int i = 0; i < o->nr; ++i)
+        for (int j = 0; j < o->nt; ++j)
+            for (int k = 0; k < o->np; ++k)
+                out[cell_ix(o, 0, i, j, k)] = weighted ? wvol(o, i, j, k) : or_volume(o, i, j, k);
+}
+
+/* Lagged diffusivity (Eq. tc, T0 = previous temperature):
+ * c = scale * f_c(r_i) * f_m(T0) * T0^expo, or scale * f_c(r_i) when T0 is
+ * NULL.  B: corner field, normalised here to bhat = B/|B| (zero where
+ * |B| = 0).  Returns 0, or -1 on a non-finite or negative coefficient. */
 int or_set_coefficients(or_ctx* o, const double* T0, double scale, double expo, const double* B)
 {
     const size_t n = ncell(o);
+    const size_t P = (size_t)o->nt * o->np;
     for (size_t m = 0; m < n; ++m) {
-        const double c = T0 ? scale * pow(T0[m], expo) : scale;
+        const double prof = o->fc ? o->fc[m / P] : 1.0;
+        double c = scale * prof;
+        if (T0) {
+            const double Te = (o->Tc > 0.0 && T0[m] < o->Tc) ? o->Tc : T0[m];
+            c = scale * prof * pow(Te, expo);
+        }
         if (!isfinite(c) || c < 0.0) return -1;
         o->coef[m] = c;
     }
@@ -269,7 +326,7 @@ static void apply_iso7(const or_ctx* o, int c, const double* u, double* F, int a
                     Lu += 0.5 * (cm + o->coef[cell_ix(o, 0, i, j, km)]) * trans_p(o, i, j, k) * (um - u[cell_ix(o, c, i, j, km)]);
                     Lu += 0.5 * (cm + o->coef[cell_ix(o, 0, i, j, kp)]) * trans_p(o, i, j, kp) * (um - u[cell_ix(o, c, i, j, kp)]);
                 }
-                F[m] = -Lu / or_volume(o, i, j, k);
+                F[m] = -Lu / wvol(o, i, j, k);
             }
 }
 
@@ -385,7 +442,7 @@ static void apply_aligned(or_ctx* o, int c, const double* u, double* F, int affi
                             const size_t q = corner_ix(o, ic, jc, kc);
                             Lu += f[q] * dg[0] + f[nn + q] * dg[1] + f[2 * nn + q] * dg[2];
                         }
-                F[cell_ix(o, c, i, j, k)] = -Lu / or_volume(o, i, j, k);
+                F[cell_ix(o, c, i, j, k)] = -Lu / wvol(o, i, j, k);
             }
 }
 
@@ -476,7 +533,7 @@ double or_dt_explicit(const or_ctx* o)
             for (int k = 0; k < o->np; ++k) {
                 double d, s;
                 row_bounds(o, i, j, k, &d, &s);
-                const double v = s / or_volume(o, i, j, k);
+                const double v = s / wvol(o, i, j, k);
                 if (v > rp) rp = v;
             }
         if (rp > rho) rho = rp;
@@ -670,7 +727,7 @@ static void be_matvec(or_ctx* o, const double* x, double* y, double dt, double* 
             for (int j = 0; j < o->nt; ++j)
                 for (int k = 0; k < o->np; ++k) {
                     const size_t m = c * N + cell_ix(o, 0, i, j, k);
-                    const double V = or_volume(o, i, j, k);
+                    const double V = wvol(o, i, j, k);
                     y[m] = V * x[m] + dt * (-V * tmp[m]);
                 }
 }
@@ -699,7 +756,7 @@ static int be_solve(or_ctx* o, double* u, double dt, double tol, int max_iter, i
         for (int j = 0; j < o->nt; ++j)
             for (int k = 0; k < o->np; ++k) {
                 const size_t m = cell_ix(o, 0, i, j, k);
-                D[m] = or_volume(o, i, j, k) + dt * Ld[m];
+                D[m] = wvol(o, i, j, k) + dt * Ld[m];
             }
     /* b = V u^n + dt h, with h = V F(0) the boundary-data part of F */
     or_apply(o, zero, tmp, 1);
@@ -708,7 +765,7 @@ static int be_solve(or_ctx* o, double* u, double dt, double tol, int max_iter, i
             for (int j = 0; j < o->nt; ++j)
                 for (int k = 0; k < o->np; ++k) {
                     const size_t m = c * N + cell_ix(o, 0, i, j, k);
-                    const double V = or_volume(o, i, j, k);
+                    const double V = wvol(o, i, j, k);
                     b[m] = V * u[m] + dt * V * tmp[m];
                 }
     memcpy(x, u, n * sizeof(double));

@@ -23,7 +23,10 @@ typedef struct {
 or_ctx* or_create(int nr, int nt, int np, int nc, const double* r_faces, const double* t_faces,
                   const double* p_faces, int op, int bc_in, int bc_out);
 void or_destroy(or_ctx* o);
+int or_set_profile(or_ctx* o, const double* w, const double* fc, double Tc);
 int or_set_coefficients(or_ctx* o, const double* T0, double scale, double expo, const double* B);
+double or_wvolume(const or_ctx* o, int i, int j, int k);
+void or_volumes(const or_ctx* o, int weighted, double* out);
 void or_set_bc(or_ctx* o, const double* ub_in, const double* ub_out);
 double or_volume(const or_ctx* o, int i, int j, int k);
 void or_apply(or_ctx* o, const double* u, double* F, int affine);

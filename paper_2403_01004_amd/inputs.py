@@ -178,6 +178,9 @@ class Problem:
     bc_in: str = "dirichlet"
     bc_out: str = "dirichlet"
     name: str = ""
+    w: np.ndarray | None = None    # (nr, nt, np) weight of F = (1/w) div(...)
+    fc: np.ndarray | None = None   # (nr,) radial profile of the coefficient
+    Tc: float = 0.0                # low-temperature threshold of f_m (0: none)
 
 
 def heat_iso(nr=32, nt=32, np_=64, seed=101, stretch=1.02):
