@@ -166,6 +166,23 @@ pa_status pa_bind_field(pa_ctx* ctx, double* u_dev);
 pa_status pa_set_coefficients(pa_ctx* ctx, const double* T0_dev, double scale, double expo,
                               const double* B_dev);
 
+/* Full forms of Eqs. (visc) and (tc): F = (1/w) div(c grad u) and
+ * (1/w) div(c bhat bhat . grad T), with
+ *   w_dev: device double[nr][nt][np], the weight of the time derivative
+ *          (Eq. visc: rho; Eq. tc: 2 k rho / ((gamma - 1) m_p)), > 0;
+ *          NULL for w = 1.  Copied.
+ *   fc:    host double[nr], the radial profile f_c(r) of the coefficient,
+ *          >= 0; NULL for 1.  Copied.
+ *   Tc:    threshold of f_m (Eq. tc cites it without a formula; here the
+ *          conductivity is held at its Tc value below Tc: f_m(T0) T0^expo =
+ *          Tc^expo for T0 < Tc); <= 0 for f_m = 1.
+ * The coefficient becomes c = scale f_c(r_i) f_m(T0) T0^expo (scale f_c(r_i)
+ * without T0); for Eq. (visc) pass T0 = nu(x) rho with expo 1.  w V replaces
+ * V in F, the explicit limit and the BE system (w V + dt L) x = w V u + dt h.
+ * Takes effect with the next pa_set_coefficients, which must follow.
+ * PA_ERR_ARG for a non-positive weight or a negative profile value. */
+pa_status pa_set_profile(pa_ctx* ctx, const double* w_dev, const double* fc, double Tc);
+
 /* Dirichlet boundary values at r_in and r_out, device double[ncomp][nt][np]
  * (copied; NULL leaves that side unchanged).  Ignored on no-flux sides. */
 pa_status pa_set_bc(pa_ctx* ctx, const double* ub_in_dev, const double* ub_out_dev);

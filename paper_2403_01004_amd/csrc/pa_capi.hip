@@ -50,7 +50,15 @@ struct pa_ctx {
     double* e64 = nullptr;
     float* e32 = nullptr;
     double* diagL = nullptr;
-    double* Dbuf = nullptr;  // Jacobi diagonal V + dt diag(L) of the current BE solve
+    double* Dbuf = nullptr;  // Jacobi diagonal w V + dt diag(L) of the current BE solve
+    // full operator forms: cell weight w of F = (1/w) div(...), radial
+    // profile f_c and f_m threshold of the coefficient
+    bool use_w = false;
+    double* w64 = nullptr;
+    float* w32 = nullptr;
+    bool use_fc = false;
+    double* fc_dev = nullptr;  // [nr]
+    double Tc = 0.0;
     bool have_coef = false;
     double dtE = 0.0;
     // boundary data
@@ -199,6 +207,8 @@ KArgs<T> base_args(pa_ctx* c, int r_lo, int r_hi)
         a.ub_out = (const T*)c->ub_out32;
     }
     a.cs = (T)c->cscale;
+    if constexpr (sizeof(T) == 8) a.wgt = c->use_w ? (const T*)c->w64 : nullptr;
+    else a.wgt = c->use_w ? (const T*)c->w32 : nullptr;
     return a;
 }
 
@@ -621,6 +631,45 @@ pa_status pa_set_bc(pa_ctx* c, const double* ui, const double* uo)
     return PA_OK;
 }
 
+pa_status pa_set_profile(pa_ctx* c, const double* w, const double* fc, double Tc)
+{
+    if (!c) return PA_ERR_ARG;
+    if (!isfinite(Tc)) return fail(c, PA_ERR_ARG, "Tc must be finite");
+    if (fc)
+        for (int i = 0; i < c->d.nr; ++i)
+            if (!(fc[i] >= 0.0) || !isfinite(fc[i]))
+                return fail(c, PA_ERR_ARG, "f_c must be finite and >= 0");
+    c->have_coef = false;
+    c->nn_cpl_ok = false;
+    c->Tc = Tc > 0.0 ? Tc : 0.0;
+    c->use_fc = fc != nullptr;
+    if (fc) {
+        if (!c->fc_dev) c->fc_dev = (double*)dev_alloc(c, sizeof(double) * c->d.nr);
+        if (!c->fc_dev) return fail(c, PA_ERR_ALLOC, "out of device memory");
+        HIPCHK(c, hipMemcpy(c->fc_dev, fc, sizeof(double) * c->d.nr, hipMemcpyHostToDevice));
+    }
+    c->use_w = w != nullptr;
+    if (w) {
+        if (!c->w64) c->w64 = (double*)dev_alloc(c, sizeof(double) * c->N);
+        if (c->fp32 && !c->w32) c->w32 = (float*)dev_alloc(c, sizeof(float) * c->N);
+        if (!c->w64 || (c->fp32 && !c->w32)) return fail(c, PA_ERR_ALLOC, "out of device memory");
+        launch_copy(w, c->w64, sizeof(double) * c->N, c->stream);
+        if (c->fp32) launch_f64_to_f32(c->w64, c->w32, c->N, c->stream);
+        launch_fill_zero(c->flag, sizeof(int), c->stream);
+        launch_nonpositive(c->w64, c->N, c->flag, c->stream);
+        HIPCHK(c, hipGetLastError());
+        pa_status s = sync_state(c);
+        if (s) return s;
+        if (*c->hflag) {
+            c->use_w = false;
+            return fail(c, PA_ERR_ARG, "weights must be finite and > 0");
+        }
+    }
+    HIPCHK(c, hipGetLastError());
+    c->err.clear();
+    return PA_OK;
+}
+
 pa_status pa_set_coefficients(pa_ctx* c, const double* T0, double scale, double expo,
                               const double* B)
 {
@@ -632,8 +681,10 @@ pa_status pa_set_coefficients(pa_ctx* c, const double* T0, double scale, double 
     c->nn_cpl_ok = false;
     launch_fill_zero(c->flag, sizeof(int), c->stream);
     const int N = (int)c->N;
-    launch_coef(T0, scale, expo, N, c->coef64, c->coef32, c->flag, c->stream);
-    c->coef_var = T0 != nullptr;
+    launch_coef(T0, scale, expo, c->use_fc ? c->fc_dev : nullptr, c->Tc, (int)c->P, N, c->coef64,
+                c->coef32, c->flag, c->stream);
+    c->coef_var = T0 != nullptr || c->use_fc;
+    const double* wv = c->use_w ? c->w64 : nullptr;
     c->cscale = scale;
     const Geo<double> g = geo(c, c->m64);
     int np_ = 0;
@@ -641,9 +692,10 @@ pa_status pa_set_coefficients(pa_ctx* c, const double* T0, double scale, double 
         CornerGeo cg{c->c_hr, c->c_wr, c->c_R, c->c_htt, c->c_sT, c->c_dpc};
         launch_corner_e(c->d.nr, c->d.nt, c->d.np, cg, c->coef64, B, c->e64, c->e32, c->flag,
                         c->stream);
-        launch_diag_aligned(g, c->e64, c->d.bc_in, c->d.bc_out, c->diagL, c->part, c->stream, &np_);
+        launch_diag_aligned(g, c->e64, wv, c->d.bc_in, c->d.bc_out, c->diagL, c->part, c->stream,
+                            &np_);
     } else {
-        launch_diag_iso7(g, c->coef_var ? c->coef64 : nullptr, scale, c->d.bc_in, c->d.bc_out,
+        launch_diag_iso7(g, c->coef_var ? c->coef64 : nullptr, scale, wv, c->d.bc_in, c->d.bc_out,
                          c->diagL, c->part, c->stream, &np_);
     }
     launch_reduce_max(c->part, np_, &c->st->gmax, c->stream);
@@ -1054,8 +1106,9 @@ void nn_static(pa_ctx* c, double dt, bool make_D)
                          c->d.bc_in, c->d.bc_out, c->nn_cpl, c->stream);
         c->nn_cpl_ok = true;
     }
-    if (make_D) launch_jacobi_D(g, dt, c->diagL, c->Dbuf, c->stream);
-    launch_nn_static(g, dt, c->Dbuf, c->nn_cpl, c->nn_xs, c->stream);
+    const double* wv = c->use_w ? c->w64 : nullptr;
+    if (make_D) launch_jacobi_D(g, dt, wv, c->diagL, c->Dbuf, c->stream);
+    launch_nn_static(g, dt, wv, c->Dbuf, c->nn_cpl, c->nn_xs, c->stream);
 }
 
 // out = N(x) on nb elements of nr x nt x np cells (activations kept in a1, a2)
@@ -1279,7 +1332,8 @@ pa_status pa_advance_be_pcg(pa_ctx* c, double dt, double tol, int32_t cycles, pa
             {
                 KScope t(c, PA_K_INIT);
                 if (any_dir) boundary_data(c, q);
-                launch_pcg_init<double>(g, nc, dtc, c->u, y0, any_dir ? q : nullptr, c->diagL,
+                launch_pcg_init<double>(g, nc, dtc, c->use_w ? c->w64 : nullptr, c->u, y0,
+                                        any_dir ? q : nullptr, c->diagL,
                                         c->Dbuf, r, p, c->nn_b, c->part, &nparts, c->stream);
             }
             {
@@ -1295,7 +1349,8 @@ pa_status pa_advance_be_pcg(pa_ctx* c, double dt, double tol, int32_t cycles, pa
             {
                 KScope t(c, PA_K_INIT);
                 if (any_dir) boundary_data(c, q);
-                launch_pcg_init<double>(g, nc, dtc, c->u, y0, any_dir ? q : nullptr, c->diagL,
+                launch_pcg_init<double>(g, nc, dtc, c->use_w ? c->w64 : nullptr, c->u, y0,
+                                        any_dir ? q : nullptr, c->diagL,
                                         c->Dbuf, r, p, nullptr, c->part, &nparts, c->stream);
             }
             {
@@ -1315,7 +1370,8 @@ pa_status pa_advance_be_pcg(pa_ctx* c, double dt, double tol, int32_t cycles, pa
             {
                 KScope t(c, PA_K_INIT);
                 if (any_dir) boundary_data(c, q);
-                launch_pcg_init<float>(g, nc, dtc, c->u, y0, any_dir ? q : nullptr, c->diagL,
+                launch_pcg_init<float>(g, nc, dtc, c->use_w ? c->w64 : nullptr, c->u, y0,
+                                       any_dir ? q : nullptr, c->diagL,
                                        c->Dbuf, r, p32, bvec, c->part, &nparts, c->stream);
             }
             int outer = 0;
@@ -1579,7 +1635,8 @@ pa_status pa_lpc_train(pa_ctx* c, double dt, const pa_lpc_train_opts* oin, pa_lp
     first_pass<double>(c, c->u, y0);
     int nparts = 0;
     if (any_dir) boundary_data(c, q);
-    launch_pcg_init<double>(g, 1, dt, c->u, y0, any_dir ? q : nullptr, c->diagL, c->Dbuf, r, p,
+    launch_pcg_init<double>(g, 1, dt, c->use_w ? c->w64 : nullptr, c->u, y0, any_dir ? q : nullptr,
+                            c->diagL, c->Dbuf, r, p,
                             c->nn_b, c->part, &nparts, S);
     launch_pcg_start(c->part, nparts, c->st, o.tol_star, c->opt.max_iter, 0, 0, 0.0, S);
     s = sync_state(c);

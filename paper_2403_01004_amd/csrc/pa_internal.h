@@ -61,6 +61,7 @@ struct KArgs {
     long long* part_idx;
     int* flag;        // non-finite flag (kFirst)
     const int* done;  // skip the launch when *done != 0 (PCG), may be null
+    const T* wgt;     // cell weight w of F = (1/w) div(...), [nr][nt][np], null for 1
 };
 
 // stencil launchers (pa_kernels.hip)
@@ -76,8 +77,8 @@ int blocks_per_plane(int op, int nt, int np);
 int stencil_tiles(int op, int nt, int np, int nlev, int rch, int nc);
 
 // setup kernels
-void launch_coef(const double* T0, double scale, double expo, int n, double* c64, float* c32,
-                 int* flag, hipStream_t s);
+void launch_coef(const double* T0, double scale, double expo, const double* fc, double Tc, int P,
+                 int n, double* c64, float* c32, int* flag, hipStream_t s);
 struct CornerGeo {
     const double* hr;   // [nr+1] radial centre distance at corner plane ic
     const double* wr;   // [nr+1] radial dual extent
@@ -88,10 +89,10 @@ struct CornerGeo {
 };
 void launch_corner_e(int nr, int nt, int np, const CornerGeo& cg, const double* coef,
                      const double* B, double* e64, float* e32, int* flag, hipStream_t s);
-void launch_diag_iso7(const Geo<double>& g, const double* coef, double cs, int bc_in, int bc_out,
-                      double* diag, double* part, hipStream_t s, int* nparts);
-void launch_diag_aligned(const Geo<double>& g, const double* e, int bc_in, int bc_out,
-                         double* diag, double* part, hipStream_t s, int* nparts);
+void launch_diag_iso7(const Geo<double>& g, const double* coef, double cs, const double* w,
+                      int bc_in, int bc_out, double* diag, double* part, hipStream_t s, int* nparts);
+void launch_diag_aligned(const Geo<double>& g, const double* e, const double* w, int bc_in,
+                         int bc_out, double* diag, double* part, hipStream_t s, int* nparts);
 
 // reductions and vector kernels (pa_vec.hip)
 struct DevState {
@@ -116,9 +117,9 @@ template <class T>
 void launch_ptl_finalize(const double* pval, const long long* pidx, int n, const T* u, const T* F,
                          int nc, int nr, int nt, int np, DevState* st, hipStream_t s);
 template <class PT>
-void launch_pcg_init(const Geo<double>& g, int nc, double dt, const double* u, const double* y0,
-                     const double* hF, const double* diagL, double* D, double* r, PT* p,
-                     double* b, double* part, int* nparts, hipStream_t s);
+void launch_pcg_init(const Geo<double>& g, int nc, double dt, const double* w, const double* u,
+                     const double* y0, const double* hF, const double* diagL, double* D, double* r,
+                     PT* p, double* b, double* part, int* nparts, hipStream_t s);
 template <class PT>
 void launch_pcg_resid(size_t N, int nc, const double* b, const double* q, const double* D,
                       double* r, PT* p, double* part, int* nparts, hipStream_t s);
@@ -158,8 +159,8 @@ void launch_nn_conv(int layer, int dir, int nb, int nr, int nt, int np, int per,
 int nn_wgrad_blocks(long npoints);
 void launch_nn_wgrad(int layer, int nb, int nr, int nt, int np, int per, const __bf16* X,
                      const __bf16* G, float* part, float* grad, hipStream_t s);
-void launch_nn_static(const Geo<double>& g, double dt, const double* D, const double* cpl,
-                      __bf16* x, hipStream_t s);
+void launch_nn_static(const Geo<double>& g, double dt, const double* w, const double* D,
+                      const double* cpl, __bf16* x, hipStream_t s);
 void launch_nn_c0(size_t N, const double* r, const double* D, const double* sigma, const int* done,
                   __bf16* x, hipStream_t s);
 // energy-norm training loss |P(r) - e|_M^2 / |e|_M^2 pieces
@@ -172,7 +173,8 @@ void launch_energy_gout(size_t N, const double* Md, const double* sig, const dou
 void launch_scal_reduce(const double* part, int n, const double* den, double scale, double* out,
                         hipStream_t s);
 void launch_sub(size_t N, const double* a, const double* b, double* out, hipStream_t s);
-void launch_jacobi_D(const Geo<double>& g, double dt, const double* dL, double* D, hipStream_t s);
+void launch_jacobi_D(const Geo<double>& g, double dt, const double* w, const double* dL, double* D,
+                     hipStream_t s);
 void launch_nn_unpack(size_t N, const __bf16* x, float* f, hipStream_t s);
 void launch_nn_apply(size_t N, const double* r, const double* D, const float* out,
                      const double* sigma, double* z, hipStream_t s);
@@ -197,5 +199,6 @@ void launch_f32_to_f64(const float* a, double* b, size_t n, hipStream_t s);
 void launch_copy(const void* a, void* b, size_t bytes, hipStream_t s);
 void launch_fill_zero(void* a, size_t bytes, hipStream_t s);
 void launch_nonfinite(const double* a, size_t n, int* flag, hipStream_t s);
+void launch_nonpositive(const double* a, size_t n, int* flag, hipStream_t s);  // !(a > 0) or NaN
 
 }  // namespace pa

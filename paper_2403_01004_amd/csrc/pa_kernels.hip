@@ -263,15 +263,17 @@ template <class T, bool CV, int MODE>
 struct Lev7 {
     T x, w, e, s, n;                  // u at own, phi-, phi+, theta-, theta+
     T cx, cw, ce, cs, cn;             // coefficient at the same points (CV)
+    T wt;                             // cell weight of the own cell (WT)
     Streams<T> st;                    // stage streams of the own cell
 };
 
-template <class T, bool CV, int MODE, bool VIRT>
+template <class T, bool CV, int MODE, bool VIRT, bool WT>
 __device__ __forceinline__ void fetch7(const KArgs<T>& a, const T* u, const T* y, size_t lb,
                                        unsigned pp, unsigned ow, unsigned oe, unsigned os,
                                        unsigned on, size_t sb, Lev7<T, CV, MODE>& R)
 {
     R.x = ldu<T, VIRT>(a, u, y, lb + pp);
+    if constexpr (WT) R.wt = a.wgt[lb + pp];
     R.w = ldu<T, VIRT>(a, u, y, lb + ow);
     R.e = ldu<T, VIRT>(a, u, y, lb + oe);
     R.s = ldu<T, VIRT>(a, u, y, lb + os);
@@ -302,7 +304,7 @@ struct Pt7 {
 // Rn (the level above).  Levels at or past i1 are computed but not stored:
 // the body has no data-dependent branches, and with the ring's roles
 // rotating between calls no register copy waits on a load in flight.
-template <class T, int MODE, bool VIRT, bool CV>
+template <class T, int MODE, bool VIRT, bool CV, bool WT>
 __device__ __forceinline__ void step7(const Geo<T>& g, const KArgs<T>& a, const T* u, const T* y,
                                       size_t cb, const Pt7<T>& t, int i, int i0, int i1,
                                       const T* lgr, const T* lgtr, const T* lvr,
@@ -313,8 +315,8 @@ __device__ __forceinline__ void step7(const Geo<T>& g, const KArgs<T>& a, const 
     const size_t P = (size_t)g.P;
     {
         const int lv = min(i + 2, nr - 1), ls = min(i + 2, i1 - 1);
-        fetch7<T, CV, MODE, VIRT>(a, u, y, (size_t)lv * P, t.pp, t.ow, t.oe, t.os, t.on,
-                                  cb + (size_t)ls * P + t.pp, Rp);
+        fetch7<T, CV, MODE, VIRT, WT>(a, u, y, (size_t)lv * P, t.pp, t.ow, t.oe, t.os, t.on,
+                                      cb + (size_t)ls * P + t.pp, Rp);
     }
     const int ic = min(i, nr - 1);
     const T half = T(0.5);
@@ -336,13 +338,13 @@ __device__ __forceinline__ void step7(const Geo<T>& g, const KArgs<T>& a, const 
     Lu += half * (cc + cn) * (gtri * t.An) * (uc - Rc.n);
     Lu += half * (cc + cw) * (gtri * t.Aw) * (uc - Rc.w);
     Lu += half * (cc + ce) * (gtri * t.Ae) * (uc - Rc.e);
-    const T V = lvr[il] * t.Ar;
+    const T V = WT ? lvr[il] * t.Ar * Rc.wt : lvr[il] * t.Ar;  // (w) V
     if (t.valid && i < i1) epilogue<T, MODE>(a, cb + (size_t)ic * P + t.pp, Lu, V, uc, Rc.st, acc);
     um = uc;
     cm = cc;
 }
 
-template <class T, int MODE, bool VIRT, bool CV>
+template <class T, int MODE, bool VIRT, bool CV, bool WT>
 __global__ __launch_bounds__(64 * W7) void k_iso7(Geo<T> g, KArgs<T> a)
 {
     const int L = xcd_tile();
@@ -402,21 +404,21 @@ __global__ __launch_bounds__(64 * W7) void k_iso7(Geo<T> g, KArgs<T> a)
             um = ldu<T, VIRT>(a, u, y, (size_t)(i0 - 1) * P + pp);
             if constexpr (CV) cm = a.coef[(size_t)(i0 - 1) * P + pp];
         }
-        fetch7<T, CV, MODE, VIRT>(a, u, y, (size_t)i0 * P, t.pp, t.ow, t.oe, t.os, t.on,
-                                  cb + (size_t)i0 * P + pp, R0);
+        fetch7<T, CV, MODE, VIRT, WT>(a, u, y, (size_t)i0 * P, t.pp, t.ow, t.oe, t.os, t.on,
+                                      cb + (size_t)i0 * P + pp, R0);
         {
             const int lv = min(i0 + 1, nr - 1), ls = min(i0 + 1, i1 - 1);
-            fetch7<T, CV, MODE, VIRT>(a, u, y, (size_t)lv * P, t.pp, t.ow, t.oe, t.os, t.on,
-                                      cb + (size_t)ls * P + pp, R1);
+            fetch7<T, CV, MODE, VIRT, WT>(a, u, y, (size_t)lv * P, t.pp, t.ow, t.oe, t.os, t.on,
+                                          cb + (size_t)ls * P + pp, R1);
         }
         // three levels per trip with the ring's roles rotating
         for (int i = i0; i < i1; i += 3) {
-            step7<T, MODE, VIRT, CV>(g, a, u, y, cb, t, i, i0, i1, lgr, lgtr, lvr, R0, R1, R2, um,
-                                     cm, acc);
-            step7<T, MODE, VIRT, CV>(g, a, u, y, cb, t, i + 1, i0, i1, lgr, lgtr, lvr, R1, R2, R0,
-                                     um, cm, acc);
-            step7<T, MODE, VIRT, CV>(g, a, u, y, cb, t, i + 2, i0, i1, lgr, lgtr, lvr, R2, R0, R1,
-                                     um, cm, acc);
+            step7<T, MODE, VIRT, CV, WT>(g, a, u, y, cb, t, i, i0, i1, lgr, lgtr, lvr, R0, R1, R2,
+                                         um, cm, acc);
+            step7<T, MODE, VIRT, CV, WT>(g, a, u, y, cb, t, i + 1, i0, i1, lgr, lgtr, lvr, R1, R2,
+                                         R0, um, cm, acc);
+            step7<T, MODE, VIRT, CV, WT>(g, a, u, y, cb, t, i + 2, i0, i1, lgr, lgtr, lvr, R2, R0,
+                                         R1, um, cm, acc);
         }
     }
     finish<T, MODE>(a, L, acc);
@@ -434,10 +436,11 @@ template <class T>
 struct LevA {
     T u, h;
     T e0r, e0t, e0p, e1r, e1t, e1p;
+    T wt;  // cell weight of the own cell at level ic - 1 (WT)
     Streams<T> s;
 };
 
-template <class T, int MODE, bool VIRT>
+template <class T, int MODE, bool VIRT, bool WT>
 __device__ __forceinline__ void fetchA(const KArgs<T>& a, const T* u, const T* y, const TileMap& tm,
                                        size_t cb, int P, int nr, int nt, int np, size_t nco,
                                        int ic, int i0, int i1, int cq0, int cq1, LevA<T>& R)
@@ -454,6 +457,7 @@ __device__ __forceinline__ void fetchA(const KArgs<T>& a, const T* u, const T* y
     R.e1p = a.e[2 * nco + qb + cq1];
     const int ls = min(max(ic - 1, i0), i1 - 1);
     load_streams<T, MODE>(a, cb + (size_t)ls * P + tm.own_off, R.s);
+    if constexpr (WT) R.wt = a.wgt[(size_t)ls * P + tm.own_off];
 }
 
 // Scatter weights for one corner plane: the cell's weight as the upper cell
@@ -540,7 +544,7 @@ struct PtA {
 // of plane ic + 2 into Rp, compute the plane's corner fluxes, gather the
 // upper share into carry and complete level ic - 1.  Planes past i1 are
 // computed but complete nothing.
-template <class T, int MODE, bool VIRT>
+template <class T, int MODE, bool VIRT, bool WT>
 __device__ __forceinline__ void stepA(const Geo<T>& g, const KArgs<T>& a, const T* u, const T* y,
                                       const TileMap& tm, const PtA& pt, ShA<T>& sh, size_t cb,
                                       size_t nco, T Ar, int ic, int i0, int i1,
@@ -552,7 +556,7 @@ __device__ __forceinline__ void stepA(const Geo<T>& g, const KArgs<T>& a, const 
         sh.su[bh][tm.own_slot] = Rc.u;
         if (tm.has_h) sh.su[bh][tm.h_slot] = Rc.h;
     }
-    fetchA<T, MODE, VIRT>(a, u, y, tm, cb, P, nr, nt, np, nco, ic + 2, i0, i1, pt.cq0, pt.cq1, Rp);
+    fetchA<T, MODE, VIRT, WT>(a, u, y, tm, cb, P, nr, nt, np, nco, ic + 2, i0, i1, pt.cq0, pt.cq1, Rp);
     __syncthreads();
     int kind = 0, gside = 0, bc = 0;
     const T* ubp = sh.ubi;
@@ -592,14 +596,14 @@ __device__ __forceinline__ void stepA(const Geo<T>& g, const KArgs<T>& a, const 
     const int i = ic - 1;
     if (i >= i0 && i < i1) {
         const T Lu = carry + dn;
-        const T V = sh.vr[i - i0] * Ar;
+        const T V = WT ? sh.vr[i - i0] * Ar * Rc.wt : sh.vr[i - i0] * Ar;  // (w) V
         const T uc = lo[tm.own_slot];
         if (tm.valid) epilogue<T, MODE>(a, cb + (size_t)i * P + tm.own_off, Lu, V, uc, Rc.s, acc);
     }
     carry = up;
 }
 
-template <class T, int MODE, bool VIRT>
+template <class T, int MODE, bool VIRT, bool WT>
 __global__ __launch_bounds__(kBlock) void k_aligned(Geo<T> g, KArgs<T> a)
 {
     __shared__ ShA<T> sh;
@@ -653,17 +657,19 @@ __global__ __launch_bounds__(kBlock) void k_aligned(Geo<T> g, KArgs<T> a)
             if (tm.has_h) sh.su[(i0 - 1) % 3][tm.h_slot] = ldu<T, VIRT>(a, u, y, lb + tm.h_off);
         }
         LevA<T> R0, R1, R2;
-        fetchA<T, MODE, VIRT>(a, u, y, tm, cb, P, nr, nt, np, nco, i0, i0, i1, pt.cq0, pt.cq1, R0);
-        fetchA<T, MODE, VIRT>(a, u, y, tm, cb, P, nr, nt, np, nco, i0 + 1, i0, i1, pt.cq0, pt.cq1, R1);
+        fetchA<T, MODE, VIRT, WT>(a, u, y, tm, cb, P, nr, nt, np, nco, i0, i0, i1, pt.cq0, pt.cq1, R0);
+        fetchA<T, MODE, VIRT, WT>(a, u, y, tm, cb, P, nr, nt, np, nco, i0 + 1, i0, i1, pt.cq0, pt.cq1,
+                                  R1);
         T carry = 0;
         // corner plane ic completes cell level ic-1 and starts level ic;
         // three planes per trip with the ring's roles rotating
         for (int ic = i0; ic <= i1; ic += 3) {
-            stepA<T, MODE, VIRT>(g, a, u, y, tm, pt, sh, cb, nco, Ar, ic, i0, i1, R0, R2, carry, acc);
-            stepA<T, MODE, VIRT>(g, a, u, y, tm, pt, sh, cb, nco, Ar, ic + 1, i0, i1, R1, R0, carry,
-                                 acc);
-            stepA<T, MODE, VIRT>(g, a, u, y, tm, pt, sh, cb, nco, Ar, ic + 2, i0, i1, R2, R1, carry,
-                                 acc);
+            stepA<T, MODE, VIRT, WT>(g, a, u, y, tm, pt, sh, cb, nco, Ar, ic, i0, i1, R0, R2, carry,
+                                     acc);
+            stepA<T, MODE, VIRT, WT>(g, a, u, y, tm, pt, sh, cb, nco, Ar, ic + 1, i0, i1, R1, R0,
+                                     carry, acc);
+            stepA<T, MODE, VIRT, WT>(g, a, u, y, tm, pt, sh, cb, nco, Ar, ic + 2, i0, i1, R2, R1,
+                                     carry, acc);
         }
     }
     finish<T, MODE>(a, L, acc);
@@ -676,20 +682,26 @@ static void go_iso7(const Geo<T>& g, const KArgs<T>& a, hipStream_t s)
 {
     const int nt = a.nbx * a.nrc * a.nc;
     if (a.rch > RCH_MAX) return;  // the host never asks for longer chunks
-    if (a.coef)
-        hipLaunchKernelGGL((k_iso7<T, MODE, VIRT, true>), dim3(grid_for_tiles(nt)), dim3(64 * W7), 0,
-                           s, g, a);
-    else
-        hipLaunchKernelGGL((k_iso7<T, MODE, VIRT, false>), dim3(grid_for_tiles(nt)), dim3(64 * W7), 0,
-                           s, g, a);
+    const dim3 gr(grid_for_tiles(nt)), bl(64 * W7);
+    if (a.coef) {
+        if (a.wgt) hipLaunchKernelGGL((k_iso7<T, MODE, VIRT, true, true>), gr, bl, 0, s, g, a);
+        else hipLaunchKernelGGL((k_iso7<T, MODE, VIRT, true, false>), gr, bl, 0, s, g, a);
+    } else {
+        if (a.wgt) hipLaunchKernelGGL((k_iso7<T, MODE, VIRT, false, true>), gr, bl, 0, s, g, a);
+        else hipLaunchKernelGGL((k_iso7<T, MODE, VIRT, false, false>), gr, bl, 0, s, g, a);
+    }
 }
 template <class T, int MODE, bool VIRT>
 static void go_aligned(const Geo<T>& g, const KArgs<T>& a, hipStream_t s)
 {
     const int nt = a.nbx * a.nrc * a.nc;
     if (a.rch > RCH_MAX) return;  // the host never asks for longer chunks
-    hipLaunchKernelGGL((k_aligned<T, MODE, VIRT>), dim3(grid_for_tiles(nt)), dim3(kBlock), 0, s,
-                       g, a);
+    if (a.wgt)
+        hipLaunchKernelGGL((k_aligned<T, MODE, VIRT, true>), dim3(grid_for_tiles(nt)), dim3(kBlock),
+                           0, s, g, a);
+    else
+        hipLaunchKernelGGL((k_aligned<T, MODE, VIRT, false>), dim3(grid_for_tiles(nt)), dim3(kBlock),
+                           0, s, g, a);
 }
 
 #define PA_DISPATCH(FN)                                                 \

@@ -305,27 +305,27 @@ void launch_nn_wgrad(int layer, int nb, int nr, int nt, int np, int per, const _
 
 // ---------------------------------------------------------------- features
 
-// Static input channels, once per solve: x[p][1] = V/D, x[p][2..7] =
+// Static input channels, once per solve: x[p][1] = w V/D, x[p][2..7] =
 // -dt L_{p,nb}/D for the six face neighbours (r-, r+, t-, t+, p-, p+).
-__global__ void k_nn_static(Geo<double> g, double dt, const double* D, const double* cpl,
-                            __bf16* x)
+__global__ void k_nn_static(Geo<double> g, double dt, const double* w, const double* D,
+                            const double* cpl, __bf16* x)
 {
     const unsigned N = (unsigned)g.nr * g.P;
     for (unsigned m = blockIdx.x * blockDim.x + threadIdx.x; m < N; m += gridDim.x * blockDim.x) {
         const unsigned i = m / g.P, pp = m - i * g.P, j = pp / g.np, k = pp - j * g.np;
-        const double V = g.vr[i] * g.vt[j] * g.vp[k];
+        const double V = g.vr[i] * g.vt[j] * g.vp[k] * (w ? w[m] : 1.0);
         const double d = D[m];
         x[(size_t)m * 8 + 1] = (__bf16)(float)(V / d);
         for (int q = 0; q < 6; ++q) x[(size_t)m * 8 + 2 + q] = (__bf16)(float)(-dt * cpl[(size_t)q * N + m] / d);
     }
 }
 
-void launch_nn_static(const Geo<double>& g, double dt, const double* D, const double* cpl,
-                      __bf16* x, hipStream_t s)
+void launch_nn_static(const Geo<double>& g, double dt, const double* w, const double* D,
+                      const double* cpl, __bf16* x, hipStream_t s)
 {
     const size_t N = (size_t)g.nr * g.P;
     hipLaunchKernelGGL(k_nn_static, dim3((unsigned)((N + 255) / 256 > 4096 ? 4096 : (N + 255) / 256)),
-                       dim3(256), 0, s, g, dt, D, cpl, x);
+                       dim3(256), 0, s, g, dt, w, D, cpl, x);
 }
 
 // Dynamic channel: x[p][0] = (r/D)/sigma (0 when sigma == 0)
@@ -350,21 +350,22 @@ void launch_nn_c0(size_t N, const double* r, const double* D, const double* sigm
 
 __global__ void k_sum_finish(const double* part, int n, double N, double* out);
 
-// Jacobi diagonal of the BE system: D = V + dt diag(L)
-__global__ void k_jacobi_D(Geo<double> g, double dt, const double* dL, double* D)
+// Jacobi diagonal of the BE system: D = w V + dt diag(L) (w null for 1)
+__global__ void k_jacobi_D(Geo<double> g, double dt, const double* w, const double* dL, double* D)
 {
     const unsigned N = (unsigned)g.nr * g.P;
     for (unsigned m = blockIdx.x * blockDim.x + threadIdx.x; m < N; m += gridDim.x * blockDim.x) {
         const unsigned i = m / g.P, pp = m - i * g.P, j = pp / g.np, k = pp - j * g.np;
-        D[m] = g.vr[i] * g.vt[j] * g.vp[k] + dt * dL[m];
+        D[m] = g.vr[i] * g.vt[j] * g.vp[k] * (w ? w[m] : 1.0) + dt * dL[m];
     }
 }
 
-void launch_jacobi_D(const Geo<double>& g, double dt, const double* dL, double* D, hipStream_t s)
+void launch_jacobi_D(const Geo<double>& g, double dt, const double* w, const double* dL, double* D,
+                     hipStream_t s)
 {
     const size_t N = (size_t)g.nr * g.P;
     hipLaunchKernelGGL(k_jacobi_D, dim3((unsigned)((N + 255) / 256 > 4096 ? 4096 : (N + 255) / 256)),
-                       dim3(256), 0, s, g, dt, dL, D);
+                       dim3(256), 0, s, g, dt, w, dL, D);
 }
 
 // Network input of one pair on the whole grid: x[.][0] = bf16((r/D)/sigma),

@@ -6,22 +6,30 @@
 namespace pa {
 
 
-__global__ void k_coef(const double* T0, double scale, double expo, int n, double* c64,
-                       float* c32, int* flag)
+// c = scale f_c(r_i) f_m(T0) T0^expo (f_m: the conductivity held at its Tc
+// value below Tc, Tc <= 0 for none), or scale f_c(r_i) without T0; f_c may
+// be null (1)
+__global__ void k_coef(const double* T0, double scale, double expo, const double* fc, double Tc,
+                       int P, int n, double* c64, float* c32, int* flag)
 {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= n) return;
-    const double c = T0 ? scale * pow(T0[m], expo) : scale;
+    const double prof = fc ? fc[m / P] : 1.0;
+    double c = scale * prof;
+    if (T0) {
+        const double Te = (Tc > 0.0 && T0[m] < Tc) ? Tc : T0[m];
+        c = scale * prof * pow(Te, expo);
+    }
     if (!isfinite(c) || c < 0.0) atomicOr(flag, 1);
     c64[m] = c;
     if (c32) c32[m] = (float)c;
 }
 
-void launch_coef(const double* T0, double scale, double expo, int n, double* c64, float* c32,
-                 int* flag, hipStream_t s)
+void launch_coef(const double* T0, double scale, double expo, const double* fc, double Tc, int P,
+                 int n, double* c64, float* c32, int* flag, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_coef, dim3((n + 255) / 256), dim3(256), 0, s, T0, scale, expo, n, c64,
-                       c32, flag);
+    hipLaunchKernelGGL(k_coef, dim3((n + 255) / 256), dim3(256), 0, s, T0, scale, expo, fc, Tc, P, n,
+                       c64, c32, flag);
 }
 
 // per-corner coefficients e_d = sqrt(W kappa_c) bhat_d / h_d
@@ -83,10 +91,11 @@ void launch_corner_e(int nr, int nt, int np, const CornerGeo& cg, const double* 
                        np, cg, coef, B, e64, e32, flag);
 }
 
-// diag(L) and the Gershgorin row bound sum_n |L_mn| / V_m (per-block maxima)
+// diag(L) and the Gershgorin row bound sum_n |L_mn| / (w_m V_m) (per-block
+// maxima; w the cell weight, null for 1)
 __global__ __launch_bounds__(kBlock) void k_diag_iso7(Geo<double> g, const double* coef,
-                                                      double cs, int bc_in, int bc_out,
-                                                      double* diag, double* part)
+                                                      double cs, const double* w, int bc_in,
+                                                      int bc_out, double* diag, double* part)
 {
     __shared__ double lds[kBlock / 64];
     const int nr = g.nr, nt = g.nt, np = g.np, P = g.P;
@@ -110,7 +119,7 @@ __global__ __launch_bounds__(kBlock) void k_diag_iso7(Geo<double> g, const doubl
         C = 0.5 * (cc + cf(rb + km)) * (g.gtr[i] * g.gpt[j] * g.gpp[k]); d += C; off += C;
         C = 0.5 * (cc + cf(rb + kp)) * (g.gtr[i] * g.gpt[j] * g.gpp[kp]); d += C; off += C;
         diag[m] = d;
-        rho = (d + off) / (g.vr[i] * vt * vp);
+        rho = (d + off) / (g.vr[i] * vt * vp * (w ? w[m] : 1.0));
     }
     // block maximum (values are >= 0)
     double v = rho;
@@ -126,8 +135,8 @@ __global__ __launch_bounds__(kBlock) void k_diag_iso7(Geo<double> g, const doubl
 }
 
 __global__ __launch_bounds__(kBlock) void k_diag_aligned(Geo<double> g, const double* e,
-                                                         int bc_in, int bc_out, double* diag,
-                                                         double* part)
+                                                         const double* wc, int bc_in, int bc_out,
+                                                         double* diag, double* part)
 {
     __shared__ double lds[kBlock / 64];
     const int nr = g.nr, nt = g.nt, np = g.np, P = g.P;
@@ -173,7 +182,7 @@ __global__ __launch_bounds__(kBlock) void k_diag_aligned(Geo<double> g, const do
             }
         }
         diag[m] = d;
-        rho = s / (g.vr[i] * g.vt[j] * g.vp[k]);
+        rho = s / (g.vr[i] * g.vt[j] * g.vp[k] * (wc ? wc[m] : 1.0));
     }
     double v = rho;
 #pragma unroll
@@ -187,23 +196,23 @@ __global__ __launch_bounds__(kBlock) void k_diag_aligned(Geo<double> g, const do
     }
 }
 
-void launch_diag_iso7(const Geo<double>& g, const double* coef, double cs, int bc_in, int bc_out,
-                      double* diag, double* part, hipStream_t s, int* nparts)
+void launch_diag_iso7(const Geo<double>& g, const double* coef, double cs, const double* w,
+                      int bc_in, int bc_out, double* diag, double* part, hipStream_t s, int* nparts)
 {
     const size_t N = (size_t)g.nr * g.P;
     const int nb = (int)((N + kBlock - 1) / kBlock);
     *nparts = nb;
-    hipLaunchKernelGGL(k_diag_iso7, dim3(nb), dim3(kBlock), 0, s, g, coef, cs, bc_in, bc_out, diag,
+    hipLaunchKernelGGL(k_diag_iso7, dim3(nb), dim3(kBlock), 0, s, g, coef, cs, w, bc_in, bc_out, diag,
                        part);
 }
 
-void launch_diag_aligned(const Geo<double>& g, const double* e, int bc_in, int bc_out,
-                         double* diag, double* part, hipStream_t s, int* nparts)
+void launch_diag_aligned(const Geo<double>& g, const double* e, const double* w, int bc_in,
+                         int bc_out, double* diag, double* part, hipStream_t s, int* nparts)
 {
     const size_t N = (size_t)g.nr * g.P;
     const int nb = (int)((N + kBlock - 1) / kBlock);
     *nparts = nb;
-    hipLaunchKernelGGL(k_diag_aligned, dim3(nb), dim3(kBlock), 0, s, g, e, bc_in, bc_out, diag,
+    hipLaunchKernelGGL(k_diag_aligned, dim3(nb), dim3(kBlock), 0, s, g, e, w, bc_in, bc_out, diag,
                        part);
 }
 

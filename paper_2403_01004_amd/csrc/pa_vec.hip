@@ -260,7 +260,8 @@ __device__ __forceinline__ void block_partials(const double (&v)[NV], double* pa
 // partials <r,z>, <r,r>, <b,b>.
 template <class PT>
 __global__ __launch_bounds__(kBlock) void k_pcg_init(Geo<double> g, int nc, double dt,
-                                                     const double* u, const double* y0,
+                                                     const double* w, const double* u,
+                                                     const double* y0,
                                                      const double* hF, const double* dL,
                                                      double* Dout, double* r, PT* p, double* bout,
                                                      double* part)
@@ -271,7 +272,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(Geo<double> g, int nc, doub
     for (unsigned cell = blockIdx.x * blockDim.x + threadIdx.x; cell < N;
          cell += gridDim.x * blockDim.x) {
         const unsigned i = cell / P, pp = cell - i * P, j = pp / (unsigned)np, k = pp - j * np;
-        const double V = g.vr[i] * g.vt[j] * g.vp[k];
+        const double V = g.vr[i] * g.vt[j] * g.vp[k] * (w ? w[cell] : 1.0);  // w V
         const double D = V + dt * dL[cell];
         Dout[cell] = D;
         const bool bnd = hF && (i == 0 || i == (unsigned)nr - 1);
@@ -293,21 +294,21 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(Geo<double> g, int nc, doub
 }
 
 template <class PT>
-void launch_pcg_init(const Geo<double>& g, int nc, double dt, const double* u, const double* y0,
-                     const double* hF, const double* diagL, double* D, double* r, PT* p,
-                     double* b, double* part, int* nparts, hipStream_t s)
+void launch_pcg_init(const Geo<double>& g, int nc, double dt, const double* w, const double* u,
+                     const double* y0, const double* hF, const double* diagL, double* D, double* r,
+                     PT* p, double* b, double* part, int* nparts, hipStream_t s)
 {
     const int nb = vec_blocks((size_t)g.nr * g.P);
     *nparts = nb;
-    hipLaunchKernelGGL((k_pcg_init<PT>), dim3(nb), dim3(kBlock), 0, s, g, nc, dt, u, y0, hF, diagL,
-                       D, r, p, b, part);
+    hipLaunchKernelGGL((k_pcg_init<PT>), dim3(nb), dim3(kBlock), 0, s, g, nc, dt, w, u, y0, hF,
+                       diagL, D, r, p, b, part);
 }
 template void launch_pcg_init<double>(const Geo<double>&, int, double, const double*, const double*,
-                                      const double*, const double*, double*, double*, double*,
-                                      double*, double*, int*, hipStream_t);
+                                      const double*, const double*, const double*, double*,
+                                      double*, double*, double*, double*, int*, hipStream_t);
 template void launch_pcg_init<float>(const Geo<double>&, int, double, const double*, const double*,
-                                     const double*, const double*, double*, double*, float*,
-                                     double*, double*, int*, hipStream_t);
+                                     const double*, const double*, const double*, double*,
+                                     double*, float*, double*, double*, int*, hipStream_t);
 
 // Defect correction: r = b - q (q = M x from an FP64 matvec), p = r/D;
 // partials <r,z>, <r,r>, <b,b>.
@@ -555,6 +556,18 @@ void launch_fill_zero(void* a, size_t bytes, hipStream_t s)
     hipLaunchKernelGGL(k_zero1, dim3(vec_blocks(bytes)), dim3(kBlock), 0, s, (unsigned char*)a,
                        bytes);
 }
+__global__ void k_nonpositive(const double* a, size_t n, int* flag)
+{
+    for (size_t m = (size_t)blockIdx.x * blockDim.x + threadIdx.x; m < n;
+         m += (size_t)gridDim.x * blockDim.x)
+        if (!(a[m] > 0.0) || !isfinite(a[m])) atomicOr(flag, 1);
+}
+
+void launch_nonpositive(const double* a, size_t n, int* flag, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_nonpositive, dim3(vec_blocks(n)), dim3(kBlock), 0, s, a, n, flag);
+}
+
 void launch_nonfinite(const double* a, size_t n, int* flag, hipStream_t s)
 {
     hipLaunchKernelGGL(k_nonfinite, dim3(vec_blocks(n)), dim3(kBlock), 0, s, a, n, flag);

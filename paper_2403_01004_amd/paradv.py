@@ -28,7 +28,8 @@ BCS = {"dirichlet": 0, "noflux": 1}
 PRECS = {"fp64": 0, "fp32": 1}
 
 EXPORTS = ["pa_init", "pa_destroy", "pa_last_error", "pa_default_options", "pa_set_options",
-           "pa_bind_field", "pa_set_coefficients", "pa_set_bc", "pa_dt_explicit", "pa_apply",
+           "pa_bind_field", "pa_set_profile", "pa_set_coefficients", "pa_set_bc", "pa_dt_explicit",
+           "pa_apply",
            "pa_diag", "pa_compute_ptl", "pa_compute_ptl_full", "pa_advance_rkl2", "pa_advance_rkg2",
            "pa_advance_be_pcg", "pa_lpc_default_train_opts", "pa_lpc_set_weights",
            "pa_lpc_get_weights", "pa_lpc_features", "pa_lpc_apply", "pa_lpc_loss_grad",
@@ -113,6 +114,7 @@ def load(path: str = LIB_PATH):
         "pa_set_options": (I32, [V, P(pa_opts)]),
         "pa_bind_field": (I32, [V, V]),
         "pa_set_coefficients": (I32, [V, V, D, D, V]),
+        "pa_set_profile": (I32, [V, V, V, D]),
         "pa_set_bc": (I32, [V, V, V]),
         "pa_dt_explicit": (I32, [V, P(D)]),
         "pa_apply": (I32, [V, V, V, I32]),
@@ -166,6 +168,10 @@ def pa_set_options(ctx, opts):
 
 def pa_bind_field(ctx, u_ptr):
     return load().pa_bind_field(ctx, u_ptr)
+
+
+def pa_set_profile(ctx, w_ptr, fc_host_ptr, Tc):
+    return load().pa_set_profile(ctx, w_ptr, fc_host_ptr, Tc)
 
 
 def pa_set_coefficients(ctx, T0_ptr, scale, expo, B_ptr):
@@ -368,6 +374,17 @@ class Operator:
         self._check(pa_set_coefficients(self.ctx, self._p(T0), float(scale), float(expo),
                                         self._p(B)))
 
+    def set_profile(self, w=None, fc=None, Tc=0.0):
+        """Weight w (cells), radial profile fc [nr] and f_m threshold Tc of
+        the full operator forms; set_coefficients must follow."""
+        w = self._dev(w, (self.nr, self.nt, self.np))
+        fch = None if fc is None else np.ascontiguousarray(fc, dtype=np.float64)
+        self._keep["fc"] = fch
+        self._keep["w"] = w
+        self._check(pa_set_profile(self.ctx, self._p(w),
+                                   None if fch is None else fch.ctypes.data_as(ctypes.c_void_p),
+                                   float(Tc)))
+
     def set_bc(self, ub_in=None, ub_out=None):
         shp = (self.nc, self.nt, self.np)
         a, b = self._dev(ub_in, shp), self._dev(ub_out, shp)
@@ -377,6 +394,8 @@ class Operator:
     @classmethod
     def from_problem(cls, prob, prec="fp64", device="cuda"):
         o = cls(prob.mesh, prob.op, prob.ncomp, prob.bc_in, prob.bc_out, prec, device)
+        if prob.w is not None or prob.fc is not None or prob.Tc > 0:
+            o.set_profile(prob.w, prob.fc, prob.Tc)
         o.set_coefficients(prob.T0, prob.scale, prob.expo, prob.B)
         o.set_bc(prob.ub_in, prob.ub_out)
         return o
