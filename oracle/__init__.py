@@ -22,6 +22,7 @@ MAX_LOG = 4096
 OPS = {"iso7": 0, "aligned": 1}
 BCS = {"dirichlet": 0, "noflux": 1}
 STS = {"rkl2": 0, "rkg2": 1}
+PCS = {"jacobi": 0, "bilu0": 2}
 
 
 def build(force: bool = True) -> str:
@@ -85,6 +86,13 @@ def _load():
     lib.or_sts_stages.argtypes = [i, d, i]
     lib.or_num_threads.restype = i
     lib.or_num_threads.argtypes = []
+    lib.or_set_pc.restype = i
+    lib.or_set_pc.argtypes = [vp, i, i, i, i]
+    ip = ctypes.POINTER(ctypes.c_int)
+    lib.or_bilu0_export.restype = i
+    lib.or_bilu0_export.argtypes = [vp, d, ip, ip, _D, _D, i]
+    lib.or_precondition.restype = i
+    lib.or_precondition.argtypes = [vp, d, _D, _D]
     lib.or_advance.restype = i
     lib.or_advance.argtypes = [vp, _D, d, i, i, i, i, i, d, i, i, i, d, _D, i,
                                ctypes.POINTER(_Stats)]
@@ -246,9 +254,39 @@ class Oracle:
                              s_override=s_override, max_cycles=max_cycles,
                              ptl_floor=ptl_floor, replay=replay)
 
+    def set_pc(self, pc="jacobi", block=(8, 4, 16)):
+        """Preconditioner of the BE solves: point Jacobi (PC1) or block ILU(0)
+        (PC2) on boxes of block = (r, theta, phi) cells (7-point operator)."""
+        if _load().or_set_pc(self._h, PCS[pc], *[int(b) for b in block]):
+            raise ValueError("block ILU(0) needs the 7-point operator and a positive box")
+
+    def bilu0_csr(self, dt):
+        """(rowp, col, m0, lu): the block-diagonal part of M = wV + dt L in CSR
+        (columns ascending) and its ILU(0) factors in the same pattern (strict
+        lower part: L with unit diagonal implied; diagonal and upper: U)."""
+        n = self.nr * self.nt * self.np
+        rowp = np.zeros(n + 1, dtype=np.intc)
+        col = np.zeros(7 * n, dtype=np.intc)
+        m0, lu = np.zeros(7 * n), np.zeros(7 * n)
+        ip = ctypes.POINTER(ctypes.c_int)
+        nnz = _load().or_bilu0_export(self._h, float(dt), rowp.ctypes.data_as(ip),
+                                      col.ctypes.data_as(ip), _ptr(m0), _ptr(lu), 7 * n)
+        if nnz < 0:
+            raise ValueError("block ILU(0) export failed (%d)" % nnz)
+        return rowp, col[:nnz], m0[:nnz], lu[:nnz]
+
+    def precondition(self, r, dt):
+        """z = P^{-1} r (all components) with the preconditioner of set_pc."""
+        r = _c(r).reshape(self.field_shape)
+        z = np.empty_like(r)
+        if _load().or_precondition(self._h, float(dt), _ptr(r), _ptr(z)):
+            raise ValueError("preconditioner set-up failed")
+        return z
+
     def advance_be(self, u, dt, tol=1e-10, cycles=0, max_iter=10000, force_iters=0,
                    max_cycles=100000, ptl_floor=1.0, replay=None):
-        """Backward Euler + Jacobi PCG advance, PTL-cycled when cycles == 0."""
+        """Backward Euler + PCG advance (preconditioner of set_pc, Jacobi by
+        default), PTL-cycled when cycles == 0."""
         return self._advance(u, dt, cycles, 1, tol=tol, max_iter=max_iter,
                              force_iters=force_iters, max_cycles=max_cycles,
                              ptl_floor=ptl_floor, replay=replay)

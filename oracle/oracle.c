@@ -33,9 +33,12 @@
  *     (2014), the paper's reference for RKL2 (Sec. 3.1); stage counts from
  *     the App. A formula (RKG2) and its RKL2 analogue, with the odd-stage
  *     rule of Sec. 3.1 / App. A;
- *   - Backward Euler (Sec. 3.1) solved by textbook point-Jacobi
- *     preconditioned conjugate gradients (PC1 of Sec. 3.1) on the
- *     symmetric system (V + dt L) x = V u^n + dt h.
+ *   - Backward Euler (Sec. 3.1) solved by textbook preconditioned conjugate
+ *     gradients on the symmetric system (V + dt L) x = V u^n + dt h, with
+ *     point Jacobi (PC1 of Sec. 3.1) or non-overlapping block ILU(0) (PC2 of
+ *     Sec. 3.1): M restricted to boxes of cells, each box factored by
+ *     incomplete LU with the sparsity of M (Saad's IKJ elimination, natural
+ *     cell order).
  *
  * Index conventions: cell (c,i,j,k) -> ((c*nr+i)*nt+j)*np+k, k fastest;
  * corner (ic,jc,kc) with ic in [0,nr], jc in [0,nt], kc in [0,np) sits at
@@ -66,6 +69,8 @@ struct or_ctx {
     double *wgt;             /* cell weight w of F = (1/w) div(...), NULL: 1 */
     double *fc;              /* radial profile f_c [nr], NULL: 1 */
     double Tc;               /* f_m threshold, <= 0: f_m = 1 */
+    int pcond;               /* BE preconditioner: 0 point Jacobi, 2 block ILU(0) */
+    int pbi, pbj, pbk;       /* block ILU(0) box in cells (r, theta, phi) */
 };
 
 static size_t cell_ix(const or_ctx* o, int c, int i, int j, int k)
@@ -707,6 +712,219 @@ static void sts_cycle(or_ctx* o, double* u, double dt, int kind, int s)
     free(u0); free(y0); free(ukm2); free(ukm1); free(uk); free(Fk);
 }
 
+/* ------------------------------------------------- block ILU(0) (PC2) */
+
+/* PC2 of Sec. 3.1: non-overlapping ILU(0).  The paper names the method only
+ * (its implementation is in the first paper of the series); the reading
+ * here: the cells are split into boxes of pbi x pbj x pbk cells starting at
+ * cell 0 in each direction (the last box in a direction may be short); the
+ * preconditioner is P = L U with L U the incomplete LU factorisation, with
+ * the sparsity of M and cells in their natural (i, j, k) order, of the
+ * block-diagonal part of M = wV + dt L (every coupling between cells of
+ * different boxes dropped).  The periodic phi coupling between k = np-1 and
+ * k = 0 is always dropped, also when both cells lie in one box, so that each
+ * box is a plain sub-grid.  Implemented for the 7-point operator. */
+
+#define OR_PC_JACOBI 0
+#define OR_PC_BILU0 2
+
+typedef struct {
+    int n;
+    int* rowp;      /* CSR, columns ascending, every row holds its diagonal */
+    int* col;
+    double* m0;     /* entries of the block-diagonal part of M */
+    double* lu;     /* after factoring: strict lower part L (unit diagonal
+                       implied), diagonal and upper part U */
+    int* dpos;      /* position of the diagonal in each row */
+} or_csr;
+
+static void csr_free(or_csr* A)
+{
+    free(A->rowp); free(A->col); free(A->m0); free(A->lu); free(A->dpos);
+    memset(A, 0, sizeof(*A));
+}
+
+static int same_box(const or_ctx* o, int i, int j, int k, int i2, int j2, int k2)
+{
+    return i / o->pbi == i2 / o->pbi && j / o->pbj == j2 / o->pbj && k / o->pbk == k2 / o->pbk;
+}
+
+/* the block-diagonal part of M = wV + dt L for the 7-point operator: the
+ * off-diagonal entry of a face is -dt c_f A_f/d_f (the coupling of
+ * apply_iso7), the diagonal wV + dt diag(L) */
+static int bilu0_assemble(const or_ctx* o, double dt, or_csr* A)
+{
+    if (o->op != OR_ISO7) return 3;
+    const int nr = o->nr, nt = o->nt, np = o->np;
+    const int n = (int)ncell(o);
+    A->n = n;
+    A->rowp = (int*)malloc((size_t)(n + 1) * sizeof(int));
+    A->col = (int*)malloc((size_t)7 * n * sizeof(int));
+    A->m0 = (double*)malloc((size_t)7 * n * sizeof(double));
+    A->lu = (double*)malloc((size_t)7 * n * sizeof(double));
+    A->dpos = (int*)malloc((size_t)n * sizeof(int));
+    double* Ld = (double*)malloc((size_t)n * sizeof(double));
+    or_diag(o, Ld);
+    int q = 0;
+    for (int i = 0; i < nr; ++i)
+        for (int j = 0; j < nt; ++j)
+            for (int k = 0; k < np; ++k) {
+                const int m = (int)cell_ix(o, 0, i, j, k);
+                const double cm = o->coef[m];
+                A->rowp[m] = q;
+                /* neighbours in ascending cell order: r-, theta-, phi-, self,
+                 * phi+, theta+, r+ (phi without the periodic wrap) */
+                const int di[7] = {-1, 0, 0, 0, 0, 0, 1};
+                const int dj[7] = {0, -1, 0, 0, 0, 1, 0};
+                const int dk[7] = {0, 0, -1, 0, 1, 0, 0};
+                for (int t = 0; t < 7; ++t) {
+                    const int i2 = i + di[t], j2 = j + dj[t], k2 = k + dk[t];
+                    if (i2 < 0 || i2 >= nr || j2 < 0 || j2 >= nt || k2 < 0 || k2 >= np) continue;
+                    if (!same_box(o, i, j, k, i2, j2, k2)) continue;
+                    const int nb = (int)cell_ix(o, 0, i2, j2, k2);
+                    double v;
+                    if (t == 3) {
+                        v = wvol(o, i, j, k) + dt * Ld[m];
+                        A->dpos[m] = q;
+                    } else {
+                        const double cf = 0.5 * (cm + o->coef[nb]);
+                        double tr;
+                        if (di[t]) tr = trans_r(o, di[t] < 0 ? i : i + 1, j, k);
+                        else if (dj[t]) tr = trans_t(o, i, dj[t] < 0 ? j : j + 1, k);
+                        else tr = trans_p(o, i, j, dk[t] < 0 ? k : k + 1);
+                        v = -dt * cf * tr;
+                    }
+                    A->col[q] = nb;
+                    A->m0[q] = v;
+                    A->lu[q] = v;
+                    ++q;
+                }
+            }
+    A->rowp[n] = q;
+    free(Ld);
+    return 0;
+}
+
+/* ILU(0) in place on A->lu, IKJ order: for each row i and each k < i in the
+ * row, l_ik = a_ik / u_kk, then a_ij -= l_ik u_kj for the j > k of row k
+ * that are in the pattern of row i.  7 (not factorable) on a pivot that is
+ * not positive and finite. */
+static int bilu0_factor(or_csr* A)
+{
+    const int n = A->n;
+    int* pos = (int*)malloc((size_t)n * sizeof(int));
+    for (int t = 0; t < n; ++t) pos[t] = -1;
+    int status = 0;
+    for (int i = 0; i < n && !status; ++i) {
+        for (int p = A->rowp[i]; p < A->rowp[i + 1]; ++p) pos[A->col[p]] = p;
+        for (int p = A->rowp[i]; p < A->dpos[i]; ++p) {
+            const int k = A->col[p];
+            A->lu[p] /= A->lu[A->dpos[k]];
+            const double lik = A->lu[p];
+            for (int qq = A->dpos[k] + 1; qq < A->rowp[k + 1]; ++qq) {
+                const int jj = pos[A->col[qq]];
+                if (jj >= 0) A->lu[jj] -= lik * A->lu[qq];
+            }
+        }
+        const double piv = A->lu[A->dpos[i]];
+        if (!(piv > 0.0) || !isfinite(piv)) status = 7;
+        for (int p = A->rowp[i]; p < A->rowp[i + 1]; ++p) pos[A->col[p]] = -1;
+    }
+    free(pos);
+    return status;
+}
+
+static int bilu0_make(const or_ctx* o, double dt, or_csr* A)
+{
+    int e = bilu0_assemble(o, dt, A);
+    if (!e) e = bilu0_factor(A);
+    return e;
+}
+
+/* z = U^{-1} L^{-1} r on one component */
+static void bilu0_solve(const or_csr* A, const double* r, double* z)
+{
+    const int n = A->n;
+    for (int i = 0; i < n; ++i) {
+        double s = r[i];
+        for (int p = A->rowp[i]; p < A->dpos[i]; ++p) s -= A->lu[p] * z[A->col[p]];
+        z[i] = s;
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double s = z[i];
+        for (int p = A->dpos[i] + 1; p < A->rowp[i + 1]; ++p) s -= A->lu[p] * z[A->col[p]];
+        z[i] = s / A->lu[A->dpos[i]];
+    }
+}
+
+/* z = P^{-1} r for every component: r / D (Jacobi) or the block ILU(0) solve */
+static void precondition(const or_ctx* o, const or_csr* F, const double* D, const double* r,
+                         double* z)
+{
+    const size_t N = ncell(o);
+    for (int c = 0; c < o->nc; ++c) {
+        if (o->pcond == OR_PC_BILU0) bilu0_solve(F, r + c * N, z + c * N);
+        else
+            for (size_t m = 0; m < N; ++m) z[c * N + m] = r[c * N + m] / D[m];
+    }
+}
+
+int or_set_pc(or_ctx* o, int pc, int bi, int bj, int bk)
+{
+    if (pc == OR_PC_JACOBI) { o->pcond = pc; return 0; }
+    if (pc != OR_PC_BILU0 || o->op != OR_ISO7 || bi < 1 || bj < 1 || bk < 1) return 1;
+    o->pcond = pc;
+    o->pbi = bi; o->pbj = bj; o->pbk = bk;
+    return 0;
+}
+
+/* The block ILU(0) factors at dt in CSR form (for the tests): rowp [n+1],
+ * col / m0 / lu [cap].  Returns the number of stored entries, or -(status)
+ * (-1 no block ILU(0) set, -2 cap too small, -3 operator, -7 pivot). */
+int or_bilu0_export(const or_ctx* o, double dt, int* rowp, int* col, double* m0, double* lu,
+                    int cap)
+{
+    if (o->pcond != OR_PC_BILU0) return -1;
+    or_csr A;
+    memset(&A, 0, sizeof(A));
+    int e = bilu0_make(o, dt, &A);
+    if (e) { csr_free(&A); return -e; }
+    const int nnz = A.rowp[A.n];
+    if (nnz > cap) { csr_free(&A); return -2; }
+    memcpy(rowp, A.rowp, (size_t)(A.n + 1) * sizeof(int));
+    memcpy(col, A.col, (size_t)nnz * sizeof(int));
+    memcpy(m0, A.m0, (size_t)nnz * sizeof(double));
+    memcpy(lu, A.lu, (size_t)nnz * sizeof(double));
+    csr_free(&A);
+    return nnz;
+}
+
+/* z = P^{-1} r (all components) with the preconditioner set by or_set_pc */
+int or_precondition(const or_ctx* o, double dt, const double* r, double* z)
+{
+    const size_t N = ncell(o);
+    or_csr A;
+    memset(&A, 0, sizeof(A));
+    double* D = NULL;
+    if (o->pcond == OR_PC_BILU0) {
+        const int e = bilu0_make(o, dt, &A);
+        if (e) { csr_free(&A); return e; }
+    } else {
+        D = (double*)malloc(N * sizeof(double));
+        or_diag(o, D);
+        for (int i = 0; i < o->nr; ++i)
+            for (int j = 0; j < o->nt; ++j)
+                for (int k = 0; k < o->np; ++k) {
+                    const size_t m = cell_ix(o, 0, i, j, k);
+                    D[m] = wvol(o, i, j, k) + dt * D[m];
+                }
+    }
+    precondition(o, &A, D, r, z);
+    free(D);
+    csr_free(&A);
+    return 0;
+}
+
 /* ------------------------------------------------------------ BE + PCG */
 
 static double dot(const double* a, const double* b, size_t n)
@@ -733,14 +951,16 @@ static void be_matvec(or_ctx* o, const double* x, double* y, double dt, double* 
 }
 
 /* Backward Euler step (I - dt V^{-1}(h - L.))u^{n+1} = u^n written as the
- * SPD system (V + dt L) x = V u^n + dt h, solved by point-Jacobi PCG from
- * x0 = u^n, stopping when ||r||_2 <= tol ||b||_2 (or after exactly
- * force_iters iterations when > 0).  Returns 0, 4 (no convergence),
- * 5 (breakdown: <p,Mp> <= 0 or not finite). */
+ * SPD system (V + dt L) x = V u^n + dt h, solved by preconditioned CG (point
+ * Jacobi, or block ILU(0) when set by or_set_pc) from x0 = u^n, stopping
+ * when ||r||_2 <= tol ||b||_2 (or after exactly force_iters iterations when
+ * > 0).  Returns 0, 4 (no convergence), 5 (breakdown: <p,Mp> <= 0 or not
+ * finite), 3 / 7 (block ILU(0): operator not supported / pivot not positive). */
 static int be_solve(or_ctx* o, double* u, double dt, double tol, int max_iter, int force_iters,
                     int* iters, double* relres)
 {
     const size_t N = ncell(o), n = (size_t)o->nc * N;
+    int status = 0;
     double* b = (double*)malloc(n * sizeof(double));
     double* x = (double*)malloc(n * sizeof(double));
     double* r = (double*)malloc(n * sizeof(double));
@@ -771,12 +991,19 @@ static int be_solve(or_ctx* o, double* u, double dt, double tol, int max_iter, i
     memcpy(x, u, n * sizeof(double));
     be_matvec(o, x, q, dt, tmp);
     for (size_t m = 0; m < n; ++m) r[m] = b[m] - q[m];
-    for (size_t m = 0; m < n; ++m) z[m] = r[m] / D[m % N];
+    or_csr F;
+    memset(&F, 0, sizeof(F));
+    if (o->pcond == OR_PC_BILU0) {
+        const int e = bilu0_make(o, dt, &F);
+        if (e) { status = e; free(b); free(x); free(r); free(z); free(p); free(q); free(tmp);
+                 free(zero); free(Ld); free(D); csr_free(&F); *iters = 0; *relres = 0.0; return e; }
+    }
+    precondition(o, &F, D, r, z);
     memcpy(p, z, n * sizeof(double));
     double rho = dot(r, z, n);
     const double bnorm = sqrt(dot(b, b, n));
     double rnorm = sqrt(dot(r, r, n));
-    int it = 0, status = 0;
+    int it = 0;
     const int limit = force_iters > 0 ? force_iters : max_iter;
     if (!(force_iters > 0) && rnorm <= tol * bnorm) goto done;
     for (it = 1; it <= limit; ++it) {
@@ -789,7 +1016,7 @@ static int be_solve(or_ctx* o, double* u, double dt, double tol, int max_iter, i
         rnorm = sqrt(dot(r, r, n));
         if (force_iters > 0) { if (it == force_iters) break; }
         else if (rnorm <= tol * bnorm) break;
-        for (size_t m = 0; m < n; ++m) z[m] = r[m] / D[m % N];
+        precondition(o, &F, D, r, z);
         const double rho1 = dot(r, z, n);
         const double beta = rho1 / rho;
         for (size_t m = 0; m < n; ++m) p[m] = z[m] + beta * p[m];
@@ -801,6 +1028,7 @@ done:
     *iters = it;
     *relres = bnorm > 0.0 ? rnorm / bnorm : rnorm;
     free(b); free(x); free(r); free(z); free(p); free(q); free(tmp); free(zero); free(Ld); free(D);
+    csr_free(&F);
     return status;
 }
 

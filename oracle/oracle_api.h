@@ -38,6 +38,10 @@ double or_ptl(or_ctx* o, const double* u, int64_t* kmax);
 int or_sts_coeffs(int kind, int s, double* mu, double* nu, double* mut, double* gam);
 int or_sts_stages(int kind, double ratio, int force_odd);
 int or_num_threads(void);
+int or_set_pc(or_ctx* o, int pc, int bi, int bj, int bk);
+int or_bilu0_export(const or_ctx* o, double dt, int* rowp, int* col, double* m0, double* lu,
+                    int cap);
+int or_precondition(const or_ctx* o, double dt, const double* r, double* z);
 int or_advance(or_ctx* o, double* u, double dt, int cycles, int scheme, int sts_kind,
                int force_odd, int s_override, double tol, int max_iter, int force_iters,
                int max_cycles, double ptl_floor, const double* replay_dt, int replay_n,
