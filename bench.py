@@ -213,6 +213,40 @@ def learned_leg(paradv, inputs, torch, dev, nr, nt, np_, reps=2):
     }
 
 
+def bilu0_leg(paradv, inputs, torch, dev, visc, nr, nt, np_, reps=3):
+    """BE with the block ILU(0) preconditioner (PC2 of Sec. 3.1) against
+    point Jacobi (PC1) on the 7-point workloads: the three-component
+    viscosity and the isotropic heat recipe at the same grid, PTL-cycled at
+    dt = 50 dt_E, tol 1e-10; seconds per advance, iterations, speedup."""
+    out = {"workload": f"{nr}x{nt}x{np_}, BE PTL-cycled at dt = 50 dt_E, tol 1e-10, "
+                       "boxes 8x4x16"}
+    for name, prob in (("viscosity", visc), ("heat", inputs.heat_iso(nr, nt, np_))):
+        g = paradv.Operator.from_problem(prob)
+        u0 = torch.as_tensor(prob.u, device=dev)
+        u = torch.empty_like(u0)
+        dt = 50 * g.dt_explicit()
+        res = {}
+        for pc in ("jacobi", "bilu0"):
+            g.set_options(pc=paradv.PCS[pc])
+            best = None
+            for k in range(reps + 1):
+                u.copy_(u0)
+                g.bind(u)
+                st = g.advance_be(dt, 1e-10, 0)
+                if k > 0 and (best is None or st["ms_total"] < best["ms_total"]):
+                    best = st
+            res[pc] = {"s_per_advance": round(best["ms_total"] / 1e3, 4),
+                       "pcg_iters": best["iters_total"], "cycles": best["cycles"],
+                       "rel_residual": best["rel_residual"]}
+        res["iters_ratio"] = round(res["bilu0"]["pcg_iters"] / max(res["jacobi"]["pcg_iters"], 1), 3)
+        res["speedup_vs_jacobi"] = round(res["jacobi"]["s_per_advance"] /
+                                         max(res["bilu0"]["s_per_advance"], 1e-9), 3)
+        out[name] = res
+        del g
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -220,8 +254,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--shape", default="151,301,400")
-    ap.add_argument("--legs", default="fp32,learned",
-                    help="extra legs reported beside the timed step: fp32, learned, none")
+    ap.add_argument("--legs", default="fp32,learned,bilu0",
+                    help="extra legs reported beside the timed step: fp32, learned, bilu0, none")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the advance is built for a single MI355X "
@@ -382,6 +416,9 @@ def main():
     if "learned" in legs:
         log("learned-preconditioner leg")
         out["learned_pc"] = learned_leg(paradv, inputs, torch, dev, nr, nt, np_)
+    if "bilu0" in legs:
+        log("block ILU(0) leg")
+        out["bilu0_pc"] = bilu0_leg(paradv, inputs, torch, dev, visc, nr, nt, np_)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = run_cpu_baseline(cond)

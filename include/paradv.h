@@ -67,7 +67,13 @@ typedef enum { PA_OP_ISO7 = 0, PA_OP_FIELD_ALIGNED = 1 } pa_op;
 typedef enum { PA_BC_DIRICHLET = 0, PA_BC_NOFLUX = 1 } pa_bc;
 typedef enum { PA_FP64 = 0, PA_FP32_STAGES = 1 } pa_prec;
 typedef enum { PA_STS_RKL2 = 0, PA_STS_RKG2 = 1 } pa_sts;
-typedef enum { PA_PC_JACOBI = 0, PA_PC_LEARNED = 1 } pa_pc;
+typedef enum { PA_PC_JACOBI = 0, PA_PC_LEARNED = 1, PA_PC_BILU0 = 2 } pa_pc;
+
+/* Boxes of the block ILU(0) preconditioner (PA_PC_BILU0), in cells along
+ * r, theta, phi, starting at cell 0 in each direction. */
+#define PA_BILU0_BI 8
+#define PA_BILU0_BJ 4
+#define PA_BILU0_BK 16
 
 #define PA_MAX_LOG 4096
 
@@ -99,7 +105,8 @@ typedef struct {
     int32_t force_odd;    /* 1: add a stage when s is even (Sec. 3.1, App. A). default 1 */
     int32_t s_override;   /* >0: use exactly this many stages. default 0 */
     int32_t pc;           /* pa_pc. default PA_PC_JACOBI; PA_PC_LEARNED needs weights
-                             (pa_lpc_set_weights), ncomp == 1 and PA_FP64 */
+                             (pa_lpc_set_weights), ncomp == 1 and PA_FP64;
+                             PA_PC_BILU0 needs PA_OP_ISO7 */
     int32_t max_iter;     /* PCG iteration limit per solve. default 10000 */
     int32_t max_cycles;   /* cycle limit per advance. default 100000 */
     int32_t force_iters;  /* >0: run exactly this many PCG iterations per solve. default 0 */
@@ -211,6 +218,18 @@ pa_status pa_compute_ptl(pa_ctx* ctx, double* dt_ptl, int64_t* k_lin);
  * it, -1 when no pair constrains (dt_full = +inf).  A diagnostic of that
  * assumption; the advances use pa_compute_ptl's form. */
 pa_status pa_compute_ptl_full(pa_ctx* ctx, double* dt_full, int64_t* k_lin);
+
+/* Block ILU(0) preconditioner, PC2 of Sec. 3.1 (non-overlapping ILU(0)):
+ * z = P^{-1} r for device arrays of the field's shape (all components), P the
+ * incomplete LU factorisation, with the sparsity of M and cells in natural
+ * (i, j, k) order, of the block-diagonal part of M = wV + dt L on boxes of
+ * PA_BILU0_BI x PA_BILU0_BJ x PA_BILU0_BK cells (every coupling between cells
+ * of different boxes dropped; the periodic phi coupling is never inside a
+ * box).  With the 7-point sparsity only the pivots differ from M.  The same
+ * preconditioner serves the BE solves with pc = PA_PC_BILU0.  PA_OP_ISO7
+ * only (PA_ERR_ARG otherwise); PA_ERR_BREAKDOWN if a pivot is not positive;
+ * coefficients must be set.  r_dev and z_dev must not overlap. */
+pa_status pa_bilu0_apply(pa_ctx* ctx, double dt, const double* r_dev, double* z_dev);
 
 /* Advance the bound field over dt with RKL2 (Meyer, Balsara & Aslam 2014,
  * the paper's RKL2 reference) or RKG2 (App. A).  cycles > 0: that many equal

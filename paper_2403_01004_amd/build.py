@@ -7,7 +7,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = ["pa_kernels.hip", "pa_setup.hip", "pa_vec.hip", "pa_nn.hip", "pa_capi.hip"]
+SRC = ["pa_kernels.hip", "pa_setup.hip", "pa_vec.hip", "pa_nn.hip", "pa_bilu0.hip",
+       "pa_capi.hip"]
 LIB = os.path.join(HERE, "libparadv.so")
 ARCH = os.environ.get("PA_OFFLOAD_ARCH", "gfx950")
 

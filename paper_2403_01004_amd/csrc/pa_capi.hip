@@ -105,6 +105,7 @@ struct pa_ctx {
     __bf16 *nn_ga = nullptr, *nn_gb = nullptr;   // [cap][16] activation gradients
     __bf16* nn_g1 = nullptr;                     // [cap] output gradient
     float* nn_wpart = nullptr;                   // weight-gradient partials
+    double* bilu0_ip = nullptr;  // [N] inverse block ILU(0) pivots of the current solve
 };
 
 namespace {
@@ -593,8 +594,11 @@ pa_status pa_set_options(pa_ctx* c, const pa_opts* o)
     if (!o) return fail(c, PA_ERR_ARG, "null options");
     if (o->s_override < 0 || o->s_override == 1 || o->max_iter < 1 || o->max_cycles < 1 ||
         o->force_iters < 0 || o->pcg_batch < 1 || o->replay_n < 0 || !(o->ptl_floor >= 0.0) ||
-        (o->replay_n > 0 && !o->replay_dt) || (o->pc != PA_PC_JACOBI && o->pc != PA_PC_LEARNED))
+        (o->replay_n > 0 && !o->replay_dt) ||
+        (o->pc != PA_PC_JACOBI && o->pc != PA_PC_LEARNED && o->pc != PA_PC_BILU0))
         return fail(c, PA_ERR_ARG, "invalid option value");
+    if (o->pc == PA_PC_BILU0 && c->d.op != PA_OP_ISO7)
+        return fail(c, PA_ERR_ARG, "block ILU(0): 7-point operator only");
     if (o->pc == PA_PC_LEARNED) {
         if (c->d.ncomp != 1 || c->fp32)
             return fail(c, PA_ERR_ARG, "learned preconditioner: single-component FP64 contexts only");
@@ -787,7 +791,7 @@ pa_status pa_compute_ptl_full(pa_ctx* c, double* dt, int64_t* k)
     return PA_OK;
 }
 
-}  // extern "C"
+}  // extern "C""
 
 // ---------------------------------------------------------------- drivers
 
@@ -946,7 +950,7 @@ pa_status pa_advance_rkg2(pa_ctx* c, double dt, int32_t cycles, pa_stats* st)
 namespace {
 
 // Queue n PCG iterations (each skipped on the device once the solve is
-// done).  PT is the storage type of the search direction and the matvec
+// done), point Jacobi or block ILU(0) preconditioned.  PT is the storage type of the search direction and the matvec
 // (double, or float for the FP32-matvec inner solves); x, r and all scalars
 // are FP64.
 template <class PT>
@@ -955,6 +959,12 @@ void pcg_queue(pa_ctx* c, double dtc, double* r, PT* p, PT* q, int n)
     const int nr = c->d.nr, nc = c->d.ncomp;
     const int mt = ntiles(c, nr);
     int nparts = 0;
+    // block ILU(0): the preconditioned residual goes to the y0 buffer, free
+    // once the solve has started
+    const bool bilu0 = c->opt.pc == PA_PC_BILU0;
+    const Geo<double> g = geo(c, c->m64);
+    const KArgs<double> a64 = base_args<double>(c, 0, nr);
+    double* zb = c->w[0];
     for (int b = 0; b < n; ++b) {
         KArgs<PT> a = base_args<PT>(c, 0, nr);
         a.u = p;
@@ -969,6 +979,20 @@ void pcg_queue(pa_ctx* c, double dtc, double* r, PT* p, PT* q, int n)
         {
             KScope t(c, PA_K_REDUCE);
             launch_pcg_alpha(c->part, mt, c->st, c->stream);
+        }
+        if (bilu0) {
+            {
+                KScope t(c, PA_K_UPDATE);
+                launch_pcg_update_bilu0<PT>(g, nc, a64.coef, a64.cs, dtc, c->bilu0_ip, c->u, r, p,
+                                            q, zb, c->st, c->part, &nparts, c->stream);
+            }
+            {
+                KScope t(c, PA_K_REDUCE);
+                launch_pcg_beta(c->part, nparts, c->st, c->stream);
+            }
+            KScope t(c, PA_K_DIR);
+            launch_pcg_dir_z<PT>(c->NT, zb, p, c->st, c->stream);
+            continue;
         }
         {
             KScope t(c, PA_K_UPDATE);
@@ -996,6 +1020,42 @@ pa_status pcg_loop(pa_ctx* c, double dtc, double* r, PT* p, PT* q)
         if (s) return s;
         if (c->hst->done) return PA_OK;
     }
+}
+
+// Block ILU(0) of M = wV + dt L at dt (D = wV + dt diag L already in Dbuf):
+// inverse pivots into bilu0_ip.  PA_ERR_BREAKDOWN if a pivot is not positive.
+pa_status bilu0_factor(pa_ctx* c, double dtc)
+{
+    const size_t nb = (size_t)bilu0_boxes(c->d.nr, c->d.nt, c->d.np);
+    if (!c->bilu0_ip) c->bilu0_ip = (double*)dev_alloc(c, sizeof(double) * c->N);
+    if (!c->bilu0_ip || !ensure_parts(c, nb))
+        return fail(c, PA_ERR_ALLOC, "block ILU(0): out of device memory");
+    const Geo<double> g = geo(c, c->m64);
+    const KArgs<double> a = base_args<double>(c, 0, c->d.nr);
+    launch_fill_zero(c->flag, sizeof(int), c->stream);
+    {
+        KScope t(c, PA_K_INIT);
+        launch_bilu0_factor(g, a.coef, a.cs, dtc, c->Dbuf, c->bilu0_ip, c->flag, c->stream);
+    }
+    HIPCHK(c, hipGetLastError());
+    pa_status s = sync_state(c);
+    if (s) return s;
+    if (*c->hflag) return fail(c, PA_ERR_BREAKDOWN, "block ILU(0): pivot not positive");
+    return PA_OK;
+}
+
+// Start of a block ILU(0) solve after launch_pcg_start: p = z0 = P^{-1} r0
+// and rho = <r0, z0>
+template <class PT>
+void bilu0_start(pa_ctx* c, double dtc, const double* r, PT* p)
+{
+    const Geo<double> g = geo(c, c->m64);
+    const KArgs<double> a = base_args<double>(c, 0, c->d.nr);
+    int nb = 0;
+    KScope t(c, PA_K_INIT);
+    launch_bilu0_solve<PT>(g, c->d.ncomp, a.coef, a.cs, dtc, c->bilu0_ip, r, p, c->part, &nb,
+                           c->stream);
+    launch_pcg_set_rho(c->part, nb, c->st, c->stream);
 }
 
 // F(0) on the two radial boundary levels into q (the boundary-data part of
@@ -1296,6 +1356,7 @@ pa_status pa_advance_be_pcg(pa_ctx* c, double dt, double tol, int32_t cycles, pa
     if (cycles < 0) return fail(c, PA_ERR_ARG, "cycles must be >= 0");
     if (!(tol >= 0.0) || !isfinite(tol)) return fail(c, PA_ERR_ARG, "tol must be finite and >= 0");
     const bool learned = c->opt.pc == PA_PC_LEARNED;
+    const bool bilu0 = c->opt.pc == PA_PC_BILU0;
     if (learned) {
         if (!c->nn_ready || c->d.ncomp != 1 || c->fp32)
             return fail(c, PA_ERR_STATE, "learned preconditioner not available on this context");
@@ -1358,6 +1419,11 @@ pa_status pa_advance_be_pcg(pa_ctx* c, double dt, double tol, int32_t cycles, pa
                 launch_pcg_start(c->part, nparts, c->st, tol, c->opt.max_iter,
                                  c->opt.force_iters, 0, 0.0, c->stream);
             }
+            if (bilu0) {
+                s = bilu0_factor(c, dtc);
+                if (s) break;
+                bilu0_start<double>(c, dtc, r, p);
+            }
             s = pcg_loop<double>(c, dtc, r, p, q);
             if (s) break;
             its = c->hst->iters;
@@ -1374,6 +1440,10 @@ pa_status pa_advance_be_pcg(pa_ctx* c, double dt, double tol, int32_t cycles, pa
                                        any_dir ? q : nullptr, c->diagL,
                                        c->Dbuf, r, p32, bvec, c->part, &nparts, c->stream);
             }
+            if (bilu0) {
+                s = bilu0_factor(c, dtc);
+                if (s) break;
+            }
             int outer = 0;
             while (true) {
                 {
@@ -1381,6 +1451,7 @@ pa_status pa_advance_be_pcg(pa_ctx* c, double dt, double tol, int32_t cycles, pa
                     launch_pcg_start(c->part, nparts, c->st, tol, c->opt.max_iter - its,
                                      c->opt.force_iters, 1, eta, c->stream);
                 }
+                if (bilu0) bilu0_start<float>(c, dtc, r, p32);
                 s = sync_state(c);
                 if (s || c->hst->done) break;
                 s = pcg_loop<float>(c, dtc, r, p32, q32);
@@ -1424,6 +1495,31 @@ pa_status pa_advance_be_pcg(pa_ctx* c, double dt, double tol, int32_t cycles, pa
     st->status = s;
     if (!s) c->err.clear();
     return s;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+pa_status pa_bilu0_apply(pa_ctx* c, double dt, const double* r, double* z)
+{
+    if (!c) return PA_ERR_ARG;
+    if (!r || !z) return fail(c, PA_ERR_ARG, "null vector");
+    if (c->d.op != PA_OP_ISO7) return fail(c, PA_ERR_ARG, "block ILU(0): 7-point operator only");
+    if (!(dt > 0.0) || !isfinite(dt)) return fail(c, PA_ERR_ARG, "dt must be finite and > 0");
+    if (!c->have_coef) return fail(c, PA_ERR_STATE, "coefficients not set");
+    const Geo<double> g = geo(c, c->m64);
+    launch_jacobi_D(g, dt, c->use_w ? c->w64 : nullptr, c->diagL, c->Dbuf, c->stream);
+    pa_status s = bilu0_factor(c, dt);
+    if (s) return s;
+    const KArgs<double> a = base_args<double>(c, 0, c->d.nr);
+    int nb = 0;
+    launch_bilu0_solve<double>(g, c->d.ncomp, a.coef, a.cs, dt, c->bilu0_ip, r, z, c->part, &nb,
+                               c->stream);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->err.clear();
+    return PA_OK;
 }
 
 }  // extern "C"

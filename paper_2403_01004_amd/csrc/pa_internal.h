@@ -199,6 +199,22 @@ void launch_f32_to_f64(const float* a, double* b, size_t n, hipStream_t s);
 void launch_copy(const void* a, void* b, size_t bytes, hipStream_t s);
 void launch_fill_zero(void* a, size_t bytes, hipStream_t s);
 void launch_nonfinite(const double* a, size_t n, int* flag, hipStream_t s);
-void launch_nonpositive(const double* a, size_t n, int* flag, hipStream_t s);  // !(a > 0) or NaN
+void launch_nonpositive(const double* a, size_t n, int* flag, hipStream_t s);
+// block ILU(0) (7-point operator): boxes of 8 x 4 x 16 cells, one wave each
+int bilu0_boxes(int nr, int nt, int np);
+void launch_bilu0_factor(const Geo<double>& g, const double* coef, double cs, double dt,
+                         const double* D, double* ip, int* flag, hipStream_t s);
+template <class PT>
+void launch_bilu0_solve(const Geo<double>& g, int nc, const double* coef, double cs, double dt,
+                        const double* ip, const double* r, PT* out, double* part, int* nparts,
+                        hipStream_t s);
+template <class PT>
+void launch_pcg_update_bilu0(const Geo<double>& g, int nc, const double* coef, double cs,
+                             double dt, const double* ip, double* x, double* r, const PT* p,
+                             const PT* q, double* z, const DevState* st, double* part,
+                             int* nparts, hipStream_t s);
+template <class PT>
+void launch_pcg_dir_z(size_t n, const double* z, PT* p, const DevState* st, hipStream_t s);
+void launch_pcg_set_rho(const double* part, int n, DevState* st, hipStream_t s);  // !(a > 0) or NaN
 
 }  // namespace pa

@@ -493,6 +493,41 @@ template void launch_pcg_dir<double>(size_t, int, const double*, const double*, 
 template void launch_pcg_dir<float>(size_t, int, const double*, const double*, float*,
                                     const DevState*, hipStream_t);
 
+// p = z + beta p, with z the preconditioned residual stored by a block
+// preconditioner (all components, n = nc * N values)
+template <class PT>
+__global__ __launch_bounds__(kBlock) void k_pcg_dir_z(size_t n, const double* __restrict__ z,
+                                                      PT* __restrict__ p, const DevState* st)
+{
+    if (st->done) return;
+    const double beta = st->beta;
+    for (size_t m = (size_t)blockIdx.x * blockDim.x + threadIdx.x; m < n;
+         m += (size_t)gridDim.x * blockDim.x)
+        p[m] = (PT)(z[m] + beta * (double)p[m]);
+}
+
+template <class PT>
+void launch_pcg_dir_z(size_t n, const double* z, PT* p, const DevState* st, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_pcg_dir_z<PT>), dim3(vec_blocks(n)), dim3(kBlock), 0, s, n, z, p, st);
+}
+template void launch_pcg_dir_z<double>(size_t, const double*, double*, const DevState*,
+                                       hipStream_t);
+template void launch_pcg_dir_z<float>(size_t, const double*, float*, const DevState*, hipStream_t);
+
+// rho = <r, z> from the partials of a preconditioner applied after
+// launch_pcg_start (which set rho for point Jacobi)
+__global__ __launch_bounds__(kRedBlock) void k_pcg_set_rho(const double* part, int n, DevState* st)
+{
+    const double rz = red_sum(part, n);
+    if (threadIdx.x == 0) st->rho = rz;
+}
+
+void launch_pcg_set_rho(const double* part, int n, DevState* st, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pcg_set_rho, dim3(1), dim3(kRedBlock), 0, s, part, n, st);
+}
+
 // ---------------------------------------------------------------- misc
 
 __global__ void k_f64_to_f32(const double* a, float* b, size_t n)

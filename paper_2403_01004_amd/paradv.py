@@ -33,9 +33,10 @@ EXPORTS = ["pa_init", "pa_destroy", "pa_last_error", "pa_default_options", "pa_s
            "pa_diag", "pa_compute_ptl", "pa_compute_ptl_full", "pa_advance_rkl2", "pa_advance_rkg2",
            "pa_advance_be_pcg", "pa_lpc_default_train_opts", "pa_lpc_set_weights",
            "pa_lpc_get_weights", "pa_lpc_features", "pa_lpc_apply", "pa_lpc_loss_grad",
-           "pa_lpc_train"]
+           "pa_lpc_train", "pa_bilu0_apply"]
 PA_LPC_NPARAM = 10832
-PCS = {"jacobi": 0, "learned": 1}
+PCS = {"jacobi": 0, "learned": 1, "bilu0": 2}
+PA_BILU0_BOX = (8, 4, 16)   # block ILU(0) boxes in cells along r, theta, phi
 
 _ALLOC = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 _FREE = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
@@ -121,6 +122,7 @@ def load(path: str = LIB_PATH):
         "pa_diag": (I32, [V, V]),
         "pa_compute_ptl": (I32, [V, P(D), P(I64)]),
         "pa_compute_ptl_full": (I32, [V, P(D), P(I64)]),
+        "pa_bilu0_apply": (I32, [V, D, V, V]),
         "pa_advance_rkl2": (I32, [V, D, I32, P(pa_stats)]),
         "pa_advance_rkg2": (I32, [V, D, I32, P(pa_stats)]),
         "pa_advance_be_pcg": (I32, [V, D, D, I32, P(pa_stats)]),
@@ -205,6 +207,10 @@ def pa_compute_ptl_full(ctx):
     dt, k = ctypes.c_double(), ctypes.c_int64()
     st = load().pa_compute_ptl_full(ctx, ctypes.byref(dt), ctypes.byref(k))
     return st, dt.value, k.value
+
+
+def pa_bilu0_apply(ctx, dt, r_ptr, z_ptr):
+    return load().pa_bilu0_apply(ctx, float(dt), r_ptr, z_ptr)
 
 
 def pa_advance_rkl2(ctx, dt, cycles, stats=None):
@@ -432,6 +438,13 @@ class Operator:
         st, dt, k = pa_compute_ptl_full(self.ctx)
         self._check(st)
         return dt, k
+
+    def bilu0_apply(self, r, dt):
+        """z = P^{-1} r with the block ILU(0) preconditioner of M = wV + dt L."""
+        r = self._dev(r, self.field_shape)
+        z = self.torch.empty_like(r)
+        self._check(pa_bilu0_apply(self.ctx, dt, self._p(r), self._p(z)))
+        return z
 
     def _adv(self, fn, *args, check=True):
         s = pa_stats()
