@@ -254,6 +254,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--shape", default="151,301,400")
+    ap.add_argument("--leg-reps", type=int, default=3,
+                    help="timed repetitions of each advance in the block ILU(0) leg")
     ap.add_argument("--legs", default="fp32,learned,bilu0",
                     help="extra legs reported beside the timed step: fp32, learned, bilu0, none")
     args = ap.parse_args()
@@ -418,7 +420,8 @@ def main():
         out["learned_pc"] = learned_leg(paradv, inputs, torch, dev, nr, nt, np_)
     if "bilu0" in legs:
         log("block ILU(0) leg")
-        out["bilu0_pc"] = bilu0_leg(paradv, inputs, torch, dev, visc, nr, nt, np_)
+        out["bilu0_pc"] = bilu0_leg(paradv, inputs, torch, dev, visc, nr, nt, np_,
+                                    reps=args.leg_reps)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = run_cpu_baseline(cond)

@@ -13,13 +13,14 @@
 // l % kBK) of the box and walks its kBI levels along the wavefronts
 // f = i + j + k: at step f the lane treats level f - j - k, whose three lower
 // (upper) neighbours were finished at step f - 1 (f + 1) by itself and by
-// lanes l - kBK and l - 1 (l + kBK, l + 1).  In the solves those values pass
-// between lanes by DPP row shifts and a lane permute, so the dependent chain
-// stays in registers; the box's values, couplings and inverse pivots sit in
-// LDS (20 KB per wave).
-// The PCG update x += alpha p, r -= alpha q is fused in front of the solve,
-// so r is read once per iteration; all components of the box share the
-// couplings and pivots.
+// lanes l - kBK and l - 1 (l + kBK, l + 1).  Those values pass between lanes
+// by a DPP row shift and a lane permute, so the dependent chain stays in
+// registers.  The couplings M_mn = -dt c_f G_f are rebuilt at each step from
+// per-lane column factors and per-box level factors (separable metric), so
+// LDS holds only the lane's own values, the inverse pivots and, for a
+// variable coefficient, the coefficients: 8 KB (12 KB) per wave, which keeps
+// enough waves resident to stream the PCG update fused in front of the solve
+// (x += alpha p, r -= alpha q; r is read once per iteration).
 #include "pa_internal.h"
 
 namespace pa {
@@ -61,152 +62,155 @@ __device__ __forceinline__ BoxPos box_pos(const Geo<double>& g, unsigned b, int 
     return p;
 }
 
-// Lower couplings M(m, r-), M(m, t-), M(m, p-) = -dt c_f G_f of every cell
-// of the lane's column into LDS (0 where the neighbour is outside the box or
-// the grid, and for cells outside the grid).  c_f is the mean of the two cell
-// coefficients (coef == null: the constant cs).
-__device__ __forceinline__ void box_couplings(const Geo<double>& g, const BoxPos& p,
-                                              const double* __restrict__ coef, double cs,
-                                              double dt, int lane, double* s_ar, double* s_at,
-                                              double* s_ak)
-{
-    const size_t P = (size_t)g.P, np = (size_t)g.np;
-    double vt = 0.0, vp = 0.0, gtt = 0.0, gpt = 0.0, gpp = 0.0;
-    if (p.col) {
-        vt = g.vt[p.j]; vp = g.vp[p.k]; gtt = g.gtt[p.j]; gpt = g.gpt[p.j]; gpp = g.gpp[p.k];
-    }
-#pragma unroll
-    for (int ii = 0; ii < kBI; ++ii) {
-        double ar = 0.0, at = 0.0, ak = 0.0;
-        if (p.col && ii < p.nib) {
-            const int i = p.i0 + ii;
-            const size_t m = (size_t)i * P + (size_t)p.j * np + (size_t)p.k;
-            const double cm = coef ? coef[m] : cs;
-            const double gtr = g.gtr[i];
-            if (ii > 0) ar = -dt * (0.5 * (cm + (coef ? coef[m - P] : cs))) * (g.gr[i] * vt * vp);
-            if (p.jj > 0) at = -dt * (0.5 * (cm + (coef ? coef[m - np] : cs))) * (gtr * gtt * vp);
-            if (p.kk > 0) ak = -dt * (0.5 * (cm + (coef ? coef[m - 1] : cs))) * (gtr * gpt * gpp);
-        }
-        s_ar[ii * kBL + lane] = ar;
-        s_at[ii * kBL + lane] = at;
-        s_ak[ii * kBL + lane] = ak;
-    }
-}
-
 // The value v of lane l - 1 (row_prev) or l + 1 (row_next) in the same row
-// of 16 lanes, 0 past the row's end (DPP row shifts, two 32-bit halves).
-__device__ __forceinline__ double dpp_shift(double v, int ctrl)
+// of 16 lanes, 0 past the row's end (DPP row shifts on the two halves).
+__device__ __forceinline__ double row_prev(double v)
 {
     const long long b = __double_as_longlong(v);
-    int lo = (int)(unsigned)(b & 0xffffffffll), hi = (int)(b >> 32);
-    switch (ctrl) {
-    case 0:   // row_shr:1
-        lo = __builtin_amdgcn_update_dpp(0, lo, 0x111, 0xf, 0xf, true);
-        hi = __builtin_amdgcn_update_dpp(0, hi, 0x111, 0xf, 0xf, true);
-        break;
-    default:  // row_shl:1
-        lo = __builtin_amdgcn_update_dpp(0, lo, 0x101, 0xf, 0xf, true);
-        hi = __builtin_amdgcn_update_dpp(0, hi, 0x101, 0xf, 0xf, true);
-        break;
-    }
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffll), 0x111, 0xf,
+                                               0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x111, 0xf, 0xf, true);
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
-__device__ __forceinline__ double row_prev(double v) { return dpp_shift(v, 0); }
-__device__ __forceinline__ double row_next(double v) { return dpp_shift(v, 1); }
-
-// Forward and backward solve of one component in place: s_w holds r on
-// entry (0 outside the grid) and z = U^{-1} L^{-1} r on exit.  At step f a
-// lane needs the values its lower (upper) neighbours produced at step f - 1:
-// its own previous output and the outputs of lanes l - 1 and l - kBK
-// (l + 1, l + kBK), read across lanes, so the chain of steps runs through
-// registers; s_w only keeps each lane's own values between the sweeps.
-// The couplings of the other lanes must be visible in LDS (barrier before).
-__device__ __forceinline__ void box_solve(const BoxPos& p, int lane, double* s_w,
-                                          const double* s_ar, const double* s_at,
-                                          const double* s_ak, const double* s_ip)
+__device__ __forceinline__ double row_next(double v)
 {
-    // forward: y_m = r_m - sum_lower M_mn y_n / d_n; s_w keeps w_m = y_m / d_m
-    double cur = 0.0;
-#pragma unroll 2
-    for (int f = 0; f < kSteps; ++f) {
-        const double wk = row_prev(cur);          // (i, j, k-1)
-        const double wj = __shfl_up(cur, kBK, 64);  // (i, j-1, k)
-        const int ii = f - p.jj - p.kk;
-        if (p.col && ii >= 0 && ii < p.nib) {
-            const int q = ii * kBL + lane;
-            double y = s_w[q];
-            if (ii > 0) y -= s_ar[q] * cur;
-            if (p.jj > 0) y -= s_at[q] * wj;
-            if (p.kk > 0) y -= s_ak[q] * wk;
-            cur = y * s_ip[q];
-            s_w[q] = cur;
-        }
-    }
-    // backward: z_m = w_m - (sum_upper M_mn z_n) / d_m
-    cur = 0.0;
-#pragma unroll 2
-    for (int f = kSteps - 1; f >= 0; --f) {
-        const double zk = row_next(cur);            // (i, j, k+1)
-        const double zj = __shfl_down(cur, kBK, 64);  // (i, j+1, k)
-        const int ii = f - p.jj - p.kk;
-        if (p.col && ii >= 0 && ii < p.nib) {
-            const int q = ii * kBL + lane;
-            double s = 0.0;
-            if (ii + 1 < p.nib) s += s_ar[q + kBL] * cur;
-            if (p.jj + 1 < kBJ) s += s_at[q + kBK] * zj;
-            if (p.kk + 1 < kBK) s += s_ak[q + 1] * zk;
-            cur = s_w[q] - s_ip[q] * s;
-            s_w[q] = cur;
-        }
-    }
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffll), 0x101, 0xf,
+                                               0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x101, 0xf, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-// inverse pivots of the box into s_ip (and ip[] in HBM); D = wV + dt diag L
-__device__ __forceinline__ void box_factor(const Geo<double>& g, const BoxPos& p, int lane,
-                                           const double* __restrict__ D, double* s_w,
-                                           const double* s_ar, const double* s_at,
-                                           const double* s_ak, double* s_ip, double* ip,
-                                           int* flag)
+// Face coupling -dt c_f G_f with c_f the mean of the two cells' coefficients
+// and the separable face metric G_f = (level factor) (column factor).  The
+// lower coupling of a cell and the upper coupling of its neighbour are
+// evaluated from the same operands in the same order, so they are equal bit
+// for bit and P stays symmetric.
+__device__ __forceinline__ double cpl(double mdt, double ca, double cb, double lev, double colf)
 {
-    const size_t P = (size_t)g.P;
-    const size_t base = (size_t)p.j * g.np + p.k;
+    return (mdt * (0.5 * (ca + cb))) * (lev * colf);
+}
+
+// The box's geometry: per-lane column factors of the six faces (0 where the
+// neighbour is outside the box or the grid) and per-level factors in LDS.
+struct BoxGeo {
+    double fr;             // vt[j] vp[k]: radial faces
+    double ft_lo, ft_hi;   // gtt[j] vp[k], gtt[j+1] vp[k]: colatitude faces
+    double fk_lo, fk_hi;   // gpt[j] gpp[k], gpt[j] gpp[k+1]: longitude faces
+};
+
+// s_gr[ii] = gr[i0+ii] for the radial face below level ii (0 at ii = 0 and
+// at and beyond nib), s_gtr[ii] = gtr[i0+ii] (0 beyond nib); s_c the cell
+// coefficients of the box (0 outside the grid) when VC.
+template <bool VC>
+__device__ __forceinline__ BoxGeo box_geo(const Geo<double>& g, const BoxPos& p, int lane,
+                                          const double* __restrict__ coef, double* s_gr,
+                                          double* s_gtr, double* s_c)
+{
+    if (lane <= kBI) {
+        const int i = p.i0 + lane;
+        s_gr[lane] = (lane > 0 && lane < p.nib) ? g.gr[i] : 0.0;
+        if (lane < kBI) s_gtr[lane] = lane < p.nib ? g.gtr[i] : 0.0;
+    }
+    if constexpr (VC) {
+        const size_t base = (size_t)p.j * g.np + p.k;
 #pragma unroll
-    for (int ii = 0; ii < kBI; ++ii)
-        s_w[ii * kBL + lane] = (p.col && ii < p.nib) ? D[(size_t)(p.i0 + ii) * P + base] : 1.0;
-    __syncthreads();
-#pragma unroll 1
-    for (int f = 0; f < kSteps; ++f) {
-        const int ii = f - p.jj - p.kk;
-        if (p.col && ii >= 0 && ii < p.nib) {
-            const int q = ii * kBL + lane;
-            double d = s_w[q];
-            if (ii > 0) d -= s_ar[q] * s_ar[q] * s_ip[q - kBL];
-            if (p.jj > 0) d -= s_at[q] * s_at[q] * s_ip[q - kBK];
-            if (p.kk > 0) d -= s_ak[q] * s_ak[q] * s_ip[q - 1];
-            if (!(d > 0.0) || !isfinite(d)) {
-                *flag = 1;
-                d = 1.0;
-            }
-            const double v = 1.0 / d;
-            s_ip[q] = v;
-            if (ip) ip[(size_t)(p.i0 + ii) * P + base] = v;
-        }
-        __syncthreads();
+        for (int ii = 0; ii < kBI; ++ii)
+            s_c[ii * kBL + lane] =
+                (p.col && ii < p.nib) ? coef[(size_t)(p.i0 + ii) * g.P + base] : 0.0;
+    }
+    BoxGeo q{0.0, 0.0, 0.0, 0.0, 0.0};
+    if (p.col) {
+        const double vt = g.vt[p.j], vp = g.vp[p.k];
+        q.fr = vt * vp;
+        if (p.jj > 0) q.ft_lo = g.gtt[p.j] * vp;
+        if (p.jj + 1 < kBJ && p.j + 1 < g.nt) q.ft_hi = g.gtt[p.j + 1] * vp;
+        if (p.kk > 0) q.fk_lo = g.gpt[p.j] * g.gpp[p.k];
+        if (p.kk + 1 < kBK && p.k + 1 < g.np) q.fk_hi = g.gpt[p.j] * g.gpp[p.k + 1];
+    }
+    return q;
+}
+
+// lower couplings M(m, r-), M(m, t-), M(m, p-) of the lane's cell at level
+// ii (q = ii * kBL + lane)
+template <bool VC>
+__device__ __forceinline__ void lower_cpl(const BoxGeo& b, int ii, int q, double mdt, double cs,
+                                          const double* s_gr, const double* s_gtr,
+                                          const double* s_c, double& ar, double& at, double& ak)
+{
+    const double gtr = s_gtr[ii];
+    if constexpr (VC) {
+        const double cm = s_c[q];
+        ar = cpl(mdt, cm, s_c[ii > 0 ? q - kBL : q], s_gr[ii], b.fr);
+        at = cpl(mdt, cm, s_c[q >= kBK ? q - kBK : q], gtr, b.ft_lo);
+        ak = cpl(mdt, cm, s_c[q > 0 ? q - 1 : q], gtr, b.fk_lo);
+    } else {
+        ar = cpl(mdt, cs, cs, s_gr[ii], b.fr);
+        at = cpl(mdt, cs, cs, gtr, b.ft_lo);
+        ak = cpl(mdt, cs, cs, gtr, b.fk_lo);
     }
 }
 
+// upper couplings M(m, r+), M(m, t+), M(m, p+): the lower couplings of the
+// neighbours, same operands in the same order
+template <bool VC>
+__device__ __forceinline__ void upper_cpl(const BoxGeo& b, int ii, int q, double mdt, double cs,
+                                          const double* s_gr, const double* s_gtr,
+                                          const double* s_c, double& arp, double& atp,
+                                          double& akp)
+{
+    const double gtr = s_gtr[ii];
+    if constexpr (VC) {
+        const double cm = s_c[q];
+        arp = cpl(mdt, s_c[ii + 1 < kBI ? q + kBL : q], cm, s_gr[ii + 1], b.fr);
+        atp = cpl(mdt, s_c[q + kBK < kBC ? q + kBK : q], cm, gtr, b.ft_hi);
+        akp = cpl(mdt, s_c[q + 1 < kBC ? q + 1 : q], cm, gtr, b.fk_hi);
+    } else {
+        arp = cpl(mdt, cs, cs, s_gr[ii + 1], b.fr);
+        atp = cpl(mdt, cs, cs, gtr, b.ft_hi);
+        akp = cpl(mdt, cs, cs, gtr, b.fk_hi);
+    }
+}
+
+// Inverse pivots of the box into ip[] (HBM); D = wV + dt diag L.  The chain
+// of pivots passes between lanes like the forward solve.
+template <bool VC>
 __global__ __launch_bounds__(kBL) void k_bilu0_factor(Geo<double> g, const double* __restrict__ coef,
                                                       double cs, double dt,
                                                       const double* __restrict__ D,
                                                       double* __restrict__ ip, int* flag)
 {
-    __shared__ double s_w[kBC], s_ar[kBC], s_at[kBC], s_ak[kBC], s_ip[kBC];
+    __shared__ double s_d[kBC], s_c[VC ? kBC : 1], s_gr[kBI + 1], s_gtr[kBI];
     const int lane = threadIdx.x;
     const BoxPos p = box_pos(g, blockIdx.x, lane);
-    box_couplings(g, p, coef, cs, dt, lane, s_ar, s_at, s_ak);
+    const BoxGeo bg = box_geo<VC>(g, p, lane, coef, s_gr, s_gtr, s_c);
+    const size_t base = (size_t)p.j * g.np + p.k;
 #pragma unroll
-    for (int ii = 0; ii < kBI; ++ii) s_ip[ii * kBL + lane] = 0.0;
-    box_factor(g, p, lane, D, s_w, s_ar, s_at, s_ak, s_ip, ip, flag);
+    for (int ii = 0; ii < kBI; ++ii)
+        s_d[ii * kBL + lane] = (p.col && ii < p.nib) ? D[(size_t)(p.i0 + ii) * g.P + base] : 1.0;
+    __syncthreads();
+    const double mdt = -dt;
+    double cur = 0.0;   // the lane's latest inverse pivot
+    bool bad = false;
+#pragma unroll 2
+    for (int f = 0; f < kSteps; ++f) {
+        const double ipk = row_prev(cur);
+        const double ipj = __shfl_up(cur, kBK, 64);
+        const int ii = f - p.jj - p.kk;
+        if (p.col && ii >= 0 && ii < p.nib) {
+            const int q = ii * kBL + lane;
+            double ar, at, ak;
+            lower_cpl<VC>(bg, ii, q, mdt, cs, s_gr, s_gtr, s_c, ar, at, ak);
+            double d = s_d[q] - ar * ar * cur - at * at * ipj - ak * ak * ipk;
+            if (!(d > 0.0) || !isfinite(d)) {
+                bad = true;
+                d = 1.0;
+            }
+            cur = 1.0 / d;
+            ip[(size_t)(p.i0 + ii) * g.P + base] = cur;
+        }
+    }
+    if (bad) *flag = 1;
 }
 
 __device__ __forceinline__ void load_ip(const Geo<double>& g, const BoxPos& p, int lane,
@@ -219,46 +223,119 @@ __device__ __forceinline__ void load_ip(const Geo<double>& g, const BoxPos& p, i
             (p.col && ii < p.nib) ? ip[(size_t)(p.i0 + ii) * g.P + base] : 0.0;
 }
 
-// z = P^{-1} r for every component (out in PT); partial <r, z> per box
-template <class PT>
+// Forward and backward solve of NV components in place: s_w[v * kBC + q]
+// holds r on entry (0 outside the grid) and z = U^{-1} L^{-1} r on exit.  At
+// step f a lane needs the values its lower (upper) neighbours produced at
+// step f - 1: its own previous output and the outputs of lanes l - 1 and
+// l - kBK (l + 1, l + kBK), read across lanes.  Couplings are 0 where a
+// neighbour is absent (and the values they multiply are finite), so the
+// steps need no tests.  LDS fills of other lanes must be visible (barrier
+// before).
+template <int NV, bool VC>
+__device__ __forceinline__ void box_solve(const BoxPos& p, const BoxGeo& bg, int lane, double mdt,
+                                          double cs, double* s_w, const double* s_ip,
+                                          const double* s_gr, const double* s_gtr,
+                                          const double* s_c)
+{
+    double cur[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) cur[v] = 0.0;
+    // forward: y_m = r_m - sum_lower M_mn y_n / d_n; s_w keeps w_m = y_m / d_m
+#pragma unroll 2
+    for (int f = 0; f < kSteps; ++f) {
+        double wk[NV], wj[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            wk[v] = row_prev(cur[v]);               // (i, j, k-1)
+            wj[v] = __shfl_up(cur[v], kBK, 64);     // (i, j-1, k)
+        }
+        const int ii = f - p.jj - p.kk;
+        if (p.col && ii >= 0 && ii < p.nib) {
+            const int q = ii * kBL + lane;
+            double ar, at, ak;
+            lower_cpl<VC>(bg, ii, q, mdt, cs, s_gr, s_gtr, s_c, ar, at, ak);
+            const double ipv = s_ip[q];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const double y = s_w[v * kBC + q] - ar * cur[v] - at * wj[v] - ak * wk[v];
+                cur[v] = y * ipv;
+                s_w[v * kBC + q] = cur[v];
+            }
+        }
+    }
+    // backward: z_m = w_m - (sum_upper M_mn z_n) / d_m
+#pragma unroll
+    for (int v = 0; v < NV; ++v) cur[v] = 0.0;
+#pragma unroll 2
+    for (int f = kSteps - 1; f >= 0; --f) {
+        double zk[NV], zj[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            zk[v] = row_next(cur[v]);               // (i, j, k+1)
+            zj[v] = __shfl_down(cur[v], kBK, 64);   // (i, j+1, k)
+        }
+        const int ii = f - p.jj - p.kk;
+        if (p.col && ii >= 0 && ii < p.nib) {
+            const int q = ii * kBL + lane;
+            double arp, atp, akp;
+            upper_cpl<VC>(bg, ii, q, mdt, cs, s_gr, s_gtr, s_c, arp, atp, akp);
+            const double ipv = s_ip[q];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const double sum = arp * cur[v] + atp * zj[v] + akp * zk[v];
+                cur[v] = s_w[v * kBC + q] - ipv * sum;
+                s_w[v * kBC + q] = cur[v];
+            }
+        }
+    }
+}
+
+// z = P^{-1} r for every component (out in PT), NV components per sweep;
+// partial <r, z> per box
+template <class PT, int NV, bool VC>
 __global__ __launch_bounds__(kBL) void k_bilu0_solve(Geo<double> g, int nc,
                                                      const double* __restrict__ coef, double cs,
                                                      double dt, const double* __restrict__ ip,
                                                      const double* __restrict__ r,
                                                      PT* __restrict__ out, double* part)
 {
-    __shared__ double s_w[kBC], s_ar[kBC], s_at[kBC], s_ak[kBC], s_ip[kBC];
+    __shared__ double s_w[NV * kBC], s_ip[kBC], s_c[VC ? kBC : 1], s_gr[kBI + 1], s_gtr[kBI];
     const int lane = threadIdx.x;
     const BoxPos p = box_pos(g, blockIdx.x, lane);
-    box_couplings(g, p, coef, cs, dt, lane, s_ar, s_at, s_ak);
+    const BoxGeo bg = box_geo<VC>(g, p, lane, coef, s_gr, s_gtr, s_c);
     load_ip(g, p, lane, ip, s_ip);
     const size_t N = (size_t)g.nr * g.P, base = (size_t)p.j * g.np + p.k;
     double rz = 0.0;
 #pragma unroll 1
-    for (int c = 0; c < nc; ++c) {
-        double rv[kBI];
+    for (int c0 = 0; c0 < nc; c0 += NV) {
+        double rv[NV][kBI];
 #pragma unroll
-        for (int ii = 0; ii < kBI; ++ii) {
-            rv[ii] = (p.col && ii < p.nib) ? r[c * N + (size_t)(p.i0 + ii) * g.P + base] : 0.0;
-            s_w[ii * kBL + lane] = rv[ii];
-        }
-        __syncthreads();
-        box_solve(p, lane, s_w, s_ar, s_at, s_ak, s_ip);
+        for (int v = 0; v < NV; ++v)
 #pragma unroll
-        for (int ii = 0; ii < kBI; ++ii)
-            if (p.col && ii < p.nib) {
-                const double z = s_w[ii * kBL + lane];
-                out[c * N + (size_t)(p.i0 + ii) * g.P + base] = (PT)z;
-                rz += rv[ii] * z;
+            for (int ii = 0; ii < kBI; ++ii) {
+                const bool on = p.col && ii < p.nib;
+                rv[v][ii] = on ? r[(c0 + v) * N + (size_t)(p.i0 + ii) * g.P + base] : 0.0;
+                s_w[v * kBC + ii * kBL + lane] = rv[v][ii];
             }
         __syncthreads();
+        box_solve<NV, VC>(p, bg, lane, -dt, cs, s_w, s_ip, s_gr, s_gtr, s_c);
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int ii = 0; ii < kBI; ++ii)
+                if (p.col && ii < p.nib) {
+                    const double z = s_w[v * kBC + ii * kBL + lane];
+                    out[(c0 + v) * N + (size_t)(p.i0 + ii) * g.P + base] = (PT)z;
+                    rz += rv[v][ii] * z;
+                }
     }
     rz = wave_sum(rz);
     if (lane == 0) part[blockIdx.x] = rz;
 }
 
-// x += alpha p, r -= alpha q, z = P^{-1} r; partials <r, z>, <r, r>
-template <class PT>
+// x += alpha p, r -= alpha q, z = P^{-1} r, NV components per sweep;
+// partials <r, z>, <r, r>
+template <class PT, int NV, bool VC>
 __global__ __launch_bounds__(kBL) void k_pcg_update_bilu0(Geo<double> g, int nc,
                                                           const double* __restrict__ coef,
                                                           double cs, double dt,
@@ -271,48 +348,46 @@ __global__ __launch_bounds__(kBL) void k_pcg_update_bilu0(Geo<double> g, int nc,
                                                           const DevState* st, double* part)
 {
     if (st->done) return;
-    __shared__ double s_w[kBC], s_ar[kBC], s_at[kBC], s_ak[kBC], s_ip[kBC];
+    __shared__ double s_w[NV * kBC], s_ip[kBC], s_c[VC ? kBC : 1], s_gr[kBI + 1], s_gtr[kBI];
     const double alpha = st->alpha;
     const int lane = threadIdx.x;
     const BoxPos p = box_pos(g, blockIdx.x, lane);
-    box_couplings(g, p, coef, cs, dt, lane, s_ar, s_at, s_ak);
+    const BoxGeo bg = box_geo<VC>(g, p, lane, coef, s_gr, s_gtr, s_c);
     load_ip(g, p, lane, ip, s_ip);
     const size_t N = (size_t)g.nr * g.P, base = (size_t)p.j * g.np + p.k;
     double rz = 0.0, rr = 0.0;
 #pragma unroll 1
-    for (int c = 0; c < nc; ++c) {
-        double xv[kBI], rv[kBI], pp[kBI], qq[kBI];
+    for (int c0 = 0; c0 < nc; c0 += NV) {
+        double rv[NV][kBI];
 #pragma unroll
-        for (int ii = 0; ii < kBI; ++ii) {
-            const bool on = p.col && ii < p.nib;
-            const size_t m = c * N + (size_t)(p.i0 + (on ? ii : 0)) * g.P + (on ? base : 0);
-            xv[ii] = on ? x[m] : 0.0;
-            rv[ii] = on ? r[m] : 0.0;
-            pp[ii] = on ? (double)pv[m] : 0.0;
-            qq[ii] = on ? (double)qv[m] : 0.0;
-        }
+        for (int v = 0; v < NV; ++v)
 #pragma unroll
-        for (int ii = 0; ii < kBI; ++ii) {
-            const double rn = rv[ii] - alpha * qq[ii];
-            rv[ii] = rn;
-            s_w[ii * kBL + lane] = rn;
-            if (p.col && ii < p.nib) {
-                const size_t m = c * N + (size_t)(p.i0 + ii) * g.P + base;
-                x[m] = xv[ii] + alpha * pp[ii];
-                r[m] = rn;
-                rr += rn * rn;
-            }
-        }
-        __syncthreads();
-        box_solve(p, lane, s_w, s_ar, s_at, s_ak, s_ip);
-#pragma unroll
-        for (int ii = 0; ii < kBI; ++ii)
-            if (p.col && ii < p.nib) {
-                const double zv = s_w[ii * kBL + lane];
-                z[c * N + (size_t)(p.i0 + ii) * g.P + base] = zv;
-                rz += rv[ii] * zv;
+            for (int ii = 0; ii < kBI; ++ii) {
+                const bool on = p.col && ii < p.nib;
+                const size_t m =
+                    (c0 + v) * N + (size_t)(p.i0 + (on ? ii : 0)) * g.P + (on ? base : 0);
+                const double xv = on ? x[m] : 0.0, ro = on ? r[m] : 0.0;
+                const double pp = on ? (double)pv[m] : 0.0, qq = on ? (double)qv[m] : 0.0;
+                const double rn = ro - alpha * qq;
+                rv[v][ii] = rn;
+                s_w[v * kBC + ii * kBL + lane] = rn;
+                if (on) {
+                    x[m] = xv + alpha * pp;
+                    r[m] = rn;
+                    rr += rn * rn;
+                }
             }
         __syncthreads();
+        box_solve<NV, VC>(p, bg, lane, -dt, cs, s_w, s_ip, s_gr, s_gtr, s_c);
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int ii = 0; ii < kBI; ++ii)
+                if (p.col && ii < p.nib) {
+                    const double zv = s_w[v * kBC + ii * kBL + lane];
+                    z[(c0 + v) * N + (size_t)(p.i0 + ii) * g.P + base] = zv;
+                    rz += rv[v][ii] * zv;
+                }
     }
     rz = wave_sum(rz);
     rr = wave_sum(rr);
@@ -321,6 +396,10 @@ __global__ __launch_bounds__(kBL) void k_pcg_update_bilu0(Geo<double> g, int nc,
         part[gridDim.x + blockIdx.x] = rr;
     }
 }
+
+// components that share a sweep
+constexpr int kChunk = 1;
+int chunk_of(int nc) { return nc % kChunk == 0 ? kChunk : 1; }
 
 }  // namespace
 
@@ -332,9 +411,18 @@ int bilu0_boxes(int nr, int nt, int np)
 void launch_bilu0_factor(const Geo<double>& g, const double* coef, double cs, double dt,
                          const double* D, double* ip, int* flag, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_bilu0_factor, dim3(bilu0_boxes(g.nr, g.nt, g.np)), dim3(kBL), 0, s, g,
-                       coef, cs, dt, D, ip, flag);
+    const int nb = bilu0_boxes(g.nr, g.nt, g.np);
+    if (coef)
+        hipLaunchKernelGGL((k_bilu0_factor<true>), dim3(nb), dim3(kBL), 0, s, g, coef, cs, dt, D,
+                           ip, flag);
+    else
+        hipLaunchKernelGGL((k_bilu0_factor<false>), dim3(nb), dim3(kBL), 0, s, g, coef, cs, dt, D,
+                           ip, flag);
 }
+
+#define PA_BILU0_SOLVE(NV, VC)                                                                   \
+    hipLaunchKernelGGL((k_bilu0_solve<PT, NV, VC>), dim3(nb), dim3(kBL), 0, s, g, nc, coef, cs, \
+                       dt, ip, r, out, part)
 
 template <class PT>
 void launch_bilu0_solve(const Geo<double>& g, int nc, const double* coef, double cs, double dt,
@@ -343,8 +431,13 @@ void launch_bilu0_solve(const Geo<double>& g, int nc, const double* coef, double
 {
     const int nb = bilu0_boxes(g.nr, g.nt, g.np);
     *nparts = nb;
-    hipLaunchKernelGGL((k_bilu0_solve<PT>), dim3(nb), dim3(kBL), 0, s, g, nc, coef, cs, dt, ip, r,
-                       out, part);
+    if (chunk_of(nc) == kChunk && kChunk > 1) {
+        if (coef) PA_BILU0_SOLVE(kChunk, true);
+        else PA_BILU0_SOLVE(kChunk, false);
+    } else {
+        if (coef) PA_BILU0_SOLVE(1, true);
+        else PA_BILU0_SOLVE(1, false);
+    }
 }
 template void launch_bilu0_solve<double>(const Geo<double>&, int, const double*, double, double,
                                          const double*, const double*, double*, double*, int*,
@@ -352,6 +445,10 @@ template void launch_bilu0_solve<double>(const Geo<double>&, int, const double*,
 template void launch_bilu0_solve<float>(const Geo<double>&, int, const double*, double, double,
                                         const double*, const double*, float*, double*, int*,
                                         hipStream_t);
+
+#define PA_BILU0_UPDATE(NV, VC)                                                               \
+    hipLaunchKernelGGL((k_pcg_update_bilu0<PT, NV, VC>), dim3(nb), dim3(kBL), 0, s, g, nc,  \
+                       coef, cs, dt, ip, x, r, p, q, z, st, part)
 
 template <class PT>
 void launch_pcg_update_bilu0(const Geo<double>& g, int nc, const double* coef, double cs,
@@ -361,8 +458,13 @@ void launch_pcg_update_bilu0(const Geo<double>& g, int nc, const double* coef, d
 {
     const int nb = bilu0_boxes(g.nr, g.nt, g.np);
     *nparts = nb;
-    hipLaunchKernelGGL((k_pcg_update_bilu0<PT>), dim3(nb), dim3(kBL), 0, s, g, nc, coef, cs, dt,
-                       ip, x, r, p, q, z, st, part);
+    if (chunk_of(nc) == kChunk && kChunk > 1) {
+        if (coef) PA_BILU0_UPDATE(kChunk, true);
+        else PA_BILU0_UPDATE(kChunk, false);
+    } else {
+        if (coef) PA_BILU0_UPDATE(1, true);
+        else PA_BILU0_UPDATE(1, false);
+    }
 }
 template void launch_pcg_update_bilu0<double>(const Geo<double>&, int, const double*, double,
                                               double, const double*, double*, double*,
