@@ -7,7 +7,8 @@ Dt_E, the practical time step limit, one RKL2 cycle (1e-12), and the FP64
 true residual of a Backward Euler solve evaluated with the oracle's
 operator.  Launch shapes are the ones the advances use at this size
 (several radial chunks, 33 x 64 tile planes, more than 2^31 bytes per
-array)."""
+array), and the block ILU(0) preconditioner's apply and BE solve on the
+three-component field (262144 boxes, fields of 3.2 GB)."""
 import numpy as np
 import pytest
 
@@ -100,3 +101,37 @@ def test_large_viscosity_apply(dev, oracle_mod):
         Fo = o.apply(prob.u, affine)
         assert np.abs(Fg - Fo).max() <= 1e-13 * np.abs(Fo).max()
     assert abs(g.dt_explicit() - o.dt_explicit()) <= 1e-13 * o.dt_explicit()
+
+
+def test_large_bilu0(dev, oracle_mod):
+    """Block ILU(0) (PC2) on the three-component 7-point operator at this size:
+    the preconditioner element-wise against the oracle's, and a BE solve
+    whose FP64 true residual, evaluated with the oracle's operator, meets
+    the tolerance."""
+    _log("building 256x512x1024 x 3 random field")
+    mesh = inputs.shell_mesh(*SHAPE)
+    rng = np.random.default_rng(506)
+    u = rng.standard_normal((3,) + SHAPE)
+    ub = rng.standard_normal((3, SHAPE[1], SHAPE[2]))
+    prob = inputs.Problem(mesh, "iso7", 3, u, ub, -ub, None, 1e-3, 0.0, None, name="visc_large")
+    g = dev.Operator.from_problem(prob)
+    g.set_options(pc=dev.PCS["bilu0"])
+    o = oracle_mod.Oracle.from_problem(prob)
+    o.set_pc("bilu0", (8, 4, 16))
+    dt = 5.0 * o.dt_explicit()
+    _log("large bilu0: apply")
+    zg = g.bilu0_apply(u, dt).cpu().numpy()
+    zo = o.precondition(u, dt)
+    assert np.abs(zg - zo).max() <= 1e-13 * np.abs(zo).max()
+    del zg, zo
+    _log("large bilu0: BE solve")
+    x = g.bind(u)
+    st = g.advance_be(dt, 1e-10, 1)
+    _log("  iterations", st["iters_total"])
+    V = o.volumes()[None]
+    b = V * u + dt * V * o.apply(np.zeros_like(u))
+    xh = x.cpu().numpy()
+    Mx = V * xh - dt * V * o.apply(xh, affine=False)
+    res = np.linalg.norm(b - Mx) / np.linalg.norm(b)
+    _log("  true residual", res)
+    assert res <= 1.001e-10
