@@ -366,14 +366,17 @@ __global__ __launch_bounds__(kBL) void k_pcg_update_bilu0(Geo<double> g, int nc,
                 const bool on = p.col && ii < p.nib;
                 const size_t m =
                     (c0 + v) * N + (size_t)(p.i0 + (on ? ii : 0)) * g.P + (on ? base : 0);
-                const double xv = on ? x[m] : 0.0, ro = on ? r[m] : 0.0;
-                const double pp = on ? (double)pv[m] : 0.0, qq = on ? (double)qv[m] : 0.0;
+                // x, r, p, q and z are streamed once: non-temporal accesses
+                const double xv = on ? __builtin_nontemporal_load(x + m) : 0.0;
+                const double ro = on ? __builtin_nontemporal_load(r + m) : 0.0;
+                const double pp = on ? (double)__builtin_nontemporal_load(pv + m) : 0.0;
+                const double qq = on ? (double)__builtin_nontemporal_load(qv + m) : 0.0;
                 const double rn = ro - alpha * qq;
                 rv[v][ii] = rn;
                 s_w[v * kBC + ii * kBL + lane] = rn;
                 if (on) {
-                    x[m] = xv + alpha * pp;
-                    r[m] = rn;
+                    __builtin_nontemporal_store(xv + alpha * pp, x + m);
+                    __builtin_nontemporal_store(rn, r + m);
                     rr += rn * rn;
                 }
             }
@@ -385,7 +388,7 @@ __global__ __launch_bounds__(kBL) void k_pcg_update_bilu0(Geo<double> g, int nc,
             for (int ii = 0; ii < kBI; ++ii)
                 if (p.col && ii < p.nib) {
                     const double zv = s_w[v * kBC + ii * kBL + lane];
-                    z[(c0 + v) * N + (size_t)(p.i0 + ii) * g.P + base] = zv;
+                    __builtin_nontemporal_store(zv, z + (c0 + v) * N + (size_t)(p.i0 + ii) * g.P + base);
                     rz += rv[v][ii] * zv;
                 }
     }

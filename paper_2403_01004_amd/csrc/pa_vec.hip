@@ -16,6 +16,14 @@ __device__ __forceinline__ double wsum(double v)
     return v;
 }
 
+// Streams read or written once per kernel bypass the caches' retention
+// (non-temporal): measured on MI355X, 4 reads + 2 writes over 55 M doubles
+// stream at 6.8 TB/s this way against 5.9 TB/s with ordinary accesses.
+template <class T>
+__device__ __forceinline__ T ldnt(const T* a) { return __builtin_nontemporal_load(a); }
+template <class T>
+__device__ __forceinline__ void stnt(T v, T* a) { __builtin_nontemporal_store(v, a); }
+
 // sum of part[0..n) by one workgroup of kRedBlock threads; result in thread 0
 __device__ double red_sum(const double* part, int n)
 {
@@ -291,12 +299,12 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(Geo<double> g, int nc, doub
         for (int c = 0; c < nc; ++c) {
             const size_t m = (size_t)c * N + cell;
             const double h = bnd ? hF[m] : 0.0;
-            const double b = V * u[m] + dt * V * h;
-            const double rv = dt * V * y0[m];
+            const double b = V * ldnt(u + m) + dt * V * h;
+            const double rv = dt * V * ldnt(y0 + m);
             const double z = rv / D;
-            r[m] = rv;
-            p[m] = (PT)z;
-            if (bout) bout[m] = b;
+            stnt(rv, r + m);
+            stnt((PT)z, p + m);
+            if (bout) stnt(b, bout + m);
             acc[0] += rv * z;
             acc[1] += rv * rv;
             acc[2] += b * b;
@@ -335,11 +343,11 @@ __global__ __launch_bounds__(kBlock) void k_pcg_resid(unsigned N, int nc, const 
         const double d = D[cell];
         for (int c = 0; c < nc; ++c) {
             const size_t m = (size_t)c * N + cell;
-            const double bv = b[m];
-            const double rv = bv - q[m];
+            const double bv = ldnt(b + m);
+            const double rv = bv - ldnt(q + m);
             const double z = rv / d;
-            r[m] = rv;
-            p[m] = (PT)z;
+            stnt(rv, r + m);
+            stnt((PT)z, p + m);
             acc[0] += rv * z;
             acc[1] += rv * rv;
             acc[2] += bv * bv;
@@ -412,10 +420,13 @@ void launch_pcg_alpha(const double* part, int n, DevState* st, hipStream_t s)
 
 // x += alpha p, r -= alpha q, z = r/D; partials <r,z>, <r,r>
 template <class PT>
-__global__ __launch_bounds__(kBlock) void k_pcg_update(unsigned N, int nc, const double* Db,
-                                                       double* x, double* r, const PT* p,
-                                                       const PT* q, const DevState* st,
-                                                       double* part)
+__global__ __launch_bounds__(kBlock) void k_pcg_update(unsigned N, int nc,
+                                                       const double* __restrict__ Db,
+                                                       double* __restrict__ x,
+                                                       double* __restrict__ r,
+                                                       const PT* __restrict__ p,
+                                                       const PT* __restrict__ q,
+                                                       const DevState* st, double* part)
 {
     if (st->done) return;
     const double alpha = st->alpha;
@@ -425,9 +436,9 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(unsigned N, int nc, const
         const double D = Db[cell];
         for (int c = 0; c < nc; ++c) {
             const size_t m = (size_t)c * N + cell;
-            x[m] += alpha * (double)p[m];
-            const double rv = r[m] - alpha * (double)q[m];
-            r[m] = rv;
+            stnt(ldnt(x + m) + alpha * (double)ldnt(p + m), x + m);
+            const double rv = ldnt(r + m) - alpha * (double)ldnt(q + m);
+            stnt(rv, r + m);
             const double z = rv / D;
             acc[0] += rv * z;
             acc[1] += rv * rv;
@@ -478,8 +489,10 @@ void launch_pcg_beta(const double* part, int n, DevState* st, hipStream_t s)
 
 // p = r/D + beta p
 template <class PT>
-__global__ __launch_bounds__(kBlock) void k_pcg_dir(unsigned N, int nc, const double* Db,
-                                                    const double* r, PT* p, const DevState* st)
+__global__ __launch_bounds__(kBlock) void k_pcg_dir(unsigned N, int nc,
+                                                    const double* __restrict__ Db,
+                                                    const double* __restrict__ r,
+                                                    PT* __restrict__ p, const DevState* st)
 {
     if (st->done) return;
     const double beta = st->beta;
@@ -488,7 +501,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_dir(unsigned N, int nc, const do
         const double D = Db[cell];
         for (int c = 0; c < nc; ++c) {
             const size_t m = (size_t)c * N + cell;
-            p[m] = (PT)(r[m] / D + beta * (double)p[m]);
+            stnt((PT)(ldnt(r + m) / D + beta * (double)ldnt(p + m)), p + m);
         }
     }
 }
@@ -515,7 +528,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_dir_z(size_t n, const double* __
     const double beta = st->beta;
     for (size_t m = (size_t)blockIdx.x * blockDim.x + threadIdx.x; m < n;
          m += (size_t)gridDim.x * blockDim.x)
-        p[m] = (PT)(z[m] + beta * (double)p[m]);
+        stnt((PT)(ldnt(z + m) + beta * (double)ldnt(p + m)), p + m);
 }
 
 template <class PT>
