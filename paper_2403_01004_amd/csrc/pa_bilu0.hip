@@ -400,9 +400,12 @@ __global__ __launch_bounds__(kBL) void k_pcg_update_bilu0(Geo<double> g, int nc,
     }
 }
 
-// components that share a sweep
-constexpr int kChunk = 1;
-int chunk_of(int nc) { return nc % kChunk == 0 ? kChunk : 1; }
+// Components that share a sweep's steps.  One: sharing the steps of three
+// components takes 8 KB more LDS per wave, and the lower occupancy costs
+// more than the shared step latency saves (measured 1.3x slower on the
+// three-component viscosity solve).
+constexpr int kNV = 1;
+static_assert(kNV == 1, "the launchers pass any number of components");
 
 }  // namespace
 
@@ -434,13 +437,8 @@ void launch_bilu0_solve(const Geo<double>& g, int nc, const double* coef, double
 {
     const int nb = bilu0_boxes(g.nr, g.nt, g.np);
     *nparts = nb;
-    if (chunk_of(nc) == kChunk && kChunk > 1) {
-        if (coef) PA_BILU0_SOLVE(kChunk, true);
-        else PA_BILU0_SOLVE(kChunk, false);
-    } else {
-        if (coef) PA_BILU0_SOLVE(1, true);
-        else PA_BILU0_SOLVE(1, false);
-    }
+    if (coef) PA_BILU0_SOLVE(kNV, true);
+    else PA_BILU0_SOLVE(kNV, false);
 }
 template void launch_bilu0_solve<double>(const Geo<double>&, int, const double*, double, double,
                                          const double*, const double*, double*, double*, int*,
@@ -461,13 +459,8 @@ void launch_pcg_update_bilu0(const Geo<double>& g, int nc, const double* coef, d
 {
     const int nb = bilu0_boxes(g.nr, g.nt, g.np);
     *nparts = nb;
-    if (chunk_of(nc) == kChunk && kChunk > 1) {
-        if (coef) PA_BILU0_UPDATE(kChunk, true);
-        else PA_BILU0_UPDATE(kChunk, false);
-    } else {
-        if (coef) PA_BILU0_UPDATE(1, true);
-        else PA_BILU0_UPDATE(1, false);
-    }
+    if (coef) PA_BILU0_UPDATE(kNV, true);
+    else PA_BILU0_UPDATE(kNV, false);
 }
 template void launch_pcg_update_bilu0<double>(const Geo<double>&, int, const double*, double,
                                               double, const double*, double*, double*,
