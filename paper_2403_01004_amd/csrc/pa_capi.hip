@@ -189,7 +189,7 @@ KArgs<T> base_args(pa_ctx* c, int r_lo, int r_hi)
     a.r_lo = r_lo;
     a.r_hi = r_hi;
     a.rch = c->rch;
-    a.nbx = blocks_per_plane(c->d.op, c->d.nt, c->d.np);
+    a.nbx = blocks_per_plane(c->d.op, c->d.nt, c->d.np, sizeof(T) == 4);
     a.nrc = (r_hi - r_lo + c->rch - 1) / c->rch;
     a.nc = c->d.ncomp;
     a.km2 = kKm2Array;
@@ -227,9 +227,9 @@ void stencil(pa_ctx* c, int mode, bool virt, const KArgs<T>& a)
     }
 }
 
-int ntiles(pa_ctx* c, int nlev)
+int ntiles(pa_ctx* c, int nlev, bool fp32 = false)
 {
-    return stencil_tiles(c->d.op, c->d.nt, c->d.np, nlev, c->rch, c->d.ncomp);
+    return stencil_tiles(c->d.op, c->d.nt, c->d.np, nlev, c->rch, c->d.ncomp, fp32);
 }
 
 hipEvent_t get_event(pa_ctx* c)
@@ -350,7 +350,8 @@ void first_pass(pa_ctx* c, const T* u0, T* y0)
         stencil<T>(c, kFirst, false, a);
     }
     KScope t(c, PA_K_REDUCE);
-    launch_ptl_finalize<T>(c->part, c->part_idx, ntiles(c, c->d.nr), u0, y0, c->d.ncomp, c->d.nr,
+    launch_ptl_finalize<T>(c->part, c->part_idx, ntiles(c, c->d.nr, sizeof(T) == 4), u0, y0,
+                           c->d.ncomp, c->d.nr,
                            c->d.nt, c->d.np, c->st, c->stream);
 }
 
@@ -558,7 +559,8 @@ pa_status pa_init(const pa_desc* d, void* stream, pa_ctx** out)
             ok = ok && c->f[q];
         }
     }
-    const size_t tiles = (size_t)stencil_tiles(d->op, nt, np, nr, c->rch, d->ncomp);
+    const size_t tiles = (size_t)std::max(stencil_tiles(d->op, nt, np, nr, c->rch, d->ncomp, false),
+                                          stencil_tiles(d->op, nt, np, nr, c->rch, d->ncomp, true));
     const size_t nblk = (N + kBlock - 1) / kBlock;
     ok = ok && ensure_parts(c, tiles > nblk ? (tiles > 4096 ? tiles : 4096) : (nblk > 4096 ? nblk : 4096));
     c->st = (DevState*)dev_alloc(c, sizeof(DevState));
@@ -957,7 +959,7 @@ template <class PT>
 void pcg_queue(pa_ctx* c, double dtc, double* r, PT* p, PT* q, int n)
 {
     const int nr = c->d.nr, nc = c->d.ncomp;
-    const int mt = ntiles(c, nr);
+    const int mt = ntiles(c, nr, sizeof(PT) == 4);
     int nparts = 0;
     // block ILU(0): the preconditioned residual goes to the y0 buffer, free
     // once the solve has started

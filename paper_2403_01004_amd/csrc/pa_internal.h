@@ -72,9 +72,9 @@ void launch_aligned(int mode, bool virt, const Geo<T>& g, const KArgs<T>& a, hip
 
 // workgroups covering one radial level (op: 0 7-point, 1 field-aligned),
 // and logical workgroups of a stencil launch over nlev levels (== entries
-// of a.part)
-int blocks_per_plane(int op, int nt, int np);
-int stencil_tiles(int op, int nt, int np, int nlev, int rch, int nc);
+// of a.part); the 7-point form depends on the precision (fp32)
+int blocks_per_plane(int op, int nt, int np, bool fp32 = false);
+int stencil_tiles(int op, int nt, int np, int nlev, int rch, int nc, bool fp32 = false);
 
 // setup kernels
 void launch_coef(const double* T0, double scale, double expo, const double* fc, double Tc, int P,

@@ -47,17 +47,17 @@ static inline int grid_for_tiles(int ntiles) { return ((ntiles + 7) / 8) * 8; }
 
 int tiles_per_plane(int nt, int np) { return ((np + TX - 1) / TX) * ((nt + TY - 1) / TY); }
 
-int iso7_blocks_per_plane(int nt, int np);
+int iso7_blocks_per_plane(int nt, int np, bool fp32);
 
-int blocks_per_plane(int op, int nt, int np)
+int blocks_per_plane(int op, int nt, int np, bool fp32)
 {
-    return op == 0 ? iso7_blocks_per_plane(nt, np) : tiles_per_plane(nt, np);
+    return op == 0 ? iso7_blocks_per_plane(nt, np, fp32) : tiles_per_plane(nt, np);
 }
 
-int stencil_tiles(int op, int nt, int np, int nlev, int rch, int nc)
+int stencil_tiles(int op, int nt, int np, int nlev, int rch, int nc, bool fp32)
 {
     const int nrc = (nlev + rch - 1) / rch;
-    return blocks_per_plane(op, nt, np) * nrc * nc;
+    return blocks_per_plane(op, nt, np, fp32) * nrc * nc;
 }
 
 // ------------------------------------------------------------ reductions
@@ -253,8 +253,16 @@ __device__ __forceinline__ T ldu(const KArgs<T>& a, const T* u, const T* y, size
 constexpr int W7 = 4;        // waves per workgroup
 constexpr int RCH_MAX = 32;  // radial levels per workgroup (at most)
 
-int iso7_blocks_per_plane(int nt, int np)
+// 7-point march form: 32 x 8 tiles staging each level in LDS for FP64
+// (measured on the 151x301x400 viscosity operator: matvec 213 against 296 us,
+// stage 406 against 474 us), wave rows reading the in-plane neighbours
+// through the caches for FP32 (10% faster there than the tiles)
+template <class T>
+constexpr bool iso7_tiled() { return sizeof(T) == 8; }
+
+int iso7_blocks_per_plane(int nt, int np, bool fp32)
 {
+    if (fp32 ? iso7_tiled<float>() : iso7_tiled<double>()) return tiles_per_plane(nt, np);
     const int nseg = (nt * np + 63) / 64;
     return (nseg + W7 - 1) / W7;
 }
@@ -419,6 +427,169 @@ __global__ __launch_bounds__(64 * W7) void k_iso7(Geo<T> g, KArgs<T> a)
                                          R0, um, cm, acc);
             step7<T, MODE, VIRT, CV, WT>(g, a, u, y, cb, t, i + 2, i0, i1, lgr, lgtr, lvr, R2, R0,
                                          R1, um, cm, acc);
+        }
+    }
+    finish<T, MODE>(a, L, acc);
+}
+
+// ------------------------------------------------------------ 7-point, tiled
+//
+// Tiles of 32 (phi) x 8 (theta) cells march a radial chunk.  Each level's
+// tile plane with its one-cell halo ring is staged in LDS (double
+// buffered, one barrier per level); the four in-plane neighbours are read
+// there, the radial ones come from the register ring (the own column,
+// loaded two levels ahead) and the previous level's carried value.  A
+// thread loads its own cell and, for 84 threads, one halo cell (the others
+// load a duplicate), so a level costs two loads per thread.
+
+template <class T, bool CV, int MODE, bool WT>
+struct LevT {
+    T x, h;           // own and halo cell
+    T cx, ch;         // coefficient at the same cells (CV)
+    T wt;             // cell weight of the own cell (WT)
+    Streams<T> st;    // stage streams of the own cell
+};
+
+template <class T, bool CV, int MODE, bool VIRT, bool WT>
+__device__ __forceinline__ void fetchT(const KArgs<T>& a, const T* u, const T* y, const TileMap& tm,
+                                       size_t lb, size_t sb, LevT<T, CV, MODE, WT>& R)
+{
+    R.x = ldu<T, VIRT>(a, u, y, lb + tm.own_off);
+    R.h = ldu<T, VIRT>(a, u, y, lb + tm.h_off);
+    if constexpr (CV) {
+        R.cx = a.coef[lb + tm.own_off];
+        R.ch = a.coef[lb + tm.h_off];
+    }
+    if constexpr (WT) R.wt = a.wgt[lb + tm.own_off];
+    load_streams<T, MODE>(a, sb, R.st);
+}
+
+template <class T>
+struct ShT {
+    T su[2][HN];
+    T sc[2][HN];
+    T gr[RCH_MAX + 3], gtr[RCH_MAX + 3], vr[RCH_MAX + 3];
+};
+
+template <class T, int MODE, bool VIRT, bool CV, bool WT>
+__device__ __forceinline__ void stepT(const Geo<T>& g, const KArgs<T>& a, const T* u, const T* y,
+                                      size_t cb, const TileMap& tm, const Pt7<T>& t, ShT<T>& sh,
+                                      int i, int i0, int i1,
+                                      const LevT<T, CV, MODE, WT>& Rc,
+                                      const LevT<T, CV, MODE, WT>& Rn,
+                                      LevT<T, CV, MODE, WT>& Rp, T& um, T& cm, Acc<T, MODE>& acc)
+{
+    const int nr = g.nr;
+    const size_t P = (size_t)g.P;
+    const int b = i & 1;
+    sh.su[b][tm.own_slot] = Rc.x;
+    if (tm.has_h) sh.su[b][tm.h_slot] = Rc.h;
+    if constexpr (CV) {
+        sh.sc[b][tm.own_slot] = Rc.cx;
+        if (tm.has_h) sh.sc[b][tm.h_slot] = Rc.ch;
+    }
+    {
+        const int lv = min(i + 2, nr - 1), ls = min(i + 2, i1 - 1);
+        fetchT<T, CV, MODE, VIRT, WT>(a, u, y, tm, (size_t)lv * P, cb + (size_t)ls * P + tm.own_off,
+                                      Rp);
+    }
+    __syncthreads();
+    const int o = tm.own_slot;
+    const T* su = sh.su[b];
+    const T uc = Rc.x;
+    const T uw = su[o - 1], ue = su[o + 1], us = su[o - HX], un = su[o + HX];
+    const T cc = CV ? Rc.cx : a.cs;
+    T cw = a.cs, ce = a.cs, cs_ = a.cs, cn = a.cs;
+    if constexpr (CV) {
+        const T* sc = sh.sc[b];
+        cw = sc[o - 1];
+        ce = sc[o + 1];
+        cs_ = sc[o - HX];
+        cn = sc[o + HX];
+    }
+    const T cu = CV ? Rn.cx : a.cs;
+    const int ic = min(i, nr - 1);
+    const T half = T(0.5);
+    const int il = ic - i0;
+    const T gtri = sh.gtr[il];
+    const bool lo = ic > 0, hi = ic < nr - 1;
+    const T Cl = lo ? half * (cc + cm) * (sh.gr[il] * t.Ar) : t.fin * cc * (sh.gr[il] * t.Ar);
+    const T ul = lo ? um : t.ubl;
+    const T Cu = hi ? half * (cc + cu) * (sh.gr[il + 1] * t.Ar) : t.fout * cc * (sh.gr[il + 1] * t.Ar);
+    const T uu = hi ? Rn.x : t.ubu;
+    T Lu = Cl * (uc - ul);
+    Lu += Cu * (uc - uu);
+    Lu += half * (cc + cs_) * (gtri * t.As) * (uc - us);
+    Lu += half * (cc + cn) * (gtri * t.An) * (uc - un);
+    Lu += half * (cc + cw) * (gtri * t.Aw) * (uc - uw);
+    Lu += half * (cc + ce) * (gtri * t.Ae) * (uc - ue);
+    const T V = WT ? sh.vr[il] * t.Ar * Rc.wt : sh.vr[il] * t.Ar;  // (w) V
+    if (t.valid && i < i1) epilogue<T, MODE>(a, cb + (size_t)ic * P + tm.own_off, Lu, V, uc, Rc.st, acc);
+    um = uc;
+    cm = cc;
+}
+
+template <class T, int MODE, bool VIRT, bool CV, bool WT>
+__global__ __launch_bounds__(kBlock) void k_iso7t(Geo<T> g, KArgs<T> a)
+{
+    __shared__ ShT<T> sh;
+    const int L = xcd_tile();
+    if (L >= a.nbx * a.nrc * a.nc) return;
+    if (a.done && *a.done) return;
+    const int nt = g.nt, np = g.np, nr = g.nr;
+    const size_t P = (size_t)g.P;
+    const int ntk = (np + TX - 1) / TX;
+    const int bx = L % a.nbx, rest = L / a.nbx, rc = rest % a.nrc, c = rest / a.nrc;
+    const TileMap tm = tile_map(bx % ntk, bx / ntk, nt, np);
+    Pt7<T> t;
+    t.valid = tm.valid;
+    const int j = min(tm.j, nt - 1), k = tm.valid ? tm.k : 0;
+    const int kp = (k == np - 1) ? 0 : k + 1;
+    // per-cell metric products (the missing row at a pole has zero coupling)
+    t.Ar = g.vt[j] * g.vp[k];
+    t.As = g.gtt[j] * g.vp[k];
+    t.An = g.gtt[j + 1] * g.vp[k];
+    t.Aw = g.gpt[j] * g.gpp[k];
+    t.Ae = g.gpt[j] * g.gpp[kp];
+    const size_t cb = (size_t)c * nr * P;
+    const T* u = a.u + cb;
+    const T* y = VIRT ? a.y0 + cb : nullptr;
+    const int i0 = a.r_lo + rc * a.rch;
+    const int i1 = min(a.r_hi, i0 + a.rch);
+    const size_t ob = (size_t)c * P + tm.own_off;
+    t.ubl = (a.affine && i0 == 0) ? a.ub_in[ob] : T(0);
+    t.ubu = (a.affine && i1 == nr) ? a.ub_out[ob] : T(0);
+    t.fin = (a.bc_in == 0) ? T(1) : T(0);
+    t.fout = (a.bc_out == 0) ? T(1) : T(0);
+    for (int q = threadIdx.x; q < RCH_MAX + 3; q += blockDim.x) {
+        const int lv = min(i0 + q, nr - 1);
+        sh.gr[q] = g.gr[min(i0 + q, nr)];
+        sh.gtr[q] = g.gtr[lv];
+        sh.vr[q] = g.vr[lv];
+    }
+    Acc<T, MODE> acc;
+    if (i0 < i1) {
+        LevT<T, CV, MODE, WT> R0, R1, R2;
+        T um = 0, cm = a.cs;
+        if (i0 > 0) {
+            um = ldu<T, VIRT>(a, u, y, (size_t)(i0 - 1) * P + tm.own_off);
+            if constexpr (CV) cm = a.coef[(size_t)(i0 - 1) * P + tm.own_off];
+        }
+        fetchT<T, CV, MODE, VIRT, WT>(a, u, y, tm, (size_t)i0 * P, cb + (size_t)i0 * P + tm.own_off,
+                                      R0);
+        {
+            const int lv = min(i0 + 1, nr - 1), ls = min(i0 + 1, i1 - 1);
+            fetchT<T, CV, MODE, VIRT, WT>(a, u, y, tm, (size_t)lv * P,
+                                          cb + (size_t)ls * P + tm.own_off, R1);
+        }
+        // three levels per trip with the ring's roles rotating
+        for (int i = i0; i < i1; i += 3) {
+            stepT<T, MODE, VIRT, CV, WT>(g, a, u, y, cb, tm, t, sh, i, i0, i1, R0, R1, R2, um, cm,
+                                         acc);
+            stepT<T, MODE, VIRT, CV, WT>(g, a, u, y, cb, tm, t, sh, i + 1, i0, i1, R1, R2, R0, um,
+                                         cm, acc);
+            stepT<T, MODE, VIRT, CV, WT>(g, a, u, y, cb, tm, t, sh, i + 2, i0, i1, R2, R0, R1, um,
+                                         cm, acc);
         }
     }
     finish<T, MODE>(a, L, acc);
@@ -683,6 +854,16 @@ static void go_iso7(const Geo<T>& g, const KArgs<T>& a, hipStream_t s)
     const int nt = a.nbx * a.nrc * a.nc;
     if (a.rch > RCH_MAX) return;  // the host never asks for longer chunks
     const dim3 gr(grid_for_tiles(nt)), bl(64 * W7);
+    if constexpr (iso7_tiled<T>()) {
+        if (a.coef) {
+            if (a.wgt) hipLaunchKernelGGL((k_iso7t<T, MODE, VIRT, true, true>), gr, bl, 0, s, g, a);
+            else hipLaunchKernelGGL((k_iso7t<T, MODE, VIRT, true, false>), gr, bl, 0, s, g, a);
+        } else {
+            if (a.wgt) hipLaunchKernelGGL((k_iso7t<T, MODE, VIRT, false, true>), gr, bl, 0, s, g, a);
+            else hipLaunchKernelGGL((k_iso7t<T, MODE, VIRT, false, false>), gr, bl, 0, s, g, a);
+        }
+        return;
+    }
     if (a.coef) {
         if (a.wgt) hipLaunchKernelGGL((k_iso7<T, MODE, VIRT, true, true>), gr, bl, 0, s, g, a);
         else hipLaunchKernelGGL((k_iso7<T, MODE, VIRT, true, false>), gr, bl, 0, s, g, a);
