@@ -6,8 +6,10 @@
 //                 + mu~ dt F(u_{k-1}) + gamma~ dt y0     (STS stage, App. A)
 //   kMatvec q = V p + dt L p, per-tile <p, q>          (BE system matvec)
 //
-// Work decomposition.  A workgroup of 256 threads owns a 32 (phi) x 8
-// (theta) tile of cells and marches over a chunk of radial levels.  Each
+// Work decomposition (field-aligned operator, and the 7-point operator in
+// FP64; the FP32 7-point form marches wave rows, described at its kernel).
+// A workgroup of 256 threads owns a 32 (phi) x 8 (theta) tile of cells and
+// marches over a chunk of radial levels.  Each
 // thread owns one tile cell and (threads 0..83) one cell of the one-cell
 // halo ring; per level it loads just those values -- plus, for the
 // field-aligned operator, the three coefficients of at most two corners, and
@@ -241,7 +243,7 @@ __device__ __forceinline__ T ldu(const KArgs<T>& a, const T* u, const T* y, size
 
 // ------------------------------------------------------------ 7-point
 //
-// Wave rows: each wave owns 64 consecutive cells of a radial level (phi
+// Wave rows (the FP32 form): each wave owns 64 consecutive cells of a radial level (phi
 // fastest, rows of theta following) and marches them over a chunk of
 // levels; the four in-plane neighbours are read straight from the caches
 // (neighbouring waves load them as their own cells), the radial neighbours
