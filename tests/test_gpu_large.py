@@ -7,8 +7,10 @@ Dt_E, the practical time step limit, one RKL2 cycle (1e-12), and the FP64
 true residual of a Backward Euler solve evaluated with the oracle's
 operator.  Launch shapes are the ones the advances use at this size
 (several radial chunks, 33 x 64 tile planes, more than 2^31 bytes per
-array), and the block ILU(0) preconditioner's apply and BE solve on the
-three-component field (262144 boxes, fields of 3.2 GB)."""
+array), the block ILU(0) preconditioner's apply and BE solve on the
+three-component field (262144 boxes, fields of 3.2 GB), and twenty
+consecutive advances with the diffusivity re-lagged before each one (FP32
+stages against FP64 on the same schedules)."""
 import numpy as np
 import pytest
 
@@ -134,4 +136,51 @@ def test_large_bilu0(dev, oracle_mod):
     Mx = V * xh - dt * V * o.apply(xh, affine=False)
     res = np.linalg.norm(b - Mx) / np.linalg.norm(b)
     _log("  true residual", res)
+    assert res <= 1.001e-10
+
+
+def test_large_sequence_fp32_stages(dev, oracle_mod, cond5):
+    """Twenty PTL-cycled RKL2 advances of the 256x512x1024 transition-region
+    conduction with the diffusivity re-lagged from the current field before
+    each advance and the time step fixed from the first (50 dt_E): FP32
+    stages against the FP64 path (which matches the oracle at this size) on
+    the same cycle schedules, then one Backward Euler advance of the FP64
+    field whose FP64 true residual, with the oracle's operator, meets the
+    tolerance."""
+    torch = pytest.importorskip("torch")
+    prob = cond5
+    g64 = dev.Operator.from_problem(prob)
+    g32 = dev.Operator.from_problem(prob, prec="fp32")
+    dt = 50.0 * g64.dt_explicit()
+    u64 = g64.bind(prob.u)
+    u32 = g32.bind(prob.u)
+    for adv in range(20):
+        if adv > 0:
+            g64.set_coefficients(u64[0], prob.scale, prob.expo, prob.B)
+            g32.set_coefficients(u32[0], prob.scale, prob.expo, prob.B)
+        st = g64.advance_rkl2(dt, 0)
+        g32.set_options(replay=np.asarray(st["dt_cycle"]))
+        s32 = g32.advance_rkl2(dt, 0)
+        g32.set_options()
+        assert s32["cycles"] == st["cycles"] and s32["s_total"] == st["s_total"]
+        assert bool(torch.isfinite(u64).all()) and bool(torch.isfinite(u32).all())
+        if adv % 5 == 4:
+            _log("large sequence: advance", adv + 1, "cycles", st["cycles"],
+                 "fp32 rel err", float(torch.linalg.vector_norm(u32 - u64) /
+                                       torch.linalg.vector_norm(u64)))
+    err = float(torch.linalg.vector_norm(u32 - u64) / torch.linalg.vector_norm(u64))
+    assert err <= 1e-5, err
+    del g32, u32
+    _log("large sequence: BE advance of the relaxed field")
+    g64.set_coefficients(u64[0], prob.scale, prob.expo, prob.B)
+    un = u64.cpu().numpy()
+    st = g64.advance_be(dt, 1e-10, 1)
+    x = u64.cpu().numpy()
+    o = oracle_mod.Oracle.from_problem(prob)
+    o.set_coefficients(un[0], prob.scale, prob.expo, prob.B)
+    V = o.volumes()[None]
+    b = V * un + dt * V * o.apply(np.zeros_like(un))
+    Mx = V * x - dt * V * o.apply(x, affine=False)
+    res = np.linalg.norm(b - Mx) / np.linalg.norm(b)
+    _log("  iterations", st["iters_total"], "true residual", res)
     assert res <= 1.001e-10
