@@ -80,10 +80,20 @@ def run_cpu_baseline(cond, budget_s=30.0):
     out, st = o.advance_sts(cond.u, 50 * dtE, cycles=1, sts="rkl2")
     t = time.perf_counter() - t0
     N = cond.mesh.ncells
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": N * st["s_total"] / t / 1e9, "unit": "Gpts/s", "cores": oracle.num_threads(),
             "kind": "oracle",
             "sample": f"one RKL2 cycle ({st['s_total']} stages, dt = 50 dt_E) of the 151x301x400 "
-                      f"field-aligned conduction advance; {t:.1f} s on the host"}
+                      f"field-aligned conduction advance; {t:.1f} s on {oracle.num_threads()} "
+                      f"threads of the host ({model})"}
 
 
 # committed counter summaries: roofline kernel -> (summary, source file of the kernel)
