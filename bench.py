@@ -386,6 +386,12 @@ def main():
     (dname, dcls), (dms, dcalls, dbytes) = max(kern.items(), key=lambda kv: kv[1][0])
     avg_ms = dms / dcalls
     achieved = dbytes / dcalls / (avg_ms / 1e3) / 1e9
+    # whole advances: algorithmic bytes of all their kernels over the advance's
+    # wall time (host syncs and reductions included)
+    for name, a in adv.items():
+        by = sum(v[2] for (an, _), v in kern.items() if an == name) / args.steps
+        a["GB_s"] = round(by / a["s"] / 1e9, 1) if a["s"] > 0 else None
+        a["hbm_frac"] = round(by / a["s"] / 1e9 / HBM_PEAK_GBS, 3) if a["s"] > 0 else None
     kernels = {f"{a}/{c}": {"ms_total": round(v[0] / args.steps, 3), "calls": v[1] // args.steps,
                             "avg_us": round(1e3 * v[0] / v[1], 2),
                             "GB_s": round(v[2] / (v[0] / 1e3) / 1e9, 1) if v[2] else None}

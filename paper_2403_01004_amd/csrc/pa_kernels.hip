@@ -440,7 +440,7 @@ __global__ __launch_bounds__(64 * W7) void k_iso7(Geo<T> g, KArgs<T> a)
 // tile plane with its one-cell halo ring is staged in LDS (double
 // buffered, one barrier per level); the four in-plane neighbours are read
 // there, the radial ones come from the register ring (the own column,
-// loaded two levels ahead) and the previous level's carried value.  A
+// loaded three levels ahead) and the previous level's carried value.  A
 // thread loads its own cell and, for 84 threads, one halo cell (the others
 // load a duplicate), so a level costs two loads per thread.
 
@@ -473,7 +473,7 @@ struct ShT {
     T gr[RCH_MAX + 3], gtr[RCH_MAX + 3], vr[RCH_MAX + 3];
 };
 
-template <class T, int MODE, bool VIRT, bool CV, bool WT>
+template <class T, int MODE, bool VIRT, bool CV, bool WT, int DEPTH>
 __device__ __forceinline__ void stepT(const Geo<T>& g, const KArgs<T>& a, const T* u, const T* y,
                                       size_t cb, const TileMap& tm, const Pt7<T>& t, ShT<T>& sh,
                                       int i, int i0, int i1,
@@ -491,7 +491,7 @@ __device__ __forceinline__ void stepT(const Geo<T>& g, const KArgs<T>& a, const 
         if (tm.has_h) sh.sc[b][tm.h_slot] = Rc.ch;
     }
     {
-        const int lv = min(i + 2, nr - 1), ls = min(i + 2, i1 - 1);
+        const int lv = min(i + DEPTH, nr - 1), ls = min(i + DEPTH, i1 - 1);
         fetchT<T, CV, MODE, VIRT, WT>(a, u, y, tm, (size_t)lv * P, cb + (size_t)ls * P + tm.own_off,
                                       Rp);
     }
@@ -584,14 +584,23 @@ __global__ __launch_bounds__(kBlock) void k_iso7t(Geo<T> g, KArgs<T> a)
             fetchT<T, CV, MODE, VIRT, WT>(a, u, y, tm, (size_t)lv * P,
                                           cb + (size_t)ls * P + tm.own_off, R1);
         }
-        // three levels per trip with the ring's roles rotating
-        for (int i = i0; i < i1; i += 3) {
-            stepT<T, MODE, VIRT, CV, WT>(g, a, u, y, cb, tm, t, sh, i, i0, i1, R0, R1, R2, um, cm,
-                                         acc);
-            stepT<T, MODE, VIRT, CV, WT>(g, a, u, y, cb, tm, t, sh, i + 1, i0, i1, R1, R2, R0, um,
-                                         cm, acc);
-            stepT<T, MODE, VIRT, CV, WT>(g, a, u, y, cb, tm, t, sh, i + 2, i0, i1, R2, R0, R1, um,
-                                         cm, acc);
+        // loads three levels ahead (a level costs two values per thread):
+        // four levels per trip with the ring's roles rotating
+        LevT<T, CV, MODE, WT> R3;
+        {
+            const int lv = min(i0 + 2, nr - 1), ls = min(i0 + 2, i1 - 1);
+            fetchT<T, CV, MODE, VIRT, WT>(a, u, y, tm, (size_t)lv * P,
+                                          cb + (size_t)ls * P + tm.own_off, R2);
+        }
+        for (int i = i0; i < i1; i += 4) {
+            stepT<T, MODE, VIRT, CV, WT, 3>(g, a, u, y, cb, tm, t, sh, i, i0, i1, R0, R1, R3,
+                                            um, cm, acc);
+            stepT<T, MODE, VIRT, CV, WT, 3>(g, a, u, y, cb, tm, t, sh, i + 1, i0, i1, R1, R2,
+                                            R0, um, cm, acc);
+            stepT<T, MODE, VIRT, CV, WT, 3>(g, a, u, y, cb, tm, t, sh, i + 2, i0, i1, R2, R3,
+                                            R1, um, cm, acc);
+            stepT<T, MODE, VIRT, CV, WT, 3>(g, a, u, y, cb, tm, t, sh, i + 3, i0, i1, R3, R0,
+                                            R2, um, cm, acc);
         }
     }
     finish<T, MODE>(a, L, acc);
