@@ -106,6 +106,7 @@ struct pa_ctx {
     __bf16* nn_g1 = nullptr;                     // [cap] output gradient
     float* nn_wpart = nullptr;                   // weight-gradient partials
     double* bilu0_ip = nullptr;  // [N] inverse block ILU(0) pivots of the current solve
+    int pcg_hint = 0;            // iterations of the last PCG solve (first batch of the next)
 };
 
 namespace {
@@ -1011,16 +1012,28 @@ void pcg_queue(pa_ctx* c, double dtc, double* r, PT* p, PT* q, int n)
 }
 
 // One PCG solve of M d = r0 from the state queued by launch_pcg_init /
-// launch_pcg_resid + launch_pcg_start: iterations are queued in batches of
-// pcg_batch and the host reads the device state after each batch.
+// launch_pcg_resid + launch_pcg_start: iterations are queued in batches and
+// the host reads the device state after each batch.  The first batch is the iteration count of the previous solve on the
+// context (the solves of a PTL-cycled advance take similar counts), capped
+// at pcg_batch; later batches are a quarter of pcg_batch.  Iterations queued
+// after the solve stopped exit at once but still cost their launches, so
+// a close first guess saves most of them at the price of a few more host
+// checks.
 template <class PT>
 pa_status pcg_loop(pa_ctx* c, double dtc, double* r, PT* p, PT* q)
 {
+    int batch = c->opt.pcg_batch;
+    if (c->opt.force_iters <= 0 && c->pcg_hint > 0) batch = std::min(batch, c->pcg_hint);
+    const int later = std::max(1, c->opt.pcg_batch / 4);
     while (true) {
-        pcg_queue<PT>(c, dtc, r, p, q, c->opt.pcg_batch);
+        pcg_queue<PT>(c, dtc, r, p, q, batch);
         pa_status s = sync_state(c);
         if (s) return s;
-        if (c->hst->done) return PA_OK;
+        if (c->hst->done) {
+            c->pcg_hint = c->hst->iters;
+            return PA_OK;
+        }
+        batch = later;
     }
 }
 
