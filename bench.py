@@ -270,8 +270,8 @@ def main():
                     help="extra legs reported beside the timed step: fp32, learned, bilu0, none")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the advance is built for a single MI355X "
-              "(multi-GPU sharding is not part of this build)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs the advance on a single "
+              "MI355X and does not shard it across GPUs", file=sys.stderr)
         sys.exit(2)
 
     import torch
