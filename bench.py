@@ -56,7 +56,7 @@ def bytes_per_launch(op, ncomp, cls, N, NCO, coef_var, stage_k=None):
     if cls == "dir":
         return 3 * f + 8 * N
     if cls == "init":
-        return 4 * f + 8 * N
+        return 4 * f + 16 * N   # u, y0, diag L read; r, p, D written
     return 0
 
 
