@@ -223,6 +223,36 @@ def learned_leg(paradv, inputs, torch, dev, nr, nt, np_, reps=2):
     }
 
 
+def rkg2_leg(paradv, torch, dev, cond, visc, reps=3):
+    """The paper's own STS scheme, RKG2 (App. A), PTL-cycled at dt = 50 dt_E on
+    both operators, beside BE+Jacobi-PCG on the same fields: seconds per
+    advance and the BE / RKG2 ratio (the comparison of Sec. 4)."""
+    out = {}
+    for name, prob in (("conduction", cond), ("viscosity", visc)):
+        g = paradv.Operator.from_problem(prob)
+        u0 = torch.as_tensor(prob.u, device=dev)
+        u = torch.empty_like(u0)
+        dt = 50 * g.dt_explicit()
+        res = {}
+        for kind in ("rkg2", "be"):
+            best = None
+            for k in range(reps + 1):
+                u.copy_(u0)
+                g.bind(u)
+                st = g.advance_rkg2(dt, 0) if kind == "rkg2" else g.advance_be(dt, 1e-10, 0)
+                if k > 0 and (best is None or st["ms_total"] < best["ms_total"]):
+                    best = st
+            res[kind] = {"s_per_advance": round(best["ms_total"] / 1e3, 4), "cycles": best["cycles"],
+                         "stages" if kind == "rkg2" else "pcg_iters":
+                             best["s_total"] if kind == "rkg2" else best["iters_total"]}
+        res["be_over_rkg2"] = round(res["be"]["s_per_advance"] /
+                                    max(res["rkg2"]["s_per_advance"], 1e-9), 2)
+        out[name] = res
+        del g
+        torch.cuda.empty_cache()
+    return out
+
+
 def bilu0_leg(paradv, inputs, torch, dev, visc, nr, nt, np_, reps=3):
     """BE with the block ILU(0) preconditioner (PC2 of Sec. 3.1) against
     point Jacobi (PC1) on the 7-point workloads: the three-component
@@ -266,8 +296,9 @@ def main():
     ap.add_argument("--shape", default="151,301,400")
     ap.add_argument("--leg-reps", type=int, default=3,
                     help="timed repetitions of each advance in the block ILU(0) leg")
-    ap.add_argument("--legs", default="fp32,learned,bilu0",
-                    help="extra legs reported beside the timed step: fp32, learned, bilu0, none")
+    ap.add_argument("--legs", default="fp32,learned,bilu0,rkg2",
+                    help="extra legs reported beside the timed step: fp32, learned, bilu0, "
+                         "rkg2, none")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library runs the advance on a single "
@@ -434,6 +465,9 @@ def main():
     if "learned" in legs:
         log("learned-preconditioner leg")
         out["learned_pc"] = learned_leg(paradv, inputs, torch, dev, nr, nt, np_)
+    if "rkg2" in legs:
+        log("RKG2 leg")
+        out["rkg2_vs_be"] = rkg2_leg(paradv, torch, dev, cond, visc)
     if "bilu0" in legs:
         log("block ILU(0) leg")
         out["bilu0_pc"] = bilu0_leg(paradv, inputs, torch, dev, visc, nr, nt, np_,
