@@ -226,7 +226,7 @@ def learned_leg(paradv, inputs, torch, dev, nr, nt, np_, reps=2):
 def rkg2_leg(paradv, torch, dev, cond, visc, reps=3):
     """The paper's own STS scheme, RKG2 (App. A), PTL-cycled at dt = 50 dt_E on
     both operators, beside BE+Jacobi-PCG on the same fields: seconds per
-    advance and the BE / RKG2 ratio (the comparison of Sec. 4)."""
+    advance and the BE / RKG2 ratio (the comparison of Sec. 4.2)."""
     out = {}
     for name, prob in (("conduction", cond), ("viscosity", visc)):
         g = paradv.Operator.from_problem(prob)
