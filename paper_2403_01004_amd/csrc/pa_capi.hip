@@ -986,6 +986,9 @@ void pcg_queue(pa_ctx* c, double dtc, double* r, PT* p, PT* q, int n)
         if (bilu0) {
             {
                 KScope t(c, PA_K_UPDATE);
+                // the block solve is bound by its wavefront steps, not by
+                // HBM: it takes the x update too (measured: cheaper than
+                // one more stream in the direction kernel)
                 launch_pcg_update_bilu0<PT>(g, nc, a64.coef, a64.cs, dtc, c->bilu0_ip, c->u, r, p,
                                             q, zb, c->st, c->part, &nparts, c->stream);
             }
@@ -994,12 +997,12 @@ void pcg_queue(pa_ctx* c, double dtc, double* r, PT* p, PT* q, int n)
                 launch_pcg_beta(c->part, nparts, c->st, c->stream);
             }
             KScope t(c, PA_K_DIR);
-            launch_pcg_dir_z<PT>(c->NT, zb, p, c->st, c->stream);
+            launch_pcg_dir_z<PT>(c->NT, zb, nullptr, p, c->st, c->stream);
             continue;
         }
         {
             KScope t(c, PA_K_UPDATE);
-            launch_pcg_update<PT>(c->N, nc, c->Dbuf, c->u, r, p, q, c->st, c->part, &nparts,
+            launch_pcg_update<PT>(c->N, nc, c->Dbuf, nullptr, r, p, q, c->st, c->part, &nparts,
                                   c->stream);
         }
         {
@@ -1007,7 +1010,7 @@ void pcg_queue(pa_ctx* c, double dtc, double* r, PT* p, PT* q, int n)
             launch_pcg_beta(c->part, nparts, c->st, c->stream);
         }
         KScope t(c, PA_K_DIR);
-        launch_pcg_dir<PT>(c->N, nc, c->Dbuf, r, p, c->st, c->stream);
+        launch_pcg_dir<PT>(c->N, nc, c->Dbuf, r, c->u, p, c->st, c->stream);
     }
 }
 

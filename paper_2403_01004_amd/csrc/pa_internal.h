@@ -101,6 +101,7 @@ struct DevState {
     double gmax;       // Gershgorin maximum
     double rho, pq, rz, rr, bb, alpha, beta, rr0, eta;
     int done, iters, status, nonfinite;
+    int xpend;         // this iteration's x += alpha p is left to the direction kernel
     int max_iter, force_iters, mode;
     double tol;
     double dt_full;    // full-grid limit (diagnostic)
@@ -126,13 +127,17 @@ void launch_pcg_resid(size_t N, int nc, const double* b, const double* q, const 
 void launch_pcg_start(const double* part, int n, DevState* st, double tol, int max_iter,
                       int force_iters, int mode, double eta, hipStream_t s);
 void launch_pcg_alpha(const double* part, int n, DevState* st, hipStream_t s);
+// r -= alpha q, partials <r, r/D>, <r, r>; also x += alpha p when x is not
+// null (otherwise launch_pcg_dir applies it, reading p once for both)
 template <class PT>
 void launch_pcg_update(size_t N, int nc, const double* D, double* x, double* r, const PT* p,
                        const PT* q, const DevState* st, double* part, int* nparts, hipStream_t s);
 void launch_pcg_beta(const double* part, int n, DevState* st, hipStream_t s);
+// x += alpha p (the update left by launch_pcg_update with x null), then
+// p = r/D + beta p unless the solve has stopped
 template <class PT>
-void launch_pcg_dir(size_t N, int nc, const double* D, const double* r, PT* p, const DevState* st,
-                    hipStream_t s);
+void launch_pcg_dir(size_t N, int nc, const double* D, const double* r, double* x, PT* p,
+                    const DevState* st, hipStream_t s);
 // face couplings L_{m,nb} for nb = r-, r+, t-, t+, p-, p+ into out[6][N]
 // (zero where the neighbour does not exist) (pa_setup.hip)
 void launch_couplings(const Geo<double>& g, int op, const double* coef, double cs, const double* e,
@@ -213,8 +218,11 @@ void launch_pcg_update_bilu0(const Geo<double>& g, int nc, const double* coef, d
                              double dt, const double* ip, double* x, double* r, const PT* p,
                              const PT* q, double* z, const DevState* st, double* part,
                              int* nparts, hipStream_t s);
+// p = z + beta p unless the solve has stopped; before it x += alpha p when
+// x is not null (the update kernel then left x alone)
 template <class PT>
-void launch_pcg_dir_z(size_t n, const double* z, PT* p, const DevState* st, hipStream_t s);
+void launch_pcg_dir_z(size_t n, const double* z, double* x, PT* p, const DevState* st,
+                      hipStream_t s);
 void launch_pcg_set_rho(const double* part, int n, DevState* st, hipStream_t s);  // !(a > 0) or NaN
 
 }  // namespace pa

@@ -389,6 +389,7 @@ __global__ __launch_bounds__(kRedBlock) void k_pcg_start(const double* part, int
     st->iters = 0;
     st->status = 0;
     st->done = 0;
+    st->xpend = 0;
     st->mode = mode;
     st->rr0 = rr;
     st->eta = eta;
@@ -405,9 +406,15 @@ void launch_pcg_start(const double* part, int n, DevState* st, double tol, int m
 
 __global__ __launch_bounds__(kRedBlock) void k_pcg_alpha(const double* part, int n, DevState* st)
 {
-    if (st->done) return;
+    // first kernel of an iteration to see the state: the previous
+    // iteration's x update has been applied by now
+    if (st->done) {
+        if (threadIdx.x == 0) st->xpend = 0;
+        return;
+    }
     const double pq = red_sum(part, n);
     if (threadIdx.x != 0) return;
+    st->xpend = 0;
     st->pq = pq;
     if (!(pq > 0.0) || !isfinite(pq)) { st->status = 5; st->done = 1; return; }
     st->alpha = st->rho / pq;
@@ -418,8 +425,10 @@ void launch_pcg_alpha(const double* part, int n, DevState* st, hipStream_t s)
     hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(kRedBlock), 0, s, part, n, st);
 }
 
-// x += alpha p, r -= alpha q, z = r/D; partials <r,z>, <r,r>
-template <class PT>
+// r -= alpha q, z = r/D, and x += alpha p when XU (otherwise k_pcg_dir
+// applies it: p is then read once per iteration instead of twice);
+// partials <r,z>, <r,r>
+template <class PT, bool XU>
 __global__ __launch_bounds__(kBlock) void k_pcg_update(unsigned N, int nc,
                                                        const double* __restrict__ Db,
                                                        double* __restrict__ x,
@@ -436,7 +445,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(unsigned N, int nc,
         const double D = Db[cell];
         for (int c = 0; c < nc; ++c) {
             const size_t m = (size_t)c * N + cell;
-            stnt(ldnt(x + m) + alpha * (double)ldnt(p + m), x + m);
+            if (XU) stnt(ldnt(x + m) + alpha * (double)ldnt(p + m), x + m);
             const double rv = ldnt(r + m) - alpha * (double)ldnt(q + m);
             stnt(rv, r + m);
             const double z = rv / D;
@@ -453,8 +462,12 @@ void launch_pcg_update(size_t N, int nc, const double* D, double* x, double* r, 
 {
     const int nb = vec_blocks(N);
     *nparts = nb;
-    hipLaunchKernelGGL((k_pcg_update<PT>), dim3(nb), dim3(kBlock), 0, s, (unsigned)N, nc, D, x, r,
-                       p, q, st, part);
+    if (x)
+        hipLaunchKernelGGL((k_pcg_update<PT, true>), dim3(nb), dim3(kBlock), 0, s, (unsigned)N, nc,
+                           D, x, r, p, q, st, part);
+    else
+        hipLaunchKernelGGL((k_pcg_update<PT, false>), dim3(nb), dim3(kBlock), 0, s, (unsigned)N, nc,
+                           D, x, r, p, q, st, part);
 }
 template void launch_pcg_update<double>(size_t, int, const double*, double*, double*, const double*,
                                         const double*, const DevState*, double*, int*, hipStream_t);
@@ -469,6 +482,7 @@ __global__ __launch_bounds__(kRedBlock) void k_pcg_beta(const double* part, int 
     const double rr = red_sum(part + n, n);
     if (threadIdx.x != 0) return;
     st->iters += 1;
+    st->xpend = 1;   // this iteration's update ran: its x update is due
     st->rr = rr;
     if (!isfinite(rr)) { st->status = 6; st->done = 1; return; }
     if (st->force_iters > 0) {
@@ -487,58 +501,79 @@ void launch_pcg_beta(const double* part, int n, DevState* st, hipStream_t s)
     hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(kRedBlock), 0, s, part, n, st);
 }
 
-// p = r/D + beta p
+// x += alpha p for the iteration whose update just ran (xpend: set by
+// k_pcg_beta, cleared by the next k_pcg_alpha), then p = r/D + beta p while
+// the solve goes on.  The iteration that stops the solve still applies its
+// x update here.
 template <class PT>
 __global__ __launch_bounds__(kBlock) void k_pcg_dir(unsigned N, int nc,
                                                     const double* __restrict__ Db,
                                                     const double* __restrict__ r,
+                                                    double* __restrict__ x,
                                                     PT* __restrict__ p, const DevState* st)
 {
-    if (st->done) return;
-    const double beta = st->beta;
+    if (!st->xpend) return;
+    const double alpha = st->alpha, beta = st->beta;
+    const bool more = !st->done;
     for (unsigned cell = blockIdx.x * blockDim.x + threadIdx.x; cell < N;
          cell += gridDim.x * blockDim.x) {
-        const double D = Db[cell];
+        const double D = more ? Db[cell] : 1.0;   // the last launch reads x and p only
         for (int c = 0; c < nc; ++c) {
             const size_t m = (size_t)c * N + cell;
-            stnt((PT)(ldnt(r + m) / D + beta * (double)ldnt(p + m)), p + m);
+            const double pv = (double)ldnt(p + m);
+            stnt(ldnt(x + m) + alpha * pv, x + m);
+            if (more) stnt((PT)(ldnt(r + m) / D + beta * pv), p + m);
         }
     }
 }
 
 template <class PT>
-void launch_pcg_dir(size_t N, int nc, const double* D, const double* r, PT* p, const DevState* st,
-                    hipStream_t s)
+void launch_pcg_dir(size_t N, int nc, const double* D, const double* r, double* x, PT* p,
+                    const DevState* st, hipStream_t s)
 {
     const int nb = vec_blocks(N);
-    hipLaunchKernelGGL((k_pcg_dir<PT>), dim3(nb), dim3(kBlock), 0, s, (unsigned)N, nc, D, r, p, st);
+    hipLaunchKernelGGL((k_pcg_dir<PT>), dim3(nb), dim3(kBlock), 0, s, (unsigned)N, nc, D, r, x, p,
+                       st);
 }
-template void launch_pcg_dir<double>(size_t, int, const double*, const double*, double*,
+template void launch_pcg_dir<double>(size_t, int, const double*, const double*, double*, double*,
                                      const DevState*, hipStream_t);
-template void launch_pcg_dir<float>(size_t, int, const double*, const double*, float*,
+template void launch_pcg_dir<float>(size_t, int, const double*, const double*, double*, float*,
                                     const DevState*, hipStream_t);
 
-// p = z + beta p, with z the preconditioned residual stored by a block
-// preconditioner (all components, n = nc * N values)
-template <class PT>
+// p = z + beta p while the solve goes on, with z the preconditioned
+// residual stored by a block preconditioner (all components, n = nc * N
+// values); with XU, x += alpha p first, run condition as k_pcg_dir
+template <class PT, bool XU>
 __global__ __launch_bounds__(kBlock) void k_pcg_dir_z(size_t n, const double* __restrict__ z,
+                                                      double* __restrict__ x,
                                                       PT* __restrict__ p, const DevState* st)
 {
-    if (st->done) return;
-    const double beta = st->beta;
+    if (XU ? !st->xpend : st->done) return;
+    const double alpha = st->alpha, beta = st->beta;
+    const bool more = !st->done;
     for (size_t m = (size_t)blockIdx.x * blockDim.x + threadIdx.x; m < n;
-         m += (size_t)gridDim.x * blockDim.x)
-        stnt((PT)(ldnt(z + m) + beta * (double)ldnt(p + m)), p + m);
+         m += (size_t)gridDim.x * blockDim.x) {
+        const double pv = (double)ldnt(p + m);
+        if (XU) stnt(ldnt(x + m) + alpha * pv, x + m);
+        if (more) stnt((PT)(ldnt(z + m) + beta * pv), p + m);
+    }
 }
 
 template <class PT>
-void launch_pcg_dir_z(size_t n, const double* z, PT* p, const DevState* st, hipStream_t s)
+void launch_pcg_dir_z(size_t n, const double* z, double* x, PT* p, const DevState* st,
+                      hipStream_t s)
 {
-    hipLaunchKernelGGL((k_pcg_dir_z<PT>), dim3(vec_blocks(n)), dim3(kBlock), 0, s, n, z, p, st);
+    if (x)
+        hipLaunchKernelGGL((k_pcg_dir_z<PT, true>), dim3(vec_blocks(n)), dim3(kBlock), 0, s, n, z,
+                           x, p, st);
+    else
+        hipLaunchKernelGGL((k_pcg_dir_z<PT, false>), dim3(vec_blocks(n)), dim3(kBlock), 0, s, n, z,
+                           x, p, st);
 }
-template void launch_pcg_dir_z<double>(size_t, const double*, double*, const DevState*,
+template void launch_pcg_dir_z<double>(size_t, const double*, double*, double*, const DevState*,
                                        hipStream_t);
-template void launch_pcg_dir_z<float>(size_t, const double*, float*, const DevState*, hipStream_t);
+template void launch_pcg_dir_z<float>(size_t, const double*, double*, float*, const DevState*,
+                                      hipStream_t);
 
 // rho = <r, z> from the partials of a preconditioner applied after
 // launch_pcg_start (which set rho for point Jacobi)

@@ -18,13 +18,14 @@ N, NCO = 1000, 1010
 @pytest.mark.parametrize("cls,op,nc,per_cell", [
     ("first", "aligned", 1, 16 + 24 * 1.01),          # u, y0 + e
     ("matvec", "aligned", 1, 16 + 24 * 1.01),         # p, q + e
-    ("update", "aligned", 1, 48 + 8),                 # x, p, r, q, D; x, r
-    ("dir", "aligned", 1, 24 + 8),                    # r, p, D; p
+    ("update", "aligned", 1, 24 + 8),                 # r, q, D; r
+    ("dir", "aligned", 1, 40 + 8),                    # r, p, x, D; p, x
     ("first", "iso7", 3, 3 * 16),
     ("matvec", "iso7", 3, 3 * 16),
-    ("update", "iso7", 3, 3 * 48 + 8),                # 152 B per cell
-    ("dir", "iso7", 3, 3 * 24 + 8),
+    ("update", "iso7", 3, 3 * 24 + 8),                # 80 B per cell
+    ("dir", "iso7", 3, 3 * 40 + 8),                   # 128 B per cell
     ("init", "iso7", 3, 3 * 32 + 16),                 # u, y0, diag L; r, p, D
+    ("dir_last", "iso7", 3, 3 * 24),                  # x, p; x
 ])
 def test_bytes_per_cell(cls, op, nc, per_cell):
     got = bench.bytes_per_launch(op, nc, cls, N, NCO, False) / N
@@ -44,3 +45,11 @@ def test_stage_bytes_per_cycle():
         (3 * 3 * f + 4 * 3 * f) + 3 * 3 * f
     # a variable 7-point coefficient adds one read per launch
     assert bench.bytes_per_launch("iso7", 1, "matvec", N, NCO, True) == 2 * f + 8 * N
+
+
+def test_dir_saving():
+    """One short direction launch per solve that took iterations."""
+    f = 8 * N
+    per = bench.bytes_per_launch("iso7", 3, "dir", N, NCO, False) - 9 * f
+    assert per == 6 * f + 8 * N
+    assert bench.dir_saving("iso7", 3, N, NCO, [12, 0, 7, 1]) == 3 * per
