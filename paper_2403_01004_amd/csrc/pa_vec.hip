@@ -24,29 +24,57 @@ __device__ __forceinline__ T ldnt(const T* a) { return __builtin_nontemporal_loa
 template <class T>
 __device__ __forceinline__ void stnt(T v, T* a) { __builtin_nontemporal_store(v, a); }
 
-// sum of part[0..n) by one workgroup of kRedBlock threads; result in thread 0
-__device__ double red_sum(const double* part, int n)
+// K sums of part[q*n .. q*n + n) by one workgroup of kRedBlock threads,
+// results in thread 0.  The K arrays are read in the same loop, so their
+// loads overlap (the stopping test needs two sums, the start of a solve
+// three); each sum's order is fixed and independent of K.
+template <int K>
+__device__ void red_sums(const double* part, int n, double (&out)[K])
 {
-    __shared__ double lds[kRedBlock / 64];
-    // eight independent accumulators keep eight loads in flight per thread
-    // (the partials of a cell-sized grid number N / 256)
+    __shared__ double lds[K][kRedBlock / 64];
+    // eight independent accumulators per sum keep eight loads per sum in
+    // flight per thread (the partials of a cell-sized grid number N / 512)
     const int bd = blockDim.x;
-    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double a[K][8];
+#pragma unroll
+    for (int q = 0; q < K; ++q)
+#pragma unroll
+        for (int t = 0; t < 8; ++t) a[q][t] = 0.0;
     int i = threadIdx.x;
     for (; i + 7 * bd < n; i += 8 * bd) {
 #pragma unroll
-        for (int t = 0; t < 8; ++t) a[t] += part[i + t * bd];
+        for (int q = 0; q < K; ++q)
+#pragma unroll
+            for (int t = 0; t < 8; ++t) a[q][t] += part[(size_t)q * n + i + t * bd];
     }
-    for (; i < n; i += bd) a[0] += part[i];
-    double v = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
-    v = wsum(v);
+    for (; i < n; i += bd)
+#pragma unroll
+        for (int q = 0; q < K; ++q) a[q][0] += part[(size_t)q * n + i];
+    double v[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q)
+        v[q] = wsum(((a[q][0] + a[q][1]) + (a[q][2] + a[q][3])) +
+                    ((a[q][4] + a[q][5]) + (a[q][6] + a[q][7])));
     __syncthreads();
-    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int q = 0; q < K; ++q) lds[q][threadIdx.x >> 6] = v[q];
     __syncthreads();
-    double s = 0.0;
     if (threadIdx.x == 0)
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += lds[w];
-    return s;
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            double s = 0.0;
+            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += lds[q][w];
+            out[q] = s;
+        }
+}
+
+// sum of part[0..n) by one workgroup of kRedBlock threads; result in thread 0
+__device__ double red_sum(const double* part, int n)
+{
+    double s[1] = {0.0};
+    red_sums<1>(part, n, s);
+    return s[0];
 }
 
 __global__ __launch_bounds__(kRedBlock) void k_reduce_max(const double* part, int n, double* outp)
@@ -376,9 +404,9 @@ __global__ __launch_bounds__(kRedBlock) void k_pcg_start(const double* part, int
                                                           double tol, int max_iter, int force_iters,
                                                           int mode, double eta)
 {
-    const double rz = red_sum(part, n);
-    const double rr = red_sum(part + n, n);
-    const double bb = red_sum(part + 2 * n, n);
+    double sums[3] = {0.0, 0.0, 0.0};
+    red_sums<3>(part, n, sums);
+    const double rz = sums[0], rr = sums[1], bb = sums[2];
     if (threadIdx.x != 0) return;
     st->tol = tol;
     st->max_iter = max_iter;
@@ -478,8 +506,9 @@ template void launch_pcg_update<float>(size_t, int, const double*, double*, doub
 __global__ __launch_bounds__(kRedBlock) void k_pcg_beta(const double* part, int n, DevState* st)
 {
     if (st->done) return;
-    const double rz = red_sum(part, n);
-    const double rr = red_sum(part + n, n);
+    double sums[2] = {0.0, 0.0};
+    red_sums<2>(part, n, sums);
+    const double rz = sums[0], rr = sums[1];
     if (threadIdx.x != 0) return;
     st->iters += 1;
     st->xpend = 1;   // this iteration's update ran: its x update is due
