@@ -240,8 +240,12 @@ hipEvent_t get_event(pa_ctx* c)
         c->ev_free.pop_back();
         return e;
     }
+    // timing-only events: no system-scope fence at record time (the host
+    // reads them after a stream synchronisation).  With the default fence
+    // every record writes back and invalidates the caches, which opened a
+    // ~10 us gap before and after each timed launch.
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
 }
 
