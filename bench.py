@@ -100,11 +100,30 @@ def run_cpu_baseline(cond, budget_s=30.0):
                     break
     except OSError:
         pass
-    return {"value": N * st["s_total"] / t / 1e9, "unit": "Gpts/s", "cores": oracle.num_threads(),
+    # one operator application at all threads and at one thread, and the
+    # host's memory bandwidth (STREAM triad), as references for the figure
+    threads = oracle.num_threads()
+
+    def apply_s():
+        t0 = time.perf_counter()
+        o.apply(cond.u)
+        return time.perf_counter() - t0
+
+    t_all = min(apply_s() for _ in range(2))
+    try:
+        oracle.set_num_threads(1)
+        t_one = apply_s()
+    finally:
+        oracle.set_num_threads(threads)
+    triad = oracle.stream_triad(1 << 26, 5)
+    return {"value": N * st["s_total"] / t / 1e9, "unit": "Gpts/s", "cores": threads,
             "kind": "oracle",
             "sample": f"one RKL2 cycle ({st['s_total']} stages, dt = 50 dt_E) of the 151x301x400 "
-                      f"field-aligned conduction advance; {t:.1f} s on {oracle.num_threads()} "
-                      f"threads of the host ({model})"}
+                      f"field-aligned conduction advance; {t:.1f} s on {threads} "
+                      f"threads of the host ({model})",
+            "apply_Gpts_s": {"threads": threads, "all_threads": round(N / t_all / 1e9, 4),
+                             "one_thread": round(N / t_one / 1e9, 4)},
+            "host_stream_triad_GB_s": round(triad, 1), "nproc": os.cpu_count()}
 
 
 # committed counter summaries: roofline kernel -> (summary, source file of the kernel)

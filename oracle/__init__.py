@@ -86,6 +86,10 @@ def _load():
     lib.or_sts_stages.argtypes = [i, d, i]
     lib.or_num_threads.restype = i
     lib.or_num_threads.argtypes = []
+    lib.or_set_num_threads.restype = None
+    lib.or_set_num_threads.argtypes = [i]
+    lib.or_stream_triad.restype = d
+    lib.or_stream_triad.argtypes = [ctypes.c_long, i]
     lib.or_set_pc.restype = i
     lib.or_set_pc.argtypes = [vp, i, i, i, i]
     ip = ctypes.POINTER(ctypes.c_int)
@@ -124,6 +128,19 @@ def sts_coeffs(kind: str, s: int):
 def num_threads() -> int:
     """OpenMP threads used by the oracle's parallel loops."""
     return int(_load().or_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads for the oracle's following parallel loops (n < 1: one per
+    processor)."""
+    _load().or_set_num_threads(int(n))
+
+
+def stream_triad(n: int = 1 << 26, reps: int = 5) -> float:
+    """Host memory bandwidth in GB/s (STREAM triad over n doubles per array,
+    best of reps) at the current thread count; a reference for the CPU
+    timings, not part of the method."""
+    return float(_load().or_stream_triad(int(n), int(reps)))
 
 
 def sts_stages(kind: str, ratio: float, force_odd: bool = True) -> int:

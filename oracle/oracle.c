@@ -1116,3 +1116,49 @@ int or_num_threads(void)
     return 1;
 #endif
 }
+
+/* threads for the following parallel loops (n < 1: one per processor) */
+void or_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : omp_get_num_procs());
+#else
+    (void)n;
+#endif
+}
+
+/* Host memory bandwidth for the CPU timings (not part of the method): the
+ * STREAM triad a = b + 3 c over n doubles per array, first touch in
+ * parallel, best of reps; 24 bytes per element.  Returns GB/s, or -1 when
+ * the arrays cannot be allocated. */
+double or_stream_triad(long n, int reps)
+{
+    double* a = (double*)malloc(sizeof(double) * (size_t)n);
+    double* b = (double*)malloc(sizeof(double) * (size_t)n);
+    double* c = (double*)malloc(sizeof(double) * (size_t)n);
+    double best = -1.0;
+    if (a && b && c) {
+#pragma omp parallel for schedule(static)
+        for (long i = 0; i < n; ++i) {
+            a[i] = 0.0;
+            b[i] = 1.0;
+            c[i] = 2.0;
+        }
+        for (int r = 0; r < reps; ++r) {
+#ifdef _OPENMP
+            const double t0 = omp_get_wtime();
+#endif
+#pragma omp parallel for schedule(static)
+            for (long i = 0; i < n; ++i) a[i] = b[i] + 3.0 * c[i];
+#ifdef _OPENMP
+            const double t = omp_get_wtime() - t0;
+            const double gbs = 24.0 * (double)n / t / 1e9;
+            if (t > 0.0 && gbs > best) best = gbs;
+#endif
+        }
+    }
+    free(a);
+    free(b);
+    free(c);
+    return best;
+}

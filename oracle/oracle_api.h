@@ -38,6 +38,8 @@ double or_ptl(or_ctx* o, const double* u, int64_t* kmax);
 int or_sts_coeffs(int kind, int s, double* mu, double* nu, double* mut, double* gam);
 int or_sts_stages(int kind, double ratio, int force_odd);
 int or_num_threads(void);
+void or_set_num_threads(int n);
+double or_stream_triad(long n, int reps);
 int or_set_pc(or_ctx* o, int pc, int bi, int bj, int bk);
 int or_bilu0_export(const or_ctx* o, double dt, int* rowp, int* col, double* m0, double* lu,
                     int cap);
