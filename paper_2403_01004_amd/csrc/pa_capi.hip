@@ -957,9 +957,12 @@ pa_status pa_advance_rkg2(pa_ctx* c, double dt, int32_t cycles, pa_stats* st)
 namespace {
 
 // Queue n PCG iterations (each skipped on the device once the solve is
-// done), point Jacobi or block ILU(0) preconditioned.  PT is the storage type of the search direction and the matvec
-// (double, or float for the FP32-matvec inner solves); x, r and all scalars
-// are FP64.
+// done), point Jacobi or block ILU(0) preconditioned.  PT is the storage
+// type of the search direction and the matvec (double, or float for the
+// FP32-matvec inner solves); x, r and all scalars are FP64.  Point Jacobi:
+// matvec, alpha, r update, stopping test, then x += alpha p together with
+// the new direction (p is read once for both; the iteration that stops the
+// solve still applies its x update there).
 template <class PT>
 void pcg_queue(pa_ctx* c, double dtc, double* r, PT* p, PT* q, int n)
 {
