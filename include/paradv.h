@@ -124,8 +124,9 @@ enum {
     PA_K_FIRST = 0,   /* y0 = F(u) + argmax |F| (PTL pass) */
     PA_K_STAGE = 1,   /* fused STS stage */
     PA_K_MATVEC = 2,  /* PCG matvec q = M p + <p,q> */
-    PA_K_UPDATE = 3,  /* PCG x, r update + <r,z>, <r,r> */
-    PA_K_DIR = 4,     /* PCG direction p = z + beta p */
+    PA_K_UPDATE = 3,  /* PCG r update + <r,z>, <r,r> (point Jacobi; block ILU(0): x and r
+                         update fused with the block solve) */
+    PA_K_DIR = 4,     /* PCG direction p = z + beta p (point Jacobi: with x += alpha p) */
     PA_K_INIT = 5,    /* PCG start (residual, boundary data) */
     PA_K_REDUCE = 6,  /* one-workgroup reductions and scalar updates */
     PA_K_OTHER = 7,   /* conversions and copies */
