@@ -61,6 +61,7 @@ struct or_ctx {
     int nr, nt, np, nc, op, bc_in, bc_out;
     double *R, *TH, *PH;     /* faces */
     double *rc, *tc, *pc;    /* centres */
+    double *cth, *sth, *stc; /* cos, sin of the theta faces; sin of the theta centres */
     double period;
     double *coef;            /* cell coefficient c, [nr*nt*np] */
     double *bhat;            /* corner unit field [3][(nr+1)(nt+1)np] */
@@ -91,7 +92,7 @@ double or_volume(const or_ctx* o, int i, int j, int k)
 {
     const double* R = o->R;
     return (R[i + 1] * R[i + 1] * R[i + 1] - R[i] * R[i] * R[i]) / 3.0 *
-           (cos(o->TH[j]) - cos(o->TH[j + 1])) * (o->PH[k + 1] - o->PH[k]);
+           (o->cth[j] - o->cth[j + 1]) * (o->PH[k + 1] - o->PH[k]);
 }
 
 /* distance in phi between the centres of cells k-1 and k (periodic) */
@@ -105,7 +106,7 @@ static double dphi_centres(const or_ctx* o, int k)
  * r-face "ir" lies at r_faces[ir], ir in [0,nr]. */
 static double trans_r(const or_ctx* o, int ir, int j, int k)
 {
-    const double area = o->R[ir] * o->R[ir] * (cos(o->TH[j]) - cos(o->TH[j + 1])) *
+    const double area = o->R[ir] * o->R[ir] * (o->cth[j] - o->cth[j + 1]) *
                         (o->PH[k + 1] - o->PH[k]);
     double d;
     if (ir == 0) d = o->rc[0] - o->R[0];
@@ -116,7 +117,7 @@ static double trans_r(const or_ctx* o, int ir, int j, int k)
 /* theta-face jt in [1,nt-1] between cells jt-1 and jt, at radius cell i */
 static double trans_t(const or_ctx* o, int i, int jt, int k)
 {
-    const double area = sin(o->TH[jt]) * 0.5 * (o->R[i + 1] * o->R[i + 1] - o->R[i] * o->R[i]) *
+    const double area = o->sth[jt] * 0.5 * (o->R[i + 1] * o->R[i + 1] - o->R[i] * o->R[i]) *
                         (o->PH[k + 1] - o->PH[k]);
     const double d = o->rc[i] * (o->tc[jt] - o->tc[jt - 1]);
     return area / d;
@@ -126,7 +127,7 @@ static double trans_p(const or_ctx* o, int i, int j, int k)
 {
     const double area = 0.5 * (o->R[i + 1] * o->R[i + 1] - o->R[i] * o->R[i]) *
                         (o->TH[j + 1] - o->TH[j]);
-    const double d = o->rc[i] * sin(o->tc[j]) * dphi_centres(o, k);
+    const double d = o->rc[i] * o->stc[j] * dphi_centres(o, k);
     return area / d;
 }
 
@@ -148,7 +149,7 @@ static void corner_metric(const or_ctx* o, int ic, int jc, int kc, double* hr, d
         wr = *hr;
     }
     *ht = o->R[ic] * (o->tc[jc] - o->tc[jc - 1]);
-    *hp = o->R[ic] * sin(o->TH[jc]) * dphi_centres(o, kc);
+    *hp = o->R[ic] * o->sth[jc] * dphi_centres(o, kc);
     *W = wr * *ht * *hp;
 }
 
@@ -173,6 +174,12 @@ or_ctx* or_create(int nr, int nt, int np, int nc, const double* r_faces, const d
     for (int i = 0; i < nr; ++i) o->rc[i] = 0.5 * (o->R[i] + o->R[i + 1]);
     for (int j = 0; j < nt; ++j) o->tc[j] = 0.5 * (o->TH[j] + o->TH[j + 1]);
     for (int k = 0; k < np; ++k) o->pc[k] = 0.5 * (o->PH[k] + o->PH[k + 1]);
+    /* the trigonometric factors of the metric, evaluated once */
+    o->cth = (double*)malloc(sizeof(double) * (nt + 1));
+    o->sth = (double*)malloc(sizeof(double) * (nt + 1));
+    o->stc = (double*)malloc(sizeof(double) * nt);
+    for (int j = 0; j <= nt; ++j) { o->cth[j] = cos(o->TH[j]); o->sth[j] = sin(o->TH[j]); }
+    for (int j = 0; j < nt; ++j) o->stc[j] = sin(o->tc[j]);
     o->period = o->PH[np] - o->PH[0];
     o->coef = (double*)malloc(sizeof(double) * ncell(o));
     for (size_t m = 0; m < ncell(o); ++m) o->coef[m] = 1.0;
@@ -189,6 +196,7 @@ void or_destroy(or_ctx* o)
 {
     if (!o) return;
     free(o->R); free(o->TH); free(o->PH); free(o->rc); free(o->tc); free(o->pc);
+    free(o->cth); free(o->sth); free(o->stc);
     free(o->coef); free(o->bhat); free(o->ub_in); free(o->ub_out); free(o->fbuf);
     free(o->wgt); free(o->fc);
     free(o);
@@ -698,10 +706,12 @@ static void sts_cycle(or_ctx* o, double* u, double dt, int kind, int s)
     double* Fk = (double*)malloc(n * sizeof(double));
     memcpy(u0, u, n * sizeof(double));
     or_apply(o, u0, y0, 1);                                   /* y0 = F(u0) */
+#pragma omp parallel for schedule(static)
     for (size_t m = 0; m < n; ++m) ukm1[m] = u0[m] + mut[1] * dt * y0[m];   /* u1 */
     memcpy(ukm2, u0, n * sizeof(double));
     for (int k = 2; k <= s; ++k) {
         or_apply(o, ukm1, Fk, 1);
+#pragma omp parallel for schedule(static)
         for (size_t m = 0; m < n; ++m)
             uk[m] = mu[k] * ukm1[m] + nu[k] * ukm2[m] + (1.0 - mu[k] - nu[k]) * u0[m] +
                     mut[k] * dt * Fk[m] + gam[k] * dt * y0[m];
@@ -865,6 +875,7 @@ static void precondition(const or_ctx* o, const or_csr* F, const double* D, cons
     for (int c = 0; c < o->nc; ++c) {
         if (o->pcond == OR_PC_BILU0) bilu0_solve(F, r + c * N, z + c * N);
         else
+#pragma omp parallel for schedule(static)
             for (size_t m = 0; m < N; ++m) z[c * N + m] = r[c * N + m] / D[m];
     }
 }
@@ -927,11 +938,24 @@ int or_precondition(const or_ctx* o, double dt, const double* r, double* z)
 
 /* ------------------------------------------------------------ BE + PCG */
 
+/* Inner product in a fixed order, independent of the thread count (the
+ * paper fixes none): consecutive blocks of DOT_BLOCK terms are summed in
+ * index order, then the block sums in block order. */
+#define DOT_BLOCK 16384
 static double dot(const double* a, const double* b, size_t n)
 {
-    /* fixed-order sum so that the oracle is reproducible */
+    const size_t nb = (n + DOT_BLOCK - 1) / DOT_BLOCK;
+    double* part = (double*)malloc((nb ? nb : 1) * sizeof(double));
+#pragma omp parallel for schedule(static)
+    for (size_t q = 0; q < nb; ++q) {
+        const size_t m1 = (q + 1) * DOT_BLOCK < n ? (q + 1) * DOT_BLOCK : n;
+        double s = 0.0;
+        for (size_t m = q * DOT_BLOCK; m < m1; ++m) s += a[m] * b[m];
+        part[q] = s;
+    }
     double s = 0.0;
-    for (size_t m = 0; m < n; ++m) s += a[m] * b[m];
+    for (size_t q = 0; q < nb; ++q) s += part[q];
+    free(part);
     return s;
 }
 
@@ -941,6 +965,7 @@ static void be_matvec(or_ctx* o, const double* x, double* y, double dt, double* 
     or_apply(o, x, tmp, 0);
     const size_t N = ncell(o);
     for (int c = 0; c < o->nc; ++c)
+#pragma omp parallel for schedule(static)
         for (int i = 0; i < o->nr; ++i)
             for (int j = 0; j < o->nt; ++j)
                 for (int k = 0; k < o->np; ++k) {
@@ -972,6 +997,7 @@ static int be_solve(or_ctx* o, double* u, double dt, double tol, int max_iter, i
     double* Ld = (double*)malloc(N * sizeof(double));
     double* D = (double*)malloc(N * sizeof(double));
     or_diag(o, Ld);
+#pragma omp parallel for schedule(static)
     for (int i = 0; i < o->nr; ++i)
         for (int j = 0; j < o->nt; ++j)
             for (int k = 0; k < o->np; ++k) {
@@ -981,6 +1007,7 @@ static int be_solve(or_ctx* o, double* u, double dt, double tol, int max_iter, i
     /* b = V u^n + dt h, with h = V F(0) the boundary-data part of F */
     or_apply(o, zero, tmp, 1);
     for (int c = 0; c < o->nc; ++c)
+#pragma omp parallel for schedule(static)
         for (int i = 0; i < o->nr; ++i)
             for (int j = 0; j < o->nt; ++j)
                 for (int k = 0; k < o->np; ++k) {
@@ -990,6 +1017,7 @@ static int be_solve(or_ctx* o, double* u, double dt, double tol, int max_iter, i
                 }
     memcpy(x, u, n * sizeof(double));
     be_matvec(o, x, q, dt, tmp);
+#pragma omp parallel for schedule(static)
     for (size_t m = 0; m < n; ++m) r[m] = b[m] - q[m];
     or_csr F;
     memset(&F, 0, sizeof(F));
@@ -1011,7 +1039,9 @@ static int be_solve(or_ctx* o, double* u, double dt, double tol, int max_iter, i
         const double pq = dot(p, q, n);
         if (!(pq > 0.0) || !isfinite(pq)) { status = 5; break; }
         const double alpha = rho / pq;
+#pragma omp parallel for schedule(static)
         for (size_t m = 0; m < n; ++m) x[m] += alpha * p[m];
+#pragma omp parallel for schedule(static)
         for (size_t m = 0; m < n; ++m) r[m] -= alpha * q[m];
         rnorm = sqrt(dot(r, r, n));
         if (force_iters > 0) { if (it == force_iters) break; }
@@ -1019,6 +1049,7 @@ static int be_solve(or_ctx* o, double* u, double dt, double tol, int max_iter, i
         precondition(o, &F, D, r, z);
         const double rho1 = dot(r, z, n);
         const double beta = rho1 / rho;
+#pragma omp parallel for schedule(static)
         for (size_t m = 0; m < n; ++m) p[m] = z[m] + beta * p[m];
         rho = rho1;
     }
