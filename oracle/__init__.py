@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 MAX_LOG = 4096
 
-OPS = {"iso7": 0, "aligned": 1}
+OPS = {"iso7": 0, "aligned": 1, "viscv": 2}
 BCS = {"dirichlet": 0, "noflux": 1}
 STS = {"rkl2": 0, "rkg2": 1}
 PCS = {"jacobi": 0, "bilu0": 2}

@@ -19,7 +19,11 @@
  *     field-aligned term as L = G^T W K G over cell corners, with G the
  *     corner gradient averaged over four cell-centre differences per
  *     direction, K = kappa bhat bhat^T and W the corner dual volume),
- *     which is symmetric positive semi-definite by construction;
+ *     which is symmetric positive semi-definite by construction; and the
+ *     vector form of Eq. (visc) for a velocity in spherical components, the
+ *     7-point operator on its Cartesian components written in each cell's
+ *     spherical basis (faces couple a cell to its neighbour's vector
+ *     rotated into that basis: the curvature coupling of the components);
  *   - the explicit Euler limit dt_E = 2 / rho, rho a Gershgorin bound on
  *     V^{-1} L (App. A uses dt_Euler without defining it);
  *   - the practical time step limit of Eqs. (ptl)-(ptl3): the one-sided
@@ -54,6 +58,7 @@
 
 #define OR_ISO7 0
 #define OR_ALIGNED 1
+#define OR_VISCV 2   /* vector form of Eq. (visc), components (v_r, v_theta, v_phi) */
 #define OR_DIRICHLET 0
 #define OR_NOFLUX 1
 
@@ -62,6 +67,7 @@ struct or_ctx {
     double *R, *TH, *PH;     /* faces */
     double *rc, *tc, *pc;    /* centres */
     double *cth, *sth, *stc; /* cos, sin of the theta faces; sin of the theta centres */
+    double *ctc, *cpc, *spc; /* cos of the theta centres; cos, sin of the phi centres */
     double period;
     double *coef;            /* cell coefficient c, [nr*nt*np] */
     double *bhat;            /* corner unit field [3][(nr+1)(nt+1)np] */
@@ -159,6 +165,7 @@ or_ctx* or_create(int nr, int nt, int np, int nc, const double* r_faces, const d
                   const double* p_faces, int op, int bc_in, int bc_out)
 {
     if (nr < 1 || nt < 2 || np < 3 || nc < 1) return NULL;
+    if (op == OR_VISCV && nc != 3) return NULL;
     or_ctx* o = (or_ctx*)calloc(1, sizeof(or_ctx));
     o->nr = nr; o->nt = nt; o->np = np; o->nc = nc; o->op = op;
     o->bc_in = bc_in; o->bc_out = bc_out;
@@ -180,6 +187,11 @@ or_ctx* or_create(int nr, int nt, int np, int nc, const double* r_faces, const d
     o->stc = (double*)malloc(sizeof(double) * nt);
     for (int j = 0; j <= nt; ++j) { o->cth[j] = cos(o->TH[j]); o->sth[j] = sin(o->TH[j]); }
     for (int j = 0; j < nt; ++j) o->stc[j] = sin(o->tc[j]);
+    o->ctc = (double*)malloc(sizeof(double) * nt);
+    o->cpc = (double*)malloc(sizeof(double) * np);
+    o->spc = (double*)malloc(sizeof(double) * np);
+    for (int j = 0; j < nt; ++j) o->ctc[j] = cos(o->tc[j]);
+    for (int k = 0; k < np; ++k) { o->cpc[k] = cos(o->pc[k]); o->spc[k] = sin(o->pc[k]); }
     o->period = o->PH[np] - o->PH[0];
     o->coef = (double*)malloc(sizeof(double) * ncell(o));
     for (size_t m = 0; m < ncell(o); ++m) o->coef[m] = 1.0;
@@ -196,7 +208,7 @@ void or_destroy(or_ctx* o)
 {
     if (!o) return;
     free(o->R); free(o->TH); free(o->PH); free(o->rc); free(o->tc); free(o->pc);
-    free(o->cth); free(o->sth); free(o->stc);
+    free(o->cth); free(o->sth); free(o->stc); free(o->ctc); free(o->cpc); free(o->spc);
     free(o->coef); free(o->bhat); free(o->ub_in); free(o->ub_out); free(o->fbuf);
     free(o->wgt); free(o->fc);
     free(o);
@@ -343,6 +355,93 @@ static void apply_iso7(const or_ctx* o, int c, const double* u, double* F, int a
             }
 }
 
+/* Spherical unit vectors at the centre of cell column (j,k), in Cartesian
+ * components: e[0] = r-hat, e[1] = theta-hat, e[2] = phi-hat. */
+static void centre_basis(const or_ctx* o, int j, int k, double e[3][3])
+{
+    const double st = o->stc[j], ct = o->ctc[j], cp = o->cpc[k], sp = o->spc[k];
+    e[0][0] = st * cp; e[0][1] = st * sp; e[0][2] = ct;
+    e[1][0] = ct * cp; e[1][1] = ct * sp; e[1][2] = -st;
+    e[2][0] = -sp;     e[2][1] = cp;      e[2][2] = 0.0;
+}
+
+/* Change of basis between two cell columns: T[a][b] = e_a(j,k) . e_b(j2,k2),
+ * so that sum_b T[a][b] v_b is component a, in the basis of (j,k), of the
+ * vector whose components in the basis of (j2,k2) are v_b. */
+static void change_of_basis(const or_ctx* o, int j, int k, int j2, int k2, double T[3][3])
+{
+    double e[3][3], f[3][3];
+    centre_basis(o, j, k, e);
+    centre_basis(o, j2, k2, f);
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) T[a][b] = e[a][0] * f[b][0] + e[a][1] * f[b][1] + e[a][2] * f[b][2];
+}
+
+/* Vector form of Eq. (visc): v in spherical components (v_r, v_theta,
+ * v_phi) at the cell centres.  div(c grad v) of a vector is the 7-point
+ * operator of apply_iso7 acting on its Cartesian components; written in
+ * each cell's own spherical basis, a face adds C_f (v_m - T v_nb), with T
+ * the change of basis from the neighbour's unit vectors to the cell's (the
+ * curvature coupling between the components).  Radial neighbours and the
+ * radial boundary points share the cell's (theta, phi): there T = I, and
+ * the Dirichlet data are spherical components at the boundary point. */
+static void apply_viscv(const or_ctx* o, const double* u, double* F, int affine)
+{
+    const int nr = o->nr, nt = o->nt, np = o->np;
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < nr; ++i)
+        for (int j = 0; j < nt; ++j)
+            for (int k = 0; k < np; ++k) {
+                const size_t mc = cell_ix(o, 0, i, j, k);
+                const double cm = o->coef[mc];
+                double Lu[3] = {0.0, 0.0, 0.0};
+                double um[3];
+                for (int a = 0; a < 3; ++a) um[a] = u[cell_ix(o, a, i, j, k)];
+                /* radial faces: same basis on both sides */
+                if (i > 0) {
+                    const double C = 0.5 * (cm + o->coef[cell_ix(o, 0, i - 1, j, k)]) * trans_r(o, i, j, k);
+                    for (int a = 0; a < 3; ++a) Lu[a] += C * (um[a] - u[cell_ix(o, a, i - 1, j, k)]);
+                } else if (o->bc_in == OR_DIRICHLET) {
+                    const double C = cm * trans_r(o, 0, j, k);
+                    for (int a = 0; a < 3; ++a) {
+                        const double ub = affine ? o->ub_in[((size_t)a * nt + j) * np + k] : 0.0;
+                        Lu[a] += C * (um[a] - ub);
+                    }
+                }
+                if (i < nr - 1) {
+                    const double C = 0.5 * (cm + o->coef[cell_ix(o, 0, i + 1, j, k)]) * trans_r(o, i + 1, j, k);
+                    for (int a = 0; a < 3; ++a) Lu[a] += C * (um[a] - u[cell_ix(o, a, i + 1, j, k)]);
+                } else if (o->bc_out == OR_DIRICHLET) {
+                    const double C = cm * trans_r(o, nr, j, k);
+                    for (int a = 0; a < 3; ++a) {
+                        const double ub = affine ? o->ub_out[((size_t)a * nt + j) * np + k] : 0.0;
+                        Lu[a] += C * (um[a] - ub);
+                    }
+                }
+                /* colatitude and longitude faces: neighbour rotated into this cell's basis */
+                const int km = (k + np - 1) % np, kp = (k + 1) % np;
+                const int nbj[4] = {j - 1, j + 1, j, j}, nbk[4] = {k, k, km, kp};
+                for (int f = 0; f < 4; ++f) {
+                    const int j2 = nbj[f], k2 = nbk[f];
+                    if (j2 < 0 || j2 >= nt) continue;   /* no face across a pole */
+                    double C;
+                    if (f == 0) C = trans_t(o, i, j, k);
+                    else if (f == 1) C = trans_t(o, i, j + 1, k);
+                    else if (f == 2) C = trans_p(o, i, j, k);
+                    else C = trans_p(o, i, j, kp);
+                    C *= 0.5 * (cm + o->coef[cell_ix(o, 0, i, j2, k2)]);
+                    double T[3][3];
+                    change_of_basis(o, j, k, j2, k2, T);
+                    double vn[3];
+                    for (int b = 0; b < 3; ++b) vn[b] = u[cell_ix(o, b, i, j2, k2)];
+                    for (int a = 0; a < 3; ++a)
+                        Lu[a] += C * (um[a] - (T[a][0] * vn[0] + T[a][1] * vn[1] + T[a][2] * vn[2]));
+                }
+                const double V = wvol(o, i, j, k);
+                for (int a = 0; a < 3; ++a) F[cell_ix(o, a, i, j, k)] = -Lu[a] / V;
+            }
+}
+
 /* For corner (ic,jc,kc): the value seen at slot (a,b,e) in {0,1}^3 (a radial:
  * 0 lower / 1 upper, b colatitude, e longitude).  Real cells give their
  * value; the mirror ghost across a radial boundary gives 2 u_b - u
@@ -461,6 +560,10 @@ static void apply_aligned(or_ctx* o, int c, const double* u, double* F, int affi
 
 void or_apply(or_ctx* o, const double* u, double* F, int affine)
 {
+    if (o->op == OR_VISCV) {
+        apply_viscv(o, u, F, affine);
+        return;
+    }
     for (int c = 0; c < o->nc; ++c) {
         if (o->op == OR_ISO7) apply_iso7(o, c, u, F, affine);
         else apply_aligned(o, c, u, F, affine);
@@ -472,12 +575,15 @@ void or_apply(or_ctx* o, const double* u, double* F, int affine)
 /* Row data of L for cell (i,j,k): diag = L_mm and abs_row = a Gershgorin
  * bound on sum_n |L_mn| (exact for the 7-point operator; for the corner
  * operator the sum over corners of the row sums of each corner's rank-one
- * block, which bounds the exact row sum from above). */
+ * block, which bounds the exact row sum from above).  The vector form of
+ * Eq. (visc) is the 7-point operator on the Cartesian components in a
+ * rotated basis (an orthogonal similarity), so it has the 7-point
+ * operator's diagonal and spectrum: its bound is the 7-point one. */
 static void row_bounds(const or_ctx* o, int i, int j, int k, double* diag, double* absrow)
 {
     const int nr = o->nr, nt = o->nt, np = o->np;
     double d = 0.0, s = 0.0;
-    if (o->op == OR_ISO7) {
+    if (o->op == OR_ISO7 || o->op == OR_VISCV) {
         const double cm = o->coef[cell_ix(o, 0, i, j, k)];
         double off = 0.0, C;
         if (i > 0) { C = 0.5 * (cm + o->coef[cell_ix(o, 0, i - 1, j, k)]) * trans_r(o, i, j, k); d += C; off += C; }

@@ -166,7 +166,7 @@ def uniform_direction_corners(mesh: Mesh, comp: int):
 class Problem:
     """One split parabolic operator's inputs."""
     mesh: Mesh
-    op: str                 # "iso7" or "aligned"
+    op: str                 # "iso7", "viscv" (vector viscosity) or "aligned"
     ncomp: int
     u: np.ndarray           # (ncomp, nr, nt, np) initial field
     ub_in: np.ndarray       # (ncomp, nt, np) Dirichlet data at r_in
@@ -205,9 +205,12 @@ def conduction(nr=151, nt=301, np_=400, seed=201, noise_amp=0.01, stretch=1.02):
                    dipole_corners(mesh), name=f"conduction_{nr}x{nt}x{np_}")
 
 
-def viscosity(nr=151, nt=301, np_=400, seed=202, noise_amp=0.01, nu=1e-3, stretch=1.02):
+def viscosity(nr=151, nt=301, np_=400, seed=202, noise_amp=0.01, nu=1e-3, stretch=1.02,
+              vector=False):
     """Artificial viscosity nu Lap v on three velocity components,
-    v_c = 0.1 S(seed+c) + 0.01 eta_c, Dirichlet v at both radial boundaries."""
+    v_c = 0.1 S(seed+c) + 0.01 eta_c, Dirichlet v at both radial boundaries.
+    vector: the components are the spherical (v_r, v_theta, v_phi) of one
+    vector field (operator "viscv"); else three scalars ("iso7")."""
     mesh = shell_mesh(nr, nt, np_, stretch=stretch)
     u, ui, uo = [], [], []
     for c in range(3):
@@ -215,8 +218,9 @@ def viscosity(nr=151, nt=301, np_=400, seed=202, noise_amp=0.01, nu=1e-3, stretc
         u.append(0.1 * s + noise_amp * noise(rng, s.shape))
         ui.append(0.1 * s_in)
         uo.append(0.1 * s_out)
-    return Problem(mesh, "iso7", 3, np.stack(u), np.stack(ui), np.stack(uo), None, nu, 0.0,
-                   None, name=f"viscosity_{nr}x{nt}x{np_}")
+    return Problem(mesh, "viscv" if vector else "iso7", 3, np.stack(u), np.stack(ui),
+                   np.stack(uo), None, nu, 0.0, None,
+                   name=f"viscosity{'_vec' if vector else ''}_{nr}x{nt}x{np_}")
 
 
 def transition_region(nr=151, nt=301, np_=400, seed=401, i_tr0=12.0, i_amp=3.0,
