@@ -63,7 +63,16 @@ typedef enum {
     PA_ERR_MAXCYCLES = 8   /* the time-step limit needs more than max_cycles cycles */
 } pa_status;
 
-typedef enum { PA_OP_ISO7 = 0, PA_OP_FIELD_ALIGNED = 1 } pa_op;
+/* PA_OP_ISO7: div(c grad u) of each component as a scalar (7-point);
+ * PA_OP_FIELD_ALIGNED: div(c bhat bhat . grad u) (corner scheme);
+ * PA_OP_VISC_VECTOR: Eq. (visc) for a velocity given by its spherical
+ * components (ncomp = 3: v_r, v_theta, v_phi) -- the 7-point operator on
+ * the Cartesian components, written in each cell's spherical basis, so a
+ * colatitude or longitude face couples the cell to the neighbour's vector
+ * rotated into that basis (the curvature coupling of the components).  It
+ * has the 7-point operator's diagonal and spectrum (an orthogonal change of
+ * basis), hence its explicit limit. */
+typedef enum { PA_OP_ISO7 = 0, PA_OP_FIELD_ALIGNED = 1, PA_OP_VISC_VECTOR = 2 } pa_op;
 typedef enum { PA_BC_DIRICHLET = 0, PA_BC_NOFLUX = 1 } pa_bc;
 typedef enum { PA_FP64 = 0, PA_FP32_STAGES = 1 } pa_prec;
 typedef enum { PA_STS_RKL2 = 0, PA_STS_RKG2 = 1 } pa_sts;
@@ -81,7 +90,7 @@ typedef enum { PA_PC_JACOBI = 0, PA_PC_LEARNED = 1, PA_PC_BILU0 = 2 } pa_pc;
  * memory, copied during pa_init: r_faces[nr+1] and t_faces[nt+1] strictly
  * increasing with 0 <= t_faces < = pi, p_faces[np+1] strictly increasing
  * (one period = p_faces[np] - p_faces[0]).  nr >= 1, nt >= 2, np >= 3,
- * ncomp >= 1.  prec selects FP64 throughout or FP32 storage and stencil
+ * ncomp >= 1 (ncomp = 3 for PA_OP_VISC_VECTOR).  prec selects FP64 throughout or FP32 storage and stencil
  * arithmetic for the STS stages (FP64 recurrence coefficients, FP64
  * combination and FP64 reductions). */
 typedef struct {

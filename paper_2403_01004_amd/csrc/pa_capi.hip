@@ -18,12 +18,13 @@
 
 using namespace pa;
 
+
 namespace {
 
 template <class T>
 struct MetricDev {
     T *vr = nullptr, *vt = nullptr, *vp = nullptr, *gr = nullptr, *gtr = nullptr, *gtt = nullptr,
-      *gpt = nullptr, *gpp = nullptr;
+      *gpt = nullptr, *gpp = nullptr, *rtf = nullptr, *rtc = nullptr, *rpf = nullptr;
 };
 
 }  // namespace
@@ -154,7 +155,7 @@ Geo<T> geo(const pa_ctx* c, const MetricDev<T>& m)
     Geo<T> g;
     g.nr = c->d.nr; g.nt = c->d.nt; g.np = c->d.np; g.P = (int)c->P;
     g.vr = m.vr; g.vt = m.vt; g.vp = m.vp; g.gr = m.gr; g.gtr = m.gtr; g.gtt = m.gtt;
-    g.gpt = m.gpt; g.gpp = m.gpp;
+    g.gpt = m.gpt; g.gpp = m.gpp; g.rtf = m.rtf; g.rtc = m.rtc; g.rpf = m.rpf;
     return g;
 }
 
@@ -193,6 +194,7 @@ KArgs<T> base_args(pa_ctx* c, int r_lo, int r_hi)
     a.nbx = blocks_per_plane(c->d.op, c->d.nt, c->d.np, sizeof(T) == 4);
     a.nrc = (r_hi - r_lo + c->rch - 1) / c->rch;
     a.nc = c->d.ncomp;
+    a.only_c = -1;
     a.km2 = kKm2Array;
     a.part = c->part;
     a.part_idx = c->part_idx;
@@ -220,10 +222,12 @@ void stencil(pa_ctx* c, int mode, bool virt, const KArgs<T>& a)
     if constexpr (sizeof(T) == 8) {
         const Geo<double> g = geo(c, c->m64);
         if (c->d.op == PA_OP_ISO7) launch_iso7<double>(mode, virt, g, a, c->stream);
+        else if (c->d.op == PA_OP_VISC_VECTOR) launch_viscv<double>(mode, virt, g, a, c->stream);
         else launch_aligned<double>(mode, virt, g, a, c->stream);
     } else {
         const Geo<float> g = geo(c, c->m32);
         if (c->d.op == PA_OP_ISO7) launch_iso7<float>(mode, virt, g, a, c->stream);
+        else if (c->d.op == PA_OP_VISC_VECTOR) launch_viscv<float>(mode, virt, g, a, c->stream);
         else launch_aligned<float>(mode, virt, g, a, c->stream);
     }
 }
@@ -457,7 +461,9 @@ pa_status pa_init(const pa_desc* d, void* stream, pa_ctx** out)
     if (d->nr < 1 || d->nt < 2 || d->np < 3 || d->ncomp < 1 || !d->r_faces || !d->t_faces ||
         !d->p_faces)
         return PA_ERR_ARG;
-    if (d->op != PA_OP_ISO7 && d->op != PA_OP_FIELD_ALIGNED) return PA_ERR_ARG;
+    if (d->op != PA_OP_ISO7 && d->op != PA_OP_FIELD_ALIGNED && d->op != PA_OP_VISC_VECTOR)
+        return PA_ERR_ARG;
+    if (d->op == PA_OP_VISC_VECTOR && d->ncomp != 3) return PA_ERR_ARG;
     if ((d->bc_in != PA_BC_DIRICHLET && d->bc_in != PA_BC_NOFLUX) ||
         (d->bc_out != PA_BC_DIRICHLET && d->bc_out != PA_BC_NOFLUX))
         return PA_ERR_ARG;
@@ -523,6 +529,19 @@ pa_status pa_init(const pa_desc* d, void* stream, pa_ctx** out)
     }
     for (int jc = 1; jc < nt; ++jc) htt[jc] = tc[jc] - tc[jc - 1];
     for (int jc = 0; jc <= nt; ++jc) sT[jc] = sin(TH[jc]);
+    // change of basis between neighbouring cell centres (vector viscosity)
+    std::vector<double> rtf(2 * (nt + 1)), rtc(2 * nt), rpf(2 * np);
+    for (int jt = 0; jt <= nt; ++jt) {
+        const double d = (jt > 0 && jt < nt) ? tc[jt] - tc[jt - 1] : 0.0;
+        rtf[jt] = cos(d);
+        rtf[nt + 1 + jt] = sin(d);
+    }
+    for (int j = 0; j < nt; ++j) { rtc[j] = sin(tc[j]); rtc[nt + j] = cos(tc[j]); }
+    for (int k = 0; k < np; ++k) {
+        const double h = sin(0.5 * dpc[k]);
+        rpf[k] = 2.0 * h * h;  // 1 - cos, without cancellation
+        rpf[np + k] = sin(dpc[k]);
+    }
 
     bool ok = dev_upload(c, &c->m64.vr, vr) && dev_upload(c, &c->m64.vt, vt) &&
               dev_upload(c, &c->m64.vp, vp) && dev_upload(c, &c->m64.gr, gr) &&
@@ -532,6 +551,9 @@ pa_status pa_init(const pa_desc* d, void* stream, pa_ctx** out)
               dev_upload(c, &c->m32.vp, vp) && dev_upload(c, &c->m32.gr, gr) &&
               dev_upload(c, &c->m32.gtr, gtr) && dev_upload(c, &c->m32.gtt, gtt) &&
               dev_upload(c, &c->m32.gpt, gpt) && dev_upload(c, &c->m32.gpp, gpp) &&
+              dev_upload(c, &c->m64.rtf, rtf) && dev_upload(c, &c->m64.rtc, rtc) &&
+              dev_upload(c, &c->m64.rpf, rpf) && dev_upload(c, &c->m32.rtf, rtf) &&
+              dev_upload(c, &c->m32.rtc, rtc) && dev_upload(c, &c->m32.rpf, rpf) &&
               dev_upload(c, &c->c_hr, hr) && dev_upload(c, &c->c_wr, wr) &&
               dev_upload(c, &c->c_R, Rf) && dev_upload(c, &c->c_htt, htt) &&
               dev_upload(c, &c->c_sT, sT) && dev_upload(c, &c->c_dpc, dpc);

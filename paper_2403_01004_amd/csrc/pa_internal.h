@@ -8,6 +8,7 @@
 namespace pa {
 
 constexpr int kBlock = 256;   // threads per workgroup (4 waves of 64)
+constexpr int kOpIso7 = 0, kOpAligned = 1, kOpViscVec = 2;  // pa_op
 constexpr int kRedBlock = 1024;
 
 // Separable 1-D metric factors of the finite-volume mesh (device arrays).
@@ -15,6 +16,10 @@ constexpr int kRedBlock = 1024;
 //  G_r(face ir, j, k) = gr[ir] * vt[j] * vp[k]        ir in [0, nr]
 //  G_t(i, face jt, k) = gtr[i] * gtt[jt] * vp[k]      jt in [0, nt], 0 at the poles
 //  G_p(i, j, face kf) = gtr[i] * gpt[j] * gpp[kf]     kf in [0, np), face between kf-1, kf
+// Change of basis between neighbouring cell centres (vector viscosity):
+//  rtf[jt], rtf[nt+1+jt] = cos, sin of tc[jt] - tc[jt-1]  (theta face jt; 1, 0 at the poles)
+//  rtc[j],  rtc[nt+j]    = sin, cos of the colatitude tc[j]
+//  rpf[kf], rpf[np+kf]   = 1 - cos, sin of pc[kf] - pc[kf-1]  (phi face kf, periodic)
 template <class T>
 struct Geo {
     int nr, nt, np, P;  // P = nt*np cells per radial level
@@ -26,6 +31,9 @@ struct Geo {
     const T* gtt;
     const T* gpt;
     const T* gpp;
+    const T* rtf;
+    const T* rtc;
+    const T* rpf;
 };
 
 enum Mode : int {
@@ -62,6 +70,7 @@ struct KArgs {
     int* flag;        // non-finite flag (kFirst)
     const int* done;  // skip the launch when *done != 0 (PCG), may be null
     const T* wgt;     // cell weight w of F = (1/w) div(...), [nr][nt][np], null for 1
+    int only_c;       // vector viscosity: store only component only_c (-1: all)
 };
 
 // stencil launchers (pa_kernels.hip)
@@ -69,6 +78,8 @@ template <class T>
 void launch_iso7(int mode, bool virt, const Geo<T>& g, const KArgs<T>& a, hipStream_t s);
 template <class T>
 void launch_aligned(int mode, bool virt, const Geo<T>& g, const KArgs<T>& a, hipStream_t s);
+template <class T>
+void launch_viscv(int mode, bool virt, const Geo<T>& g, const KArgs<T>& a, hipStream_t s);
 
 // workgroups covering one radial level (op: 0 7-point, 1 field-aligned),
 // and logical workgroups of a stencil launch over nlev levels (== entries

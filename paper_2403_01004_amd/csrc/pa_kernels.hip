@@ -53,13 +53,14 @@ int iso7_blocks_per_plane(int nt, int np, bool fp32);
 
 int blocks_per_plane(int op, int nt, int np, bool fp32)
 {
-    return op == 0 ? iso7_blocks_per_plane(nt, np, fp32) : tiles_per_plane(nt, np);
+    return op == kOpIso7 ? iso7_blocks_per_plane(nt, np, fp32) : tiles_per_plane(nt, np);
 }
 
+// the vector viscosity kernel treats the three components in one workgroup
 int stencil_tiles(int op, int nt, int np, int nlev, int rch, int nc, bool fp32)
 {
     const int nrc = (nlev + rch - 1) / rch;
-    return blocks_per_plane(op, nt, np, fp32) * nrc * nc;
+    return blocks_per_plane(op, nt, np, fp32) * nrc * (op == kOpViscVec ? 1 : nc);
 }
 
 // ------------------------------------------------------------ reductions
@@ -136,10 +137,9 @@ __device__ __forceinline__ int slot_offset(int hy, int hx, int j0, int k0, int n
     return j * np + wrapk(k0 - 1 + hx, np);
 }
 
-__device__ __forceinline__ TileMap tile_map(int bxk, int bxj, int nt, int np)
+__device__ __forceinline__ TileMap tile_map(int bxk, int bxj, int nt, int np, int t)
 {
     TileMap m;
-    const int t = threadIdx.x;
     m.k0 = bxk * TX;
     m.j0 = bxj * TY;
     m.tx = t % TX;
@@ -216,11 +216,11 @@ __device__ __forceinline__ void epilogue(const KArgs<T>& a, size_t m, T Lu, T V,
     }
 }
 
-template <class T, int MODE>
+template <class T, int MODE, int NTHREADS = kBlock>
 __device__ void finish(const KArgs<T>& a, int L, Acc<T, MODE>& acc)
 {
-    __shared__ double ldsv[kBlock / 64];
-    __shared__ long long ldsi[kBlock / 64];
+    __shared__ double ldsv[NTHREADS / 64];
+    __shared__ long long ldsi[NTHREADS / 64];
     if constexpr (MODE == kFirst) {
         double v = acc.best;
         long long i = acc.bidx;
@@ -542,7 +542,7 @@ __global__ __launch_bounds__(kBlock) void k_iso7t(Geo<T> g, KArgs<T> a)
     const size_t P = (size_t)g.P;
     const int ntk = (np + TX - 1) / TX;
     const int bx = L % a.nbx, rest = L / a.nbx, rc = rest % a.nrc, c = rest / a.nrc;
-    const TileMap tm = tile_map(bx % ntk, bx / ntk, nt, np);
+    const TileMap tm = tile_map(bx % ntk, bx / ntk, nt, np, threadIdx.x);
     Pt7<T> t;
     t.valid = tm.valid;
     const int j = min(tm.j, nt - 1), k = tm.valid ? tm.k : 0;
@@ -795,7 +795,7 @@ __global__ __launch_bounds__(kBlock) void k_aligned(Geo<T> g, KArgs<T> a)
     const int np = g.np, nt = g.nt, nr = g.nr, P = g.P;
     const int ntk = (np + TX - 1) / TX;
     const int bx = L % a.nbx, rest = L / a.nbx, rc = rest % a.nrc, c = rest / a.nrc;
-    const TileMap tm = tile_map(bx % ntk, bx / ntk, nt, np);
+    const TileMap tm = tile_map(bx % ntk, bx / ntk, nt, np, threadIdx.x);
     const size_t cb = (size_t)c * nr * P;
     const T* u = a.u + cb;
     const T* y = VIRT ? a.y0 + cb : nullptr;
@@ -857,6 +857,211 @@ __global__ __launch_bounds__(kBlock) void k_aligned(Geo<T> g, KArgs<T> a)
     finish<T, MODE>(a, L, acc);
 }
 
+
+// ------------------------------------------------------------ vector viscosity
+//
+// Eq. (visc) for a velocity in spherical components (v_r, v_theta, v_phi):
+// the 7-point operator on the Cartesian components, written in each cell's
+// own spherical basis.  A colatitude or longitude face couples component a
+// of the cell to w_a = sum_b T_ab v_b(nb), T_ab = e_a(cell) . e_b(nb) (the
+// neighbour's vector in the cell's basis); radial faces and the radial
+// boundary data share the cell's basis.  Colatitude neighbours differ by a
+// rotation about phi-hat by the angle D between the centres,
+//   rows (cos D, -sin D, 0), (sin D, cos D, 0), (0, 0, 1);
+// longitude neighbours by a rotation about the polar axis by d, with
+// s, c = sin, cos of the colatitude and q = 1 - cos d,
+//   rows (1 - s^2 q, -s c q, -s sin d), (-s c q, 1 - c^2 q, -c sin d),
+//        (s sin d, c sin d, 1 - q).
+// Workgroups of 3 x 256 threads own a 32 x 8 tile for all three components
+// (threads 256 a .. 256 a + 255 own component a, so the component is
+// uniform per wave); each level's three tile planes with their halo rings
+// are staged in LDS, where a thread reads its neighbours' three components.
+// A thread's loads are those of the scalar 7-point tile march above.
+
+constexpr int kVBlock = 3 * kBlock;
+
+template <class T>
+struct ShV {
+    T su[2][3][HN];
+    T sc[2][HN];
+    T gr[RCH_MAX + 3], gtr[RCH_MAX + 3], vr[RCH_MAX + 3];
+};
+
+// row a of the change of basis for the faces theta-, theta+, phi-, phi+
+template <class T>
+struct RowsV {
+    T q[4][3];
+};
+
+template <class T>
+__device__ __forceinline__ RowsV<T> rows_viscv(const Geo<T>& g, int a, int j, int k, int kp)
+{
+    RowsV<T> R;
+    const int nt = g.nt, np = g.np;
+    // colatitude faces j (neighbour j-1, angle -D_j) and j+1 (angle D_{j+1})
+    const T ct[2] = {g.rtf[j], g.rtf[j + 1]};
+    const T st[2] = {-g.rtf[nt + 1 + j], g.rtf[nt + 1 + j + 1]};
+    for (int f = 0; f < 2; ++f) {
+        R.q[f][0] = a == 0 ? ct[f] : a == 1 ? st[f] : T(0);
+        R.q[f][1] = a == 0 ? -st[f] : a == 1 ? ct[f] : T(0);
+        R.q[f][2] = a == 2 ? T(1) : T(0);
+    }
+    // longitude faces k (neighbour k-1, angle -d_k) and kp (angle d_kp)
+    const T s = g.rtc[j], c = g.rtc[nt + j];
+    const T qd[2] = {g.rpf[k], g.rpf[kp]};
+    const T sd[2] = {-g.rpf[np + k], g.rpf[np + kp]};
+    for (int f = 0; f < 2; ++f) {
+        const T q = qd[f], d = sd[f];
+        R.q[2 + f][0] = a == 0 ? T(1) - s * s * q : a == 1 ? -s * c * q : s * d;
+        R.q[2 + f][1] = a == 0 ? -s * c * q : a == 1 ? T(1) - c * c * q : c * d;
+        R.q[2 + f][2] = a == 0 ? -s * d : a == 1 ? -c * d : T(1) - q;
+    }
+    return R;
+}
+
+template <class T, int MODE, bool VIRT, bool CV, bool WT, int DEPTH>
+__device__ __forceinline__ void stepV(const Geo<T>& g, const KArgs<T>& a, const T* u, const T* y,
+                                      size_t cb, int comp, const TileMap& tm, const Pt7<T>& t,
+                                      const RowsV<T>& Q, ShV<T>& sh, int i, int i0, int i1,
+                                      const LevT<T, CV, MODE, WT>& Rc,
+                                      const LevT<T, CV, MODE, WT>& Rn,
+                                      LevT<T, CV, MODE, WT>& Rp, T& um, T& cm, Acc<T, MODE>& acc)
+{
+    const int nr = g.nr;
+    const size_t P = (size_t)g.P;
+    const int b = i & 1;
+    sh.su[b][comp][tm.own_slot] = Rc.x;
+    if (tm.has_h) sh.su[b][comp][tm.h_slot] = Rc.h;
+    if constexpr (CV) {
+        if (comp == 0) {
+            sh.sc[b][tm.own_slot] = Rc.cx;
+            if (tm.has_h) sh.sc[b][tm.h_slot] = Rc.ch;
+        }
+    }
+    {
+        const int lv = min(i + DEPTH, nr - 1), ls = min(i + DEPTH, i1 - 1);
+        fetchT<T, CV, MODE, VIRT, WT>(a, u, y, tm, (size_t)lv * P, cb + (size_t)ls * P + tm.own_off,
+                                      Rp);
+    }
+    __syncthreads();
+    const int o = tm.own_slot;
+    const T* s0 = sh.su[b][0];
+    const T* s1 = sh.su[b][1];
+    const T* s2 = sh.su[b][2];
+    // the in-plane neighbours' vectors in this cell's basis, component comp
+    const T us = Q.q[0][0] * s0[o - HX] + Q.q[0][1] * s1[o - HX] + Q.q[0][2] * s2[o - HX];
+    const T un = Q.q[1][0] * s0[o + HX] + Q.q[1][1] * s1[o + HX] + Q.q[1][2] * s2[o + HX];
+    const T uw = Q.q[2][0] * s0[o - 1] + Q.q[2][1] * s1[o - 1] + Q.q[2][2] * s2[o - 1];
+    const T ue = Q.q[3][0] * s0[o + 1] + Q.q[3][1] * s1[o + 1] + Q.q[3][2] * s2[o + 1];
+    const T uc = Rc.x;
+    const T cc = CV ? Rc.cx : a.cs;
+    T cw = a.cs, ce = a.cs, cs_ = a.cs, cn = a.cs;
+    if constexpr (CV) {
+        const T* sc = sh.sc[b];
+        cw = sc[o - 1];
+        ce = sc[o + 1];
+        cs_ = sc[o - HX];
+        cn = sc[o + HX];
+    }
+    const T cu = CV ? Rn.cx : a.cs;
+    const int ic = min(i, nr - 1);
+    const T half = T(0.5);
+    const int il = ic - i0;
+    const T gtri = sh.gtr[il];
+    const bool lo = ic > 0, hi = ic < nr - 1;
+    const T Cl = lo ? half * (cc + cm) * (sh.gr[il] * t.Ar) : t.fin * cc * (sh.gr[il] * t.Ar);
+    const T ul = lo ? um : t.ubl;
+    const T Cu = hi ? half * (cc + cu) * (sh.gr[il + 1] * t.Ar) : t.fout * cc * (sh.gr[il + 1] * t.Ar);
+    const T uu = hi ? Rn.x : t.ubu;
+    T Lu = Cl * (uc - ul);
+    Lu += Cu * (uc - uu);
+    Lu += half * (cc + cs_) * (gtri * t.As) * (uc - us);
+    Lu += half * (cc + cn) * (gtri * t.An) * (uc - un);
+    Lu += half * (cc + cw) * (gtri * t.Aw) * (uc - uw);
+    Lu += half * (cc + ce) * (gtri * t.Ae) * (uc - ue);
+    const T V = WT ? sh.vr[il] * t.Ar * Rc.wt : sh.vr[il] * t.Ar;  // (w) V
+    if (t.valid && i < i1 && (a.only_c < 0 || a.only_c == comp))
+        epilogue<T, MODE>(a, cb + (size_t)ic * P + tm.own_off, Lu, V, uc, Rc.st, acc);
+    um = uc;
+    cm = cc;
+    // the next level overwrites the other LDS buffer; this one is reused two
+    // levels on, after the next level's barrier
+}
+
+template <class T, int MODE, bool VIRT, bool CV, bool WT>
+__global__ __launch_bounds__(kVBlock) void k_viscv(Geo<T> g, KArgs<T> a)
+{
+    __shared__ ShV<T> sh;
+    const int L = xcd_tile();
+    if (L >= a.nbx * a.nrc) return;
+    if (a.done && *a.done) return;
+    const int nt = g.nt, np = g.np, nr = g.nr;
+    const size_t P = (size_t)g.P;
+    const int ntk = (np + TX - 1) / TX;
+    const int bx = L % a.nbx, rc = L / a.nbx;
+    const int comp = threadIdx.x / kBlock;  // uniform per wave
+    const TileMap tm = tile_map(bx % ntk, bx / ntk, nt, np, threadIdx.x % kBlock);
+    Pt7<T> t;
+    t.valid = tm.valid;
+    const int j = min(tm.j, nt - 1), k = tm.valid ? tm.k : 0;
+    const int kp = (k == np - 1) ? 0 : k + 1;
+    t.Ar = g.vt[j] * g.vp[k];
+    t.As = g.gtt[j] * g.vp[k];
+    t.An = g.gtt[j + 1] * g.vp[k];
+    t.Aw = g.gpt[j] * g.gpp[k];
+    t.Ae = g.gpt[j] * g.gpp[kp];
+    const RowsV<T> Q = rows_viscv<T>(g, comp, j, k, kp);
+    const size_t cb = (size_t)comp * nr * P;
+    const T* u = a.u + cb;
+    const T* y = VIRT ? a.y0 + cb : nullptr;
+    const int i0 = a.r_lo + rc * a.rch;
+    const int i1 = min(a.r_hi, i0 + a.rch);
+    const size_t ob = (size_t)comp * P + tm.own_off;
+    t.ubl = (a.affine && i0 == 0) ? a.ub_in[ob] : T(0);
+    t.ubu = (a.affine && i1 == nr) ? a.ub_out[ob] : T(0);
+    t.fin = (a.bc_in == 0) ? T(1) : T(0);
+    t.fout = (a.bc_out == 0) ? T(1) : T(0);
+    for (int q = threadIdx.x; q < RCH_MAX + 3; q += blockDim.x) {
+        const int lv = min(i0 + q, nr - 1);
+        sh.gr[q] = g.gr[min(i0 + q, nr)];
+        sh.gtr[q] = g.gtr[lv];
+        sh.vr[q] = g.vr[lv];
+    }
+    Acc<T, MODE> acc;
+    if (i0 < i1) {
+        LevT<T, CV, MODE, WT> R0, R1, R2, R3;
+        T um = 0, cm = a.cs;
+        if (i0 > 0) {
+            um = ldu<T, VIRT>(a, u, y, (size_t)(i0 - 1) * P + tm.own_off);
+            if constexpr (CV) cm = a.coef[(size_t)(i0 - 1) * P + tm.own_off];
+        }
+        fetchT<T, CV, MODE, VIRT, WT>(a, u, y, tm, (size_t)i0 * P, cb + (size_t)i0 * P + tm.own_off,
+                                      R0);
+        {
+            const int lv = min(i0 + 1, nr - 1), ls = min(i0 + 1, i1 - 1);
+            fetchT<T, CV, MODE, VIRT, WT>(a, u, y, tm, (size_t)lv * P,
+                                          cb + (size_t)ls * P + tm.own_off, R1);
+        }
+        {
+            const int lv = min(i0 + 2, nr - 1), ls = min(i0 + 2, i1 - 1);
+            fetchT<T, CV, MODE, VIRT, WT>(a, u, y, tm, (size_t)lv * P,
+                                          cb + (size_t)ls * P + tm.own_off, R2);
+        }
+        // loads three levels ahead, four levels per trip with the ring's roles rotating
+        for (int i = i0; i < i1; i += 4) {
+            stepV<T, MODE, VIRT, CV, WT, 3>(g, a, u, y, cb, comp, tm, t, Q, sh, i, i0, i1, R0, R1,
+                                            R3, um, cm, acc);
+            stepV<T, MODE, VIRT, CV, WT, 3>(g, a, u, y, cb, comp, tm, t, Q, sh, i + 1, i0, i1, R1,
+                                            R2, R0, um, cm, acc);
+            stepV<T, MODE, VIRT, CV, WT, 3>(g, a, u, y, cb, comp, tm, t, Q, sh, i + 2, i0, i1, R2,
+                                            R3, R1, um, cm, acc);
+            stepV<T, MODE, VIRT, CV, WT, 3>(g, a, u, y, cb, comp, tm, t, Q, sh, i + 3, i0, i1, R3,
+                                            R0, R2, um, cm, acc);
+        }
+    }
+    finish<T, MODE, kVBlock>(a, L, acc);
+}
+
 // ------------------------------------------------------------ launchers
 
 template <class T, int MODE, bool VIRT>
@@ -896,6 +1101,21 @@ static void go_aligned(const Geo<T>& g, const KArgs<T>& a, hipStream_t s)
                            0, s, g, a);
 }
 
+template <class T, int MODE, bool VIRT>
+static void go_viscv(const Geo<T>& g, const KArgs<T>& a, hipStream_t s)
+{
+    const int nt = a.nbx * a.nrc;
+    if (a.rch > RCH_MAX) return;  // the host never asks for longer chunks
+    const dim3 gr(grid_for_tiles(nt)), bl(kVBlock);
+    if (a.coef) {
+        if (a.wgt) hipLaunchKernelGGL((k_viscv<T, MODE, VIRT, true, true>), gr, bl, 0, s, g, a);
+        else hipLaunchKernelGGL((k_viscv<T, MODE, VIRT, true, false>), gr, bl, 0, s, g, a);
+    } else {
+        if (a.wgt) hipLaunchKernelGGL((k_viscv<T, MODE, VIRT, false, true>), gr, bl, 0, s, g, a);
+        else hipLaunchKernelGGL((k_viscv<T, MODE, VIRT, false, false>), gr, bl, 0, s, g, a);
+    }
+}
+
 #define PA_DISPATCH(FN)                                                 \
     switch (mode) {                                                     \
     case kApply:                                                        \
@@ -919,6 +1139,13 @@ void launch_aligned(int mode, bool virt, const Geo<T>& g, const KArgs<T>& a, hip
 {
     PA_DISPATCH(go_aligned)
 }
+template <class T>
+void launch_viscv(int mode, bool virt, const Geo<T>& g, const KArgs<T>& a, hipStream_t s)
+{
+    PA_DISPATCH(go_viscv)
+}
+template void launch_viscv<double>(int, bool, const Geo<double>&, const KArgs<double>&, hipStream_t);
+template void launch_viscv<float>(int, bool, const Geo<float>&, const KArgs<float>&, hipStream_t);
 template void launch_iso7<double>(int, bool, const Geo<double>&, const KArgs<double>&, hipStream_t);
 template void launch_iso7<float>(int, bool, const Geo<float>&, const KArgs<float>&, hipStream_t);
 template void launch_aligned<double>(int, bool, const Geo<double>&, const KArgs<double>&, hipStream_t);

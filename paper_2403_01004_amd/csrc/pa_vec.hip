@@ -105,15 +105,9 @@ __device__ __forceinline__ bool better(double v, long long i, double bv, long lo
     return v > bv || (v == bv && i < bi);
 }
 
-// Eq. (ptl3): argmax |F| over the per-tile partials, then the minimum over
-// the six face neighbours of -(u_k - u_nb)/(F_k - F_nb) where du, dF != 0 and
-// du*dF < 0 (Eq. ptl2); +inf if none.  Neighbours: phi periodic, none across
-// a pole or a radial boundary.
-template <class T>
-__global__ __launch_bounds__(kRedBlock) void k_ptl_finalize(const double* pval,
-                                                            const long long* pidx, int n,
-                                                            const T* u, const T* F, int nc,
-                                                            int nr, int nt, int np, DevState* st)
+// argmax |F| over the per-tile partials (largest value, lowest index on
+// ties), one workgroup of kRedBlock threads; the result is valid in thread 0
+__device__ long long argmax_partials(const double* pval, const long long* pidx, int n)
 {
     __shared__ double lv[kRedBlock / 64];
     __shared__ long long li[kRedBlock / 64];
@@ -129,9 +123,24 @@ __global__ __launch_bounds__(kRedBlock) void k_ptl_finalize(const double* pval,
     }
     if ((threadIdx.x & 63) == 0) { lv[threadIdx.x >> 6] = v; li[threadIdx.x >> 6] = ix; }
     __syncthreads();
+    if (threadIdx.x == 0)
+        for (int w = 1; w < kRedBlock / 64; ++w)
+            if (better(lv[w], li[w], v, ix)) { v = lv[w]; ix = li[w]; }
+    return ix;
+}
+
+// Eq. (ptl3): argmax |F| over the per-tile partials, then the minimum over
+// the six face neighbours of -(u_k - u_nb)/(F_k - F_nb) where du, dF != 0 and
+// du*dF < 0 (Eq. ptl2); +inf if none.  Neighbours: phi periodic, none across
+// a pole or a radial boundary.  F is read at the cell and its neighbours only.
+template <class T>
+__global__ __launch_bounds__(kRedBlock) void k_ptl_finalize(const double* pval,
+                                                            const long long* pidx, int n,
+                                                            const T* u, const T* F, int nc,
+                                                            int nr, int nt, int np, DevState* st)
+{
+    const long long ix = argmax_partials(pval, pidx, n);
     if (threadIdx.x != 0) return;
-    for (int w = 1; w < kRedBlock / 64; ++w)
-        if (better(lv[w], li[w], v, ix)) { v = lv[w]; ix = li[w]; }
     const long long N = (long long)nc * nr * nt * np;
     if (ix < 0 || ix >= N) {  // every |F| was NaN
         st->kmax = -1;

@@ -107,6 +107,23 @@ class SmoothField:
         return out
 
 
+def _raw_device(sf, r, t, p, torch, device):
+    """SmoothField.raw evaluated with torch on `device` (FP64): the same
+    waves, for grids too large to build in numpy in reasonable time."""
+    f64 = torch.float64
+    r = torch.as_tensor(np.asarray(r, float), dtype=f64, device=device)[:, None, None]
+    t = torch.as_tensor(np.asarray(t, float), dtype=f64, device=device)
+    p = torch.as_tensor(np.asarray(p, float), dtype=f64, device=device)
+    st, ct = torch.sin(t)[None, :, None], torch.cos(t)[None, :, None]
+    sp, cp = torch.sin(p)[None, None, :], torch.cos(p)[None, None, :]
+    x, y, z = r * st * cp, r * st * sp, r * ct * torch.ones_like(cp)
+    out = torch.zeros((r.shape[0], st.shape[1], sp.shape[2]), dtype=f64, device=device)
+    for n in range(sf.NWAVES):
+        out += float(sf.a[n]) * torch.cos(float(sf.k[n, 0]) * x + float(sf.k[n, 1]) * y
+                                          + float(sf.k[n, 2]) * z + float(sf.psi[n]))
+    return out
+
+
 def _smooth_on(seed, mesh, extra_r=()):
     """Field at cell centres and at the listed extra radii (for boundary
     data), normalised together so max |S| over the cells is 1; also returns
@@ -220,6 +237,29 @@ def viscosity(nr=151, nt=301, np_=400, seed=202, noise_amp=0.01, nu=1e-3, stretc
         uo.append(0.1 * s_out)
     return Problem(mesh, "viscv" if vector else "iso7", 3, np.stack(u), np.stack(ui),
                    np.stack(uo), None, nu, 0.0, None,
+                   name=f"viscosity{'_vec' if vector else ''}_{nr}x{nt}x{np_}")
+
+
+def viscosity_device(nr, nt, np_, torch, device, seed=202, noise_amp=0.01, nu=1e-3,
+                     stretch=1.02, vector=True):
+    """viscosity() with the smooth fields evaluated by torch on `device`
+    (same waves and noise stream; values equal to rounding).  u, ub_in and
+    ub_out are device tensors.  For the largest grids."""
+    mesh = shell_mesh(nr, nt, np_, stretch=stretch)
+    rc, tc, pc = cell_centres(mesh)
+    u = torch.empty((3, nr, nt, np_), dtype=torch.float64, device=device)
+    ui = torch.empty((3, nt, np_), dtype=torch.float64, device=device)
+    uo = torch.empty_like(ui)
+    for c in range(3):
+        sf = SmoothField(seed + c)
+        cells = _raw_device(sf, rc, tc, pc, torch, device)
+        scale = 1.0 / float(cells.abs().max())
+        u[c] = 0.1 * scale * cells
+        u[c] += noise_amp * torch.as_tensor(noise(sf.rng, cells.shape), device=device)
+        ui[c] = 0.1 * scale * _raw_device(sf, [mesh.r_faces[0]], tc, pc, torch, device)[0]
+        uo[c] = 0.1 * scale * _raw_device(sf, [mesh.r_faces[-1]], tc, pc, torch, device)[0]
+        del cells
+    return Problem(mesh, "viscv" if vector else "iso7", 3, u, ui, uo, None, nu, 0.0, None,
                    name=f"viscosity{'_vec' if vector else ''}_{nr}x{nt}x{np_}")
 
 

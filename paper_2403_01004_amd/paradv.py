@@ -23,7 +23,7 @@ PA_OK, PA_ERR_ARG, PA_ERR_ALLOC, PA_ERR_HIP, PA_ERR_NOCONV, PA_ERR_BREAKDOWN, \
 STATUS_NAMES = {0: "PA_OK", 1: "PA_ERR_ARG", 2: "PA_ERR_ALLOC", 3: "PA_ERR_HIP",
                 4: "PA_ERR_NOCONV", 5: "PA_ERR_BREAKDOWN", 6: "PA_ERR_NONFINITE",
                 7: "PA_ERR_STATE", 8: "PA_ERR_MAXCYCLES"}
-OPS = {"iso7": 0, "aligned": 1}
+OPS = {"iso7": 0, "aligned": 1, "viscv": 2}
 BCS = {"dirichlet": 0, "noflux": 1}
 PRECS = {"fp64": 0, "fp32": 1}
 
@@ -281,6 +281,38 @@ class PaError(RuntimeError):
         self.status = status
 
 
+def _callbacks(allocator, torch, device, stream, errors):
+    """ctypes allocator callbacks for pa_desc: torch's caching allocator, or
+    a user pair (alloc(nbytes) -> address or 0, free(address)).  A callback
+    never raises into C: a failed allocation returns NULL, and the exception
+    is appended to `errors`."""
+    if allocator == "torch":
+        index = device.index if device.index is not None else torch.cuda.current_device()
+
+        def alloc(n):
+            return torch.cuda.caching_allocator_alloc(n, index, stream)
+
+        def free(p):
+            torch.cuda.caching_allocator_delete(p)
+    else:
+        alloc, free = allocator
+
+    def c_alloc(n, _user):
+        try:
+            return int(alloc(int(n)) or 0) or None
+        except Exception as e:  # noqa: BLE001 -- reported through pa_init's status
+            errors.append(repr(e))
+            return None
+
+    def c_free(p, _user):
+        try:
+            free(int(p))
+        except Exception as e:  # noqa: BLE001
+            errors.append(repr(e))
+
+    return _ALLOC(c_alloc), _FREE(c_free)
+
+
 def _stats_dict(s: pa_stats):
     n = min(s.cycles, PA_MAX_LOG)
     return dict(status=s.status, cycles=s.cycles, s_total=s.s_total, s_max=s.s_max,
@@ -300,7 +332,11 @@ class Operator:
     field is advanced in place."""
 
     def __init__(self, mesh, op="iso7", ncomp=1, bc_in="dirichlet", bc_out="dirichlet",
-                 prec="fp64", device="cuda"):
+                 prec="fp64", device="cuda", allocator=None):
+        """allocator: None (the library calls hipMalloc / hipFree), "torch"
+        (torch's caching allocator on the operator's stream), or a pair of
+        Python callables (alloc(nbytes) -> device address or 0, free(address))
+        passed to pa_init as the descriptor's allocator callbacks."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the parabolic-advance library has no CPU fallback")
@@ -320,9 +356,16 @@ class Operator:
         d.op, d.bc_in, d.bc_out, d.prec = OPS[op], BCS[bc_in], BCS[bc_out], PRECS[prec]
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.current_stream(self.device)
+            self._cb = None
+            self.alloc_errors = []
+            if allocator is not None:
+                self._cb = _callbacks(allocator, torch, self.device, self.stream,
+                                      self.alloc_errors)
+                d.alloc, d.free = self._cb
             st, ctx = pa_init(d, ctypes.c_void_p(self.stream.cuda_stream))
         if st != PA_OK:
-            raise PaError(st, "pa_init failed")
+            raise PaError(st, "pa_init failed" + (f" (allocator: {self.alloc_errors[-1]})"
+                                                  if self.alloc_errors else ""))
         self.ctx = ctx
         self._lib = lib
         self._keep = {}
@@ -398,8 +441,8 @@ class Operator:
         self.torch.cuda.current_stream(self.device).synchronize()
 
     @classmethod
-    def from_problem(cls, prob, prec="fp64", device="cuda"):
-        o = cls(prob.mesh, prob.op, prob.ncomp, prob.bc_in, prob.bc_out, prec, device)
+    def from_problem(cls, prob, prec="fp64", device="cuda", allocator=None):
+        o = cls(prob.mesh, prob.op, prob.ncomp, prob.bc_in, prob.bc_out, prec, device, allocator)
         if prob.w is not None or prob.fc is not None or prob.Tc > 0:
             o.set_profile(prob.w, prob.fc, prob.Tc)
         o.set_coefficients(prob.T0, prob.scale, prob.expo, prob.B)

@@ -108,9 +108,12 @@ def test_bilu0_be_advance(dev, oracle_mod, kind, shape, bc):
     # rounding of the threshold in a cycle (the GPU multiplies by inverse
     # pivots where the oracle divides, and sums in another order): that cycle
     # then takes one iteration more or less, the next limits differ and the
-    # schedules part.  Then the oracle replays the GPU's schedule; the two
-    # iterates of the odd cycle both meet the tolerance, so they differ by
-    # at most about 2 cond(M) tol (cond(M) < 1e3 here).
+    # schedules part.  Then the oracle follows the GPU's decisions cycle by
+    # cycle (its cycle lengths and iteration counts); each cycle where the
+    # oracle would have stopped elsewhere must be a genuine near-tie: at the
+    # earlier of the two counts the oracle's relative residual lies within
+    # 1e-12 of tol (both sides' residuals agree to rounding, ~1e-15 of
+    # ||b||), and the fields then agree to the rounding drift.
     u = g.bind(prob.u)
     st = g.advance_be(50.0 * dtE, 1e-10, 0)
     uo, so = o.advance_be(prob.u, 50.0 * dtE, 1e-10, 0)
@@ -120,10 +123,22 @@ def test_bilu0_be_advance(dev, oracle_mod, kind, shape, bc):
             and list(st["per_cycle"]) == list(so["per_cycle"])):
         assert rel_l2(u.cpu().numpy(), uo) <= 1e-9
     else:
-        uo, so = o.advance_be(prob.u, 50.0 * dtE, 1e-10, 0, replay=dg)
-        dif = np.abs(np.asarray(st["per_cycle"]) - np.asarray(so["per_cycle"]))
-        assert dif.max() <= 1 and np.count_nonzero(dif) <= 2, (st["per_cycle"], so["per_cycle"])
-        assert rel_l2(u.cpu().numpy(), uo) <= 1e-7
+        x, flips = prob.u, 0
+        for dtc, ng in zip(dg, st["per_cycle"]):
+            xf, sf = o.advance_be(x, dtc, 1e-10, 1)
+            if sf["iters_total"] == int(ng):
+                x = xf
+                continue
+            flips += 1
+            xg, sg = o.advance_be(x, dtc, 1e-10, 1, force_iters=int(ng))
+            # residual at the earlier stopping count
+            r_early = sg["rel_residual"] if int(ng) < sf["iters_total"] else sf["rel_residual"]
+            _log("  near tie: gpu", int(ng), "oracle", sf["iters_total"], "residual", r_early)
+            assert abs(sf["iters_total"] - int(ng)) == 1
+            assert abs(r_early - 1e-10) <= 1e-12, r_early
+            x = xg
+        assert flips <= 2
+        assert rel_l2(u.cpu().numpy(), x) <= 1e-9
 
 
 @pytest.mark.parametrize("kind", ["heat", "viscosity"])

@@ -28,7 +28,7 @@ def dev():
 
 
 CASES = [("aligned", (17, 24, 40)), ("iso7", (17, 24, 40)), ("visc", (9, 10, 13)),
-         ("aligned", (6, 12, 400))]
+         ("aligned", (6, 12, 400)), ("viscv", (17, 24, 40)), ("viscv", (6, 12, 400))]
 
 
 def make(kind, shape):
@@ -36,6 +36,8 @@ def make(kind, shape):
         return inputs.conduction(*shape, noise_amp=0.02)
     if kind == "visc":
         return inputs.viscosity(*shape)
+    if kind == "viscv":
+        return inputs.viscosity(*shape, vector=True)
     return inputs.heat_iso(*shape)
 
 

@@ -39,6 +39,8 @@ def problem(op, shape, bc="dirichlet", seed=0, ncomp=None):
     nr, nt, np_ = shape
     if op == "aligned":
         p = inputs.conduction(nr, nt, np_, seed=seed + 201, noise_amp=0.02)
+    elif op == "viscv":
+        p = inputs.viscosity(nr, nt, np_, seed=seed + 204, vector=True)
     elif ncomp == 3:
         p = inputs.viscosity(nr, nt, np_, seed=seed + 202)
     else:
@@ -54,7 +56,7 @@ def pair(dev, oracle_mod, prob, prec="fp64"):
 
 
 SHAPES = [(9, 10, 13), (17, 24, 40), (1, 2, 3), (6, 12, 400)]
-CASES = [("iso7", None), ("aligned", None), ("iso7", 3)]
+CASES = [("iso7", None), ("aligned", None), ("iso7", 3), ("viscv", 3)]
 
 
 def _log(*a):
