@@ -231,6 +231,21 @@ pa_status pa_compute_ptl(pa_ctx* ctx, double* dt_ptl, int64_t* k_lin);
  * assumption; the advances use pa_compute_ptl's form. */
 pa_status pa_compute_ptl_full(pa_ctx* ctx, double* dt_full, int64_t* k_lin);
 
+/* pa_compute_ptl for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same limit and index, bit for bit, with no allocation in the call.
+ * Its scratch -- the per-tile argmax partials and F on the three radial
+ * levels around the cell of largest |F| -- is a 16 MiB array of device
+ * memory that the library holds on every device it runs on until the
+ * process ends.  FP64 contexts only (PA_ERR_ARG otherwise).  PA_ERR_ARG when
+ * the problem needs more scratch than that: about 24 bytes per cell of one
+ * radial level plus 16 bytes per stencil workgroup (256 x 512 x 1024 with
+ * three components needs 12.8 MiB).  PA_ERR_HIP if the array's device
+ * address could not be resolved at pa_init.  Every call on one device uses
+ * the same array, which keeps the last call's contents: calls that overlap
+ * in time on one device (other streams, other host threads) race. */
+pa_status pa_compute_ptl_noalloc(pa_ctx* ctx, double* dt_ptl, int64_t* k_lin);
+
 /* Block ILU(0) preconditioner, PC2 of Sec. 3.1 (non-overlapping ILU(0)):
  * z = P^{-1} r for device arrays of the field's shape (all components), P the
  * incomplete LU factorisation, with the sparsity of M and cells in natural

@@ -10,6 +10,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -18,6 +19,40 @@
 
 using namespace pa;
 
+// Scratch of pa_compute_ptl_noalloc: one copy per device, held from module
+// load to process exit, shared by every call on that device.  In host code
+// `scratch` names a host-side stand-in: the device copy's address comes from
+// hipGetSymbolAddress (pa_init, once per device) and only that address is
+// ever passed to kernels.
+constexpr size_t kScratchBytes = size_t(16) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+bool g_scratch_done[kMaxDevices] = {};
+void* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev, which must be current; the
+// lookup runs once per device.  Null (with *err set) if it failed.
+void* scratch_address(int dev, hipError_t* err)
+{
+    if (dev < 0 || dev >= kMaxDevices) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_done[dev]) {
+        void* ptr = nullptr;
+        g_scratch_err[dev] = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        g_scratch_ptr[dev] = g_scratch_err[dev] == hipSuccess ? ptr : nullptr;
+        g_scratch_done[dev] = true;
+    }
+    *err = g_scratch_err[dev];
+    return g_scratch_ptr[dev];
+}
+}  // namespace
 
 namespace {
 
@@ -108,6 +143,8 @@ struct pa_ctx {
     float* nn_wpart = nullptr;                   // weight-gradient partials
     double* bilu0_ip = nullptr;  // [N] inverse block ILU(0) pivots of the current solve
     int pcg_hint = 0;            // iterations of the last PCG solve (first batch of the next)
+    void* scratch = nullptr;     // this device's `scratch` (pa_compute_ptl_noalloc)
+    hipError_t scratch_err = hipSuccess;
 };
 
 namespace {
@@ -486,6 +523,7 @@ pa_status pa_init(const pa_desc* d, void* stream, pa_ctx** out)
     c->stream = (hipStream_t)stream;
     pa_default_options(&c->opt);
     (void)hipGetDevice(&c->dev);
+    c->scratch = scratch_address(c->dev, &c->scratch_err);
     c->P = (size_t)nt * np;
     c->N = c->P * nr;
     c->NT = c->N * d->ncomp;
@@ -817,6 +855,104 @@ pa_status pa_compute_ptl_full(pa_ctx* c, double* dt, int64_t* k)
     if (*c->hflag) return fail(c, PA_ERR_NONFINITE, "non-finite F");
     *dt = c->hst->dt_full;
     if (k) *k = c->hst->kfull;
+    return PA_OK;
+}
+
+pa_status pa_compute_ptl_noalloc(pa_ctx* c, double* dt, int64_t* k)
+{
+    if (!c) return PA_ERR_ARG;
+    if (!dt) return fail(c, PA_ERR_ARG, "null output");
+    if (!c->have_coef) return fail(c, PA_ERR_STATE, "coefficients not set");
+    if (!c->u) return fail(c, PA_ERR_STATE, "no field bound");
+    if (c->fp32) return fail(c, PA_ERR_ARG, "pa_compute_ptl_noalloc: FP64 contexts only");
+    if (!c->scratch)
+        return fail(c, PA_ERR_HIP, "scratch array of device %d not resolved: %s", c->dev,
+                    hipGetErrorString(c->scratch_err));
+    const int nr = c->d.nr;
+    const size_t P = c->P, N = c->N;
+    const int n = ntiles(c, nr);
+    // scratch layout: device state | flag | argmax partials (value, index) |
+    // F on the three radial levels around the argmax cell (one component)
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t o_flag = up(sizeof(DevState)), o_part = o_flag + 256;
+    const size_t o_idx = o_part + up(sizeof(double) * n);
+    const size_t o_F = o_idx + up(sizeof(long long) * n);
+    const size_t need = o_F + sizeof(double) * 3 * P;
+    if (need > kScratchBytes)
+        return fail(c, PA_ERR_ARG,
+                    "pa_compute_ptl_noalloc: needs %zu bytes of scratch (%d tiles, %zu cells "
+                    "per radial level), the maximum is %zu",
+                    need, n, P, kScratchBytes);
+    unsigned char* sb = (unsigned char*)c->scratch;
+    DevState* st = (DevState*)sb;
+    int* flag = (int*)(sb + o_flag);
+    double* part = (double*)(sb + o_part);
+    long long* pidx = (long long*)(sb + o_idx);
+    double* F3 = (double*)(sb + o_F);
+    // the scratch keeps the previous call's contents: the NaN flag must start at zero
+    launch_fill_zero(flag, sizeof(int), c->stream);
+    {
+        // pass 1: argmax partials of |F| without storing F
+        KArgs<double> a = base_args<double>(c, 0, nr);
+        a.u = c->u;
+        a.out = nullptr;
+        a.part = part;
+        a.part_idx = pidx;
+        a.flag = flag;
+        KScope t(c, PA_K_FIRST);
+        stencil<double>(c, kFirst, false, a);
+    }
+    launch_argmax(part, pidx, n, (long long)c->NT, st, c->stream);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(&c->hst->kmax, &st->kmax, sizeof(long long), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->hflag, flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    flush_timing(c);
+    const long long km = c->hst->kmax;
+    if (*c->hflag || km < 0) return fail(c, PA_ERR_NONFINITE, "non-finite F");
+    // pass 2: F of the argmax cell's component on radial levels [lo, hi);
+    // the same kernel as pass 1 over fewer levels gives bit-identical values
+    const size_t cc = (size_t)km / N;
+    const int ik = (int)(((size_t)km % N) / P);
+    const int lo = std::max(ik - 1, 0), hi = std::min(ik + 2, nr);
+    // F3 holds levels lo..hi-1 of component cc.  The scalar operators treat
+    // component cc as a one-component field, written at out + i P; the
+    // vector viscosity couples the components, so it reads all three and
+    // stores component cc only, at out + m for cell m of the whole field.
+    // The finish reads cell m at F + m.  The bases are shifted back so that
+    // every access lands in F3.
+    const uintptr_t F3a = (uintptr_t)F3;
+    {
+        KArgs<double> a = base_args<double>(c, lo, hi);
+        if (c->d.op == PA_OP_VISC_VECTOR) {
+            a.u = c->u;
+            a.only_c = (int)cc;
+            a.out = (double*)(F3a - sizeof(double) * (cc * N + (size_t)lo * P));
+        } else {
+            a.nc = 1;
+            a.u = c->u + cc * N;
+            a.ub_in = c->ub_in + cc * P;
+            a.ub_out = c->ub_out + cc * P;
+            a.out = (double*)(F3a - sizeof(double) * (size_t)lo * P);
+        }
+        KScope t(c, PA_K_FIRST);
+        stencil<double>(c, kApply, false, a);
+    }
+    {
+        const double* Fw = (const double*)(F3a - sizeof(double) * (cc * N + (size_t)lo * P));
+        KScope t(c, PA_K_REDUCE);
+        launch_ptl_finalize<double>(part, pidx, n, c->u, Fw, c->d.ncomp, nr, c->d.nt, c->d.np,
+                                    st, c->stream);
+    }
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(c->hst, st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    flush_timing(c);
+    *dt = c->hst->dt_ptl;
+    if (k) *k = c->hst->kmax;
+    if (isnan(*dt)) return fail(c, PA_ERR_NONFINITE, "non-finite F");
+    c->err.clear();
     return PA_OK;
 }
 

@@ -125,6 +125,10 @@ void launch_reduce_max(const double* part, int n, double* outp, hipStream_t s);
 template <class T>
 void launch_ptl_full(const T* u, const T* F, int nc, int nr, int nt, int np, double* pval,
                      long long* pidx, DevState* st, hipStream_t s);
+// argmax of |F| over per-tile partials into st->kmax (-1 when every |F| is
+// NaN); N = cells of all components
+void launch_argmax(const double* pval, const long long* pidx, int n, long long N, DevState* st,
+                   hipStream_t s);
 template <class T>
 void launch_ptl_finalize(const double* pval, const long long* pidx, int n, const T* u, const T* F,
                          int nc, int nr, int nt, int np, DevState* st, hipStream_t s);

@@ -193,7 +193,8 @@ __device__ __forceinline__ void epilogue(const KArgs<T>& a, size_t m, T Lu, T V,
 {
     if constexpr (MODE == kApply || MODE == kFirst) {
         const T F = -Lu / V;
-        __builtin_nontemporal_store(F, a.out + m);
+        // kFirst with out == null: the argmax partials only
+        if (MODE == kApply || a.out) __builtin_nontemporal_store(F, a.out + m);
         if constexpr (MODE == kFirst) {
             const double af = fabs((double)F);
             if (af > acc.best) { acc.best = af; acc.bidx = (long long)m; }

@@ -174,6 +174,20 @@ __global__ __launch_bounds__(kRedBlock) void k_ptl_finalize(const double* pval,
     st->dt_ptl = dt;
 }
 
+// the argmax step of Eq. (ptl3) alone: st->kmax (-1 when every |F| is NaN)
+__global__ __launch_bounds__(kRedBlock) void k_argmax(const double* pval, const long long* pidx,
+                                                      int n, long long N, DevState* st)
+{
+    const long long ix = argmax_partials(pval, pidx, n);
+    if (threadIdx.x == 0) st->kmax = (ix < 0 || ix >= N) ? -1 : ix;
+}
+
+void launch_argmax(const double* pval, const long long* pidx, int n, long long N, DevState* st,
+                   hipStream_t s)
+{
+    hipLaunchKernelGGL(k_argmax, dim3(1), dim3(kRedBlock), 0, s, pval, pidx, n, N, st);
+}
+
 template <class T>
 void launch_ptl_finalize(const double* pval, const long long* pidx, int n, const T* u, const T* F,
                          int nc, int nr, int nt, int np, DevState* st, hipStream_t s)

@@ -33,7 +33,7 @@ EXPORTS = ["pa_init", "pa_destroy", "pa_last_error", "pa_default_options", "pa_s
            "pa_diag", "pa_compute_ptl", "pa_compute_ptl_full", "pa_advance_rkl2", "pa_advance_rkg2",
            "pa_advance_be_pcg", "pa_lpc_default_train_opts", "pa_lpc_set_weights",
            "pa_lpc_get_weights", "pa_lpc_features", "pa_lpc_apply", "pa_lpc_loss_grad",
-           "pa_lpc_train", "pa_bilu0_apply"]
+           "pa_lpc_train", "pa_bilu0_apply", "pa_compute_ptl_noalloc"]
 PA_LPC_NPARAM = 10832
 PCS = {"jacobi": 0, "learned": 1, "bilu0": 2}
 PA_BILU0_BOX = (8, 4, 16)   # block ILU(0) boxes in cells along r, theta, phi
@@ -122,6 +122,7 @@ def load(path: str = LIB_PATH):
         "pa_diag": (I32, [V, V]),
         "pa_compute_ptl": (I32, [V, P(D), P(I64)]),
         "pa_compute_ptl_full": (I32, [V, P(D), P(I64)]),
+        "pa_compute_ptl_noalloc": (I32, [V, P(D), P(I64)]),
         "pa_bilu0_apply": (I32, [V, D, V, V]),
         "pa_advance_rkl2": (I32, [V, D, I32, P(pa_stats)]),
         "pa_advance_rkg2": (I32, [V, D, I32, P(pa_stats)]),
@@ -206,6 +207,12 @@ def pa_compute_ptl(ctx):
 def pa_compute_ptl_full(ctx):
     dt, k = ctypes.c_double(), ctypes.c_int64()
     st = load().pa_compute_ptl_full(ctx, ctypes.byref(dt), ctypes.byref(k))
+    return st, dt.value, k.value
+
+
+def pa_compute_ptl_noalloc(ctx):
+    dt, k = ctypes.c_double(), ctypes.c_int64()
+    st = load().pa_compute_ptl_noalloc(ctx, ctypes.byref(dt), ctypes.byref(k))
     return st, dt.value, k.value
 
 
@@ -474,6 +481,13 @@ class Operator:
 
     def ptl(self):
         st, dt, k = pa_compute_ptl(self.ctx)
+        self._check(st)
+        return dt, k
+
+    def ptl_noalloc(self):
+        """pa_compute_ptl without allocating: scratch in the library's
+        static device array (FP64 contexts)."""
+        st, dt, k = pa_compute_ptl_noalloc(self.ctx)
         self._check(st)
         return dt, k
 
