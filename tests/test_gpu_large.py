@@ -184,3 +184,64 @@ def test_large_sequence_fp32_stages(dev, oracle_mod, cond5):
     res = np.linalg.norm(b - Mx) / np.linalg.norm(b)
     _log("  iterations", st["iters_total"], "true residual", res)
     assert res <= 1.001e-10
+
+
+def test_large_first_two_advances(dev, oracle_mod, cond5):
+    """The first two advances of the 256x512x1024 sequence against the
+    oracle, bounded to one RKL2 cycle each (s = 5 at dt = 6 dt_E) so that the
+    oracle finishes in about a minute: conduction with the diffusivity
+    re-lagged from the advanced temperature before the second advance, FP64
+    (1e-12) and FP32 stages (1e-5) after each advance."""
+    torch = pytest.importorskip("torch")
+    prob = cond5
+    o = oracle_mod.Oracle.from_problem(prob)
+    g64 = dev.Operator.from_problem(prob)
+    g32 = dev.Operator.from_problem(prob, prec="fp32")
+    dt = 6.0 * o.dt_explicit()
+    u64, u32 = g64.bind(prob.u), g32.bind(prob.u)
+    uo = prob.u
+    Bd = torch.as_tensor(prob.B, device=u64.device)
+    for adv in range(2):
+        if adv:
+            _log("large first advances: re-lag the diffusivity")
+            # each side from its own advanced temperature
+            o.set_coefficients(uo[0], prob.scale, prob.expo, prob.B)
+            g64.set_coefficients(u64[0].clone(), prob.scale, prob.expo, Bd)
+            g32.set_coefficients(u32[0].clone(), prob.scale, prob.expo, Bd)
+        _log("large first advances: advance", adv + 1)
+        s64 = g64.advance_rkl2(dt, 1)
+        g32.advance_rkl2(dt, 1)
+        uo, so = o.advance_sts(uo, dt, 1, "rkl2")
+        assert s64["s_total"] == so["s_total"] == 5
+        e64 = rel_l2(u64.cpu().numpy(), uo)
+        e32 = rel_l2(u32.cpu().numpy(), uo)
+        _log("  rel L2 fp64", e64, "fp32", e32)
+        assert e64 <= 1e-12 and e32 <= 1e-5
+
+
+def test_large_vector_viscosity_first_two_advances(dev, oracle_mod):
+    """The vector viscosity at 256x512x1024 (fields built on the GPU with the
+    recipe's waves): two one-cycle RKL2 advances (s = 5) against the oracle,
+    FP64 (1e-12) and FP32 stages (1e-5)."""
+    torch = pytest.importorskip("torch")
+    _log("building 256x512x1024 vector viscosity")
+    pd = inputs.viscosity_device(*SHAPE, torch, "cuda")
+    prob = inputs.Problem(pd.mesh, "viscv", 3, pd.u.cpu().numpy(), pd.ub_in.cpu().numpy(),
+                          pd.ub_out.cpu().numpy(), None, pd.scale, 0.0, None, name=pd.name)
+    del pd
+    o = oracle_mod.Oracle.from_problem(prob)
+    g64 = dev.Operator.from_problem(prob)
+    g32 = dev.Operator.from_problem(prob, prec="fp32")
+    dt = 6.0 * o.dt_explicit()
+    u64, u32 = g64.bind(prob.u), g32.bind(prob.u)
+    uo = prob.u
+    for adv in range(2):
+        _log("large vector viscosity: advance", adv + 1)
+        s64 = g64.advance_rkl2(dt, 1)
+        g32.advance_rkl2(dt, 1)
+        uo, so = o.advance_sts(uo, dt, 1, "rkl2")
+        assert s64["s_total"] == so["s_total"] == 5
+        e64 = rel_l2(u64.cpu().numpy(), uo)
+        e32 = max(rel_l2(u32[c].cpu().numpy(), uo[c]) for c in range(3))
+        _log("  rel L2 fp64", e64, "fp32 (worst component)", e32)
+        assert e64 <= 1e-12 and e32 <= 1e-5
