@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 METRIC = "Gpts/s per stage & s per PTL-cycled advance; HBM roofline %; PCG iters vs Jacobi"
 HBM_PEAK_GBS = 8000.0
 COPY_ELEMS = 1 << 27          # 1 GiB of FP64 read and 1 GiB written
-WORKLOAD = "spherical shell 151x301x400 (18.2M cells): field-aligned conduction + 3-component viscosity, PTL-cycled RKL2 and BE+Jacobi-PCG at dt = 50 dt_E"
+WORKLOAD = "spherical shell 151x301x400 (18.2M cells): field-aligned conduction + vector viscosity (3 spherical components), PTL-cycled RKL2 and BE+Jacobi-PCG at dt = 50 dt_E"
 
 
 def log(*a):
@@ -80,50 +80,84 @@ def stage_bytes(op, ncomp, N, NCO, coef_var, per_cycle):
     return tot
 
 
-def run_cpu_baseline(cond, budget_s=30.0):
-    """Oracle (as it stands) on a bounded sample: one RKL2 cycle of the
-    151x301x400 conduction advance (PTL evaluation + 15 stages)."""
-    import oracle
-    oracle.build(force=False)
-    o = oracle.Oracle.from_problem(cond)
-    dtE = o.dt_explicit()
-    t0 = time.perf_counter()
-    out, st = o.advance_sts(cond.u, 50 * dtE, cycles=1, sts="rkl2")
-    t = time.perf_counter() - t0
-    N = cond.mesh.ncells
-    model = "unknown CPU"
+def _host_model():
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
                 if line.startswith("model name"):
-                    model = line.split(":", 1)[1].strip()
-                    break
+                    return line.split(":", 1)[1].strip()
     except OSError:
         pass
-    # one operator application at all threads and at one thread, and the
-    # host's memory bandwidth (STREAM triad), as references for the figure
+    return "unknown CPU"
+
+
+def _slab(prob, nlev):
+    """The first nlev radial levels of a problem (same theta-phi plane, same
+    coefficients; the cut is a Dirichlet face with the field's own values):
+    the one-thread sample."""
+    import dataclasses
+    from paper_2403_01004_amd import inputs as _inp
+    m = prob.mesh
+    mesh = _inp.Mesh(m.r_faces[:nlev + 1].copy(), m.t_faces, m.p_faces)
+    sub = lambda a: None if a is None else a[:nlev].copy()
+    B = None if prob.B is None else prob.B[:, :nlev + 1].copy()
+    return dataclasses.replace(prob, mesh=mesh, u=prob.u[:, :nlev].copy(),
+                               ub_out=prob.u[:, nlev - 1].copy(), T0=sub(prob.T0), B=B,
+                               w=sub(prob.w), fc=sub(prob.fc))
+
+
+def run_cpu_baseline(probs, gpu, slab_levels=8):
+    """The oracle (as it stands) on a bounded sample of each benchmarked
+    advance: its first cycle, at the cycle length the GPU took, on all host
+    threads (full grid) and on one thread (the first slab_levels radial
+    levels).  Per advance: oracle Gpts/s per STS stage or PCG iteration and
+    the seconds one advance would take at that rate, beside the GPU's."""
+    import oracle
+    oracle.build(force=False)
     threads = oracle.num_threads()
-
-    def apply_s():
-        t0 = time.perf_counter()
-        o.apply(cond.u)
-        return time.perf_counter() - t0
-
-    t_all = min(apply_s() for _ in range(2))
-    try:
-        oracle.set_num_threads(1)
-        t_one = apply_s()
-    finally:
-        oracle.set_num_threads(threads)
+    out = {}
+    tot_units = tot_t = 0.0
+    for name, st in gpu.items():
+        kind, opn = name.split("_", 1)
+        prob = probs[opn]
+        dt1 = float(st["dt_cycle"][0])
+        res = {}
+        for label, p, nth in (("all_threads", prob, threads),
+                              ("one_thread", _slab(prob, slab_levels), 1)):
+            oracle.set_num_threads(nth)
+            try:
+                o = oracle.Oracle.from_problem(p)
+                t0 = time.perf_counter()
+                if kind == "rkl2":
+                    _, so = o.advance_sts(p.u, dt1, 1, "rkl2")
+                    units = so["s_total"]
+                else:
+                    _, so = o.advance_be(p.u, dt1, 1e-10, 1)
+                    units = so["iters_total"]
+                t = time.perf_counter() - t0
+            finally:
+                oracle.set_num_threads(threads)
+            pts = p.mesh.ncells * p.ncomp * units
+            res[label] = {"Gpts_s": round(pts / t / 1e9, 5), "s": round(t, 2),
+                          "units": int(units), "cells": p.mesh.ncells * p.ncomp}
+            if label == "all_threads":
+                tot_units += pts
+                tot_t += t
+        gunits = st["s_total"] if kind == "rkl2" else st["iters_total"]
+        rate = res["all_threads"]["Gpts_s"] * 1e9
+        res["s_per_advance_est"] = round(prob.mesh.ncells * prob.ncomp * gunits / rate, 2)
+        res["gpu_s_per_advance"] = round(st["ms_total"] / 1e3, 4)
+        res["gpu_over_oracle"] = round(res["s_per_advance_est"] / res["gpu_s_per_advance"], 1)
+        res["unit"] = "STS stage" if kind == "rkl2" else "PCG iteration"
+        out[name] = res
     triad = oracle.stream_triad(1 << 26, 5)
-    return {"value": N * st["s_total"] / t / 1e9, "unit": "Gpts/s", "cores": threads,
+    return {"value": round(tot_units / tot_t / 1e9, 5), "unit": "Gpts/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"one RKL2 cycle ({st['s_total']} stages, dt = 50 dt_E) of the 151x301x400 "
-                      f"field-aligned conduction advance; {t:.1f} s on {threads} "
-                      f"threads of the host ({model})",
-            "apply_Gpts_s": {"threads": threads, "all_threads": round(N / t_all / 1e9, 4),
-                             "one_thread": round(N / t_one / 1e9, 4)},
-            "host_stream_triad_GB_s": round(triad, 1), "nproc": os.cpu_count()}
+            "sample": f"the first cycle of each of the four benchmarked advances at the GPU's "
+                      f"cycle length: full grid on {threads} host threads ({_host_model()}); "
+                      f"value = grid-point stages and PCG iterations per second over the four; "
+                      f"per advance also one thread on the first {slab_levels} radial levels",
+            "advances": out, "host_stream_triad_GB_s": round(triad, 1), "nproc": os.cpu_count()}
 
 
 # committed counter summaries: roofline kernel -> (summary, source file of the kernel)
@@ -155,6 +189,30 @@ def measured_traffic(kernel, shape):
     if not m or not h or h.group(1) != sha:
         return None
     return int(m.group(1))
+
+
+def kernel_accounting(s, op, nc, N, NCO, coef_var=False):
+    """Per kernel class of one advance's statistics (timing on): [ms,
+    effective launches, algorithmic bytes].  Launches a PCG batch queues
+    after its solve stopped exit at once: one effective launch per
+    iteration, all launch time charged to them."""
+    out = {}
+    for cls, ms in s["kernel_ms"].items():
+        calls = s["kernel_calls"][cls]
+        if calls == 0:
+            continue
+        if cls in ("matvec", "update", "dir"):
+            calls = s["iters_total"]
+            if calls == 0:
+                continue
+        if cls == "stage":
+            by = stage_bytes(op, nc, N, NCO, coef_var, s["per_cycle"])
+        else:
+            by = calls * bytes_per_launch(op, nc, cls, N, NCO, coef_var)
+        if cls == "dir":
+            by -= dir_saving(op, nc, N, NCO, s["per_cycle"])
+        out[cls] = [ms, calls, by]
+    return out
 
 
 def rel_l2(a, b):
@@ -238,6 +296,24 @@ def learned_leg(paradv, inputs, torch, dev, nr, nt, np_, reps=2):
     rep = g.lpc_train(dt1)
     t_train = time.perf_counter() - t0
     sl = run("learned")
+    # the network's step alone, z = P(r) on the first cycle's system, and the
+    # least it could cost on this chip: 21.6 kflop per cell on the BF16
+    # matrix cores, or the HBM bytes of a fused network reading r, D and the
+    # six face couplings and writing z (72 B per cell)
+    N = nr * nt * np_
+    r = torch.randn(tr.mesh.shape, dtype=torch.float64, device=dev)
+    g.lpc_apply(dt1, r)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    napp = 10
+    e0.record()
+    for _ in range(napp):
+        g.lpc_apply(dt1, r)
+    e1.record()
+    e1.synchronize()
+    t_app = e0.elapsed_time(e1) / napp / 1e3
+    flop = 21600.0 * N
+    t_roof = max(flop / 2.5e15, 72.0 * N / (HBM_PEAK_GBS * 1e9))
+    t_jac = sj["ms_total"] / 1e3 / max(sj["iters_total"], 1)
     return {
         "workload": f"transition-region conduction {nr}x{nt}x{np_}, BE PTL-cycled at dt = 50 dt_E, tol 1e-10",
         "jacobi": {"s_per_advance": round(sj["ms_total"] / 1e3, 4), "pcg_iters": sj["iters_total"],
@@ -247,6 +323,15 @@ def learned_leg(paradv, inputs, torch, dev, nr, nt, np_, reps=2):
                     "rel_residual": sl["rel_residual"]},
         "iters_ratio": round(sl["iters_total"] / max(sj["iters_total"], 1), 3),
         "speedup_vs_jacobi": round(sj["ms_total"] / max(sl["ms_total"], 1e-9), 3),
+        "network": {"ms_per_application": round(1e3 * t_app, 3),
+                    "TFLOP_s": round(flop / t_app / 1e12, 1),
+                    "frac_of_bf16_peak": round(flop / t_app / 2.5e15, 4),
+                    "roofline_ms": round(1e3 * t_roof, 3),
+                    "jacobi_ms_per_iteration": round(1e3 * t_jac, 3)},
+        # the learned solve pays only if it needs fewer than this fraction of
+        # Jacobi's iterations (a step = a Jacobi iteration plus the network)
+        "break_even_iters_ratio": {"measured_step": round(t_jac / (t_jac + t_app), 3),
+                                   "network_at_roofline": round(t_jac / (t_jac + t_roof), 3)},
         "training": {"s": round(t_train, 2), "pairs": rep["pairs"], "steps": rep["steps"],
                      "snapshots": rep["snapshots"], "ref_iters": rep["ref_iters"],
                      "loss_first": round(rep["loss_first"], 5),
@@ -287,12 +372,17 @@ def rkg2_leg(paradv, torch, dev, cond, visc, reps=3):
 
 def bilu0_leg(paradv, inputs, torch, dev, visc, nr, nt, np_, reps=3):
     """BE with the block ILU(0) preconditioner (PC2 of Sec. 3.1) against
-    point Jacobi (PC1) on the 7-point workloads: the three-component
-    viscosity and the isotropic heat recipe at the same grid, PTL-cycled at
-    dt = 50 dt_E, tol 1e-10; seconds per advance, iterations, speedup."""
+    point Jacobi (PC1) on the 7-point workloads: the viscosity fields as
+    three scalar components and the isotropic heat recipe at the same grid,
+    PTL-cycled at dt = 50 dt_E, tol 1e-10; seconds per advance, iterations,
+    speedup."""
     out = {"workload": f"{nr}x{nt}x{np_}, BE PTL-cycled at dt = 50 dt_E, tol 1e-10, "
                        "boxes 8x4x16"}
-    for name, prob in (("viscosity", visc), ("heat", inputs.heat_iso(nr, nt, np_))):
+    import dataclasses
+    # block ILU(0) is built for the 7-point operator: the viscosity fields as
+    # three scalar components
+    visc7 = dataclasses.replace(visc, op="iso7")
+    for name, prob in (("viscosity", visc7), ("heat", inputs.heat_iso(nr, nt, np_))):
         g = paradv.Operator.from_problem(prob)
         u0 = torch.as_tensor(prob.u, device=dev)
         u = torch.empty_like(u0)
@@ -336,6 +426,111 @@ def bilu0_leg(paradv, inputs, torch, dev, visc, nr, nt, np_, reps=3):
     return out
 
 
+def unfloored_leg(paradv, torch, dev, cond, visc, reps=2, max_cycles=20000):
+    """RKL2 cycled at the paper's limit without the floor of dt_E (ptl_floor
+    = 0) beside the floored form, on the benchmark's fields: cycles, stages
+    and seconds per advance (max_cycles bounds the unfloored run)."""
+    out = {}
+    for name, prob in (("conduction", cond), ("viscosity", visc)):
+        g = paradv.Operator.from_problem(prob)
+        u0 = torch.as_tensor(prob.u, device=dev)
+        u = torch.empty_like(u0)
+        dt = 50 * g.dt_explicit()
+        res = {}
+        for label, floor in (("floored", 1.0), ("unfloored", 0.0)):
+            g.set_options(ptl_floor=floor, max_cycles=max_cycles)
+            best = None
+            for k in range(reps + 1):
+                u.copy_(u0)
+                g.bind(u)
+                st = g.advance_rkl2(dt, 0, check=False)
+                if k > 0 and (best is None or st["ms_total"] < best["ms_total"]):
+                    best = st
+            res[label] = {"s_per_advance": round(best["ms_total"] / 1e3, 4),
+                          "cycles": best["cycles"], "stages": best["s_total"],
+                          "status": paradv.STATUS_NAMES[best["status"]],
+                          "dt_ptl_min_over_dtE": float(f"{best['dt_ptl_min'] / g.dt_explicit():.4g}")}
+        out[name] = res
+        del g
+        torch.cuda.empty_cache()
+    return out
+
+
+def c5_leg(paradv, inputs, torch, dev, shape=(256, 512, 1024), reps=2, nseq=20):
+    """The largest workload, 256 x 512 x 1024 (134 M cells): transition-region
+    conduction (T jump at i_tr = 20 + 4 S(501)) and the vector viscosity.
+    Per operator, PTL-cycled at dt = 50 dt_E: FP64 RKL2 and BE + Jacobi PCG
+    with seconds per advance, cycles, stages or iterations and algorithmic
+    GB/s (fraction of 8 TB/s); FP32-stage RKL2 and FP32-matvec BE with their
+    speedup.  Then nseq consecutive FP32-stage RKL2 advances of the
+    conduction with the diffusivity recomputed from the current field before
+    each (time step fixed from the first)."""
+    nr, nt, np_ = shape
+    N, NCO = nr * nt * np_, (nr + 1) * (nt + 1) * np_
+    t0 = time.perf_counter()
+    cond = inputs.transition_region(nr, nt, np_, seed=501, i_tr0=20.0, i_amp=4.0)
+    visc = inputs.viscosity_device(nr, nt, np_, torch, dev)
+    out = {"workload": f"{nr}x{nt}x{np_}: transition-region conduction and vector viscosity, "
+                       "PTL-cycled at dt = 50 dt_E, tol 1e-10",
+           "inputs_s": round(time.perf_counter() - t0, 1)}
+    for name, prob, op, nc in (("conduction", cond, "aligned", 1), ("viscosity", visc, "viscv", 3)):
+        res = {}
+        u0 = torch.as_tensor(prob.u, device=dev)
+        u = torch.empty_like(u0)
+        for prec in ("fp64", "fp32"):
+            g = paradv.Operator.from_problem(prob, prec=prec)
+            g.set_options(timing=int(prec == "fp64"))
+            dt = 50 * g.dt_explicit()
+            for kind in ("rkl2", "be"):
+                best = None
+                for k in range(reps + 1):
+                    u.copy_(u0)
+                    g.bind(u)
+                    st = g.advance_rkl2(dt, 0) if kind == "rkl2" else g.advance_be(dt, 1e-10, 0)
+                    if k > 0 and (best is None or st["ms_total"] < best["ms_total"]):
+                        best = st
+                r = {"s_per_advance": round(best["ms_total"] / 1e3, 4), "cycles": best["cycles"],
+                     "stages" if kind == "rkl2" else "pcg_iters":
+                         best["s_total"] if kind == "rkl2" else best["iters_total"]}
+                if prec == "fp64":
+                    by = sum(v[2] for v in kernel_accounting(best, op, nc, N, NCO).values())
+                    r["GB_s"] = round(by / (best["ms_total"] / 1e3) / 1e9, 1)
+                    r["hbm_frac"] = round(r["GB_s"] / HBM_PEAK_GBS, 3)
+                else:
+                    r["speedup_vs_fp64"] = round(res[f"{kind}_fp64"]["s_per_advance"] /
+                                                 r["s_per_advance"], 3)
+                res[f"{kind}_{prec}"] = r
+            del g
+            torch.cuda.empty_cache()
+        out[name] = res
+        del u0, u
+    # consecutive advances with the diffusivity re-lagged before each
+    g = paradv.Operator.from_problem(cond, prec="fp32")
+    dt = 50 * g.dt_explicit()
+    u = g.bind(cond.u)
+    T0 = torch.empty_like(u[0])
+    Bd = torch.as_tensor(cond.B, device=dev)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    cyc = stg = 0
+    for k in range(nseq):
+        if k:
+            T0.copy_(u[0])
+            g.set_coefficients(T0, cond.scale, cond.expo, Bd)
+        st = g.advance_rkl2(dt, 0)
+        cyc += st["cycles"]
+        stg += st["s_total"]
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t1
+    out["sequence"] = {"advances": nseq, "s": round(ts, 3), "s_per_advance": round(ts / nseq, 4),
+                       "cycles": cyc, "stages": stg,
+                       "what": "FP32-stage RKL2 conduction, diffusivity recomputed from the "
+                               "current temperature before each advance"}
+    del g, u, Bd
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -345,9 +540,9 @@ def main():
     ap.add_argument("--shape", default="151,301,400")
     ap.add_argument("--leg-reps", type=int, default=3,
                     help="timed repetitions of each advance in the block ILU(0) leg")
-    ap.add_argument("--legs", default="fp32,learned,bilu0,rkg2",
+    ap.add_argument("--legs", default="fp32,learned,bilu0,rkg2,unfloored,c5",
                     help="extra legs reported beside the timed step: fp32, learned, bilu0, "
-                         "rkg2, none")
+                         "rkg2, unfloored, c5, none")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library runs the advance on a single "
@@ -363,12 +558,12 @@ def main():
     dev = torch.device("cuda:0")
     log(f"building inputs {nr}x{nt}x{np_}")
     cond = inputs.conduction(nr, nt, np_)
-    visc = inputs.viscosity(nr, nt, np_)
+    visc = inputs.viscosity(nr, nt, np_, vector=True)
     N = nr * nt * np_
     NCO = (nr + 1) * (nt + 1) * np_
 
     gc = paradv.Operator(cond.mesh, "aligned", 1, "dirichlet", "dirichlet", "fp64")
-    gv = paradv.Operator(visc.mesh, "iso7", 3, "dirichlet", "dirichlet", "fp64")
+    gv = paradv.Operator(visc.mesh, "viscv", 3, "dirichlet", "dirichlet", "fp64")
     gc.set_bc(cond.ub_in, cond.ub_out)
     gv.set_bc(visc.ub_in, visc.ub_out)
     T0 = torch.as_tensor(cond.T0, device=dev)
@@ -429,8 +624,8 @@ def main():
     ms_per_step = 1e3 * elapsed / args.steps
 
     ncomp = {"rkl2_conduction": 1, "rkl2_viscosity": 3, "be_conduction": 1, "be_viscosity": 3}
-    ops = {"rkl2_conduction": "aligned", "rkl2_viscosity": "iso7", "be_conduction": "aligned",
-           "be_viscosity": "iso7"}
+    ops = {"rkl2_conduction": "aligned", "rkl2_viscosity": "viscv", "be_conduction": "aligned",
+           "be_viscosity": "viscv"}
     work = 0
     adv = {}
     kern = {}   # (advance, class) -> [ms, calls, bytes]
@@ -443,23 +638,8 @@ def main():
             a["cycles"] = s["cycles"]
             a["stages"] = s["s_total"]
             a["pcg_iters"] = s["iters_total"]
-            for cls, ms in s["kernel_ms"].items():
-                calls = s["kernel_calls"][cls]
-                if calls == 0:
-                    continue
-                if cls in ("matvec", "update", "dir"):
-                    # launches queued after the solve stopped exit at once;
-                    # count one effective launch per iteration and charge
-                    # all launch time to them
-                    calls = s["iters_total"]
-                    if calls == 0:
-                        continue
-                if cls == "stage":
-                    by = stage_bytes(ops[name], ncomp[name], N, NCO, False, s["per_cycle"])
-                else:
-                    by = calls * bytes_per_launch(ops[name], ncomp[name], cls, N, NCO, False)
-                if cls == "dir":
-                    by -= dir_saving(ops[name], ncomp[name], N, NCO, s["per_cycle"])
+            for cls, (ms, calls, by) in kernel_accounting(s, ops[name], ncomp[name], N,
+                                                          NCO).items():
                 e = kern.setdefault((name, cls), [0.0, 0, 0])
                 e[0] += ms
                 e[1] += calls
@@ -476,8 +656,23 @@ def main():
         a["hbm_frac"] = round(by / a["s"] / 1e9 / HBM_PEAK_GBS, 3) if a["s"] > 0 else None
     kernels = {f"{a}/{c}": {"ms_total": round(v[0] / args.steps, 3), "calls": v[1] // args.steps,
                             "avg_us": round(1e3 * v[0] / v[1], 2),
-                            "GB_s": round(v[2] / (v[0] / 1e3) / 1e9, 1) if v[2] else None}
+                            "GB_s": round(v[2] / (v[0] / 1e3) / 1e9, 1) if v[2] else None,
+                            "frac": round(v[2] / (v[0] / 1e3) / 1e9 / HBM_PEAK_GBS, 3)
+                            if v[2] else None}
                for (a, c), v in sorted(kern.items(), key=lambda kv: -kv[1][0])}
+    # the stencil kernels (operator apply inside the PTL pass, the fused STS
+    # stage and the PCG matvec) per operator, beside the dominant kernel
+    stencil = {}
+    for opn in ("conduction", "viscosity"):
+        for cls in ("first", "stage", "matvec"):
+            ms = by = 0.0
+            for (a, c), v in kern.items():
+                if a.endswith(opn) and c == cls:
+                    ms += v[0]
+                    by += v[2]
+            if ms > 0:
+                stencil[f"{opn}/{cls}"] = {"GB_s": round(by / (ms / 1e3) / 1e9, 1),
+                                           "frac": round(by / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 3)}
 
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "Gpts/s", "n_gpus": 1,
@@ -493,6 +688,7 @@ def main():
                      "traffic": measured_traffic(f"{dname}/{dcls}", (nr, nt, np_)),
                      "kernel": f"{dname}/{dcls}", "avg_launch_us": round(1e3 * avg_ms, 2),
                      "bytes_per_launch": int(dbytes / dcalls)},
+        "stencil_roofline": stencil,
         "kernels": kernels,
         "copy_GB_s": round(copy_gbs, 1),
     }
@@ -523,9 +719,15 @@ def main():
         log("block ILU(0) leg")
         out["bilu0_pc"] = bilu0_leg(paradv, inputs, torch, dev, visc, nr, nt, np_,
                                     reps=args.leg_reps)
+    if "unfloored" in legs:
+        log("unfloored limit leg")
+        out["rkl2_unfloored_ptl"] = unfloored_leg(paradv, torch, dev, cond, visc)
+    if "c5" in legs:
+        log("256x512x1024 leg")
+        out["c5"] = c5_leg(paradv, inputs, torch, dev)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = run_cpu_baseline(cond)
+        out["cpu_baseline"] = run_cpu_baseline({"conduction": cond, "viscosity": visc}, stats[-1])
     print(json.dumps(out), flush=True)
 
 
