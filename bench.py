@@ -37,13 +37,14 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def bytes_per_launch(op, ncomp, cls, N, NCO, coef_var, stage_k=None):
-    """Algorithmic HBM bytes of one launch (FP64): every array the kernel
-    needs read once, every output written once.  Field-aligned coefficients
-    are 3 doubles per corner; the 7-point operator reads a cell coefficient
-    array only when the coefficient varies."""
-    coef = 24 * NCO if op == "aligned" else (8 * N if coef_var else 0)
-    f = 8 * N * ncomp
+def bytes_per_launch(op, ncomp, cls, N, NCO, coef_var, stage_k=None, word=8):
+    """Algorithmic HBM bytes of one launch: every array the kernel needs read
+    once, every output written once, `word` bytes per value (8: FP64; 4:
+    the FP32 stencil and stage kernels).  Field-aligned coefficients are 3
+    values per corner; the 7-point operator reads a cell coefficient array
+    only when the coefficient varies."""
+    coef = 3 * word * NCO if op == "aligned" else (word * N if coef_var else 0)
+    f = word * N * ncomp
     if cls == "first":
         return 2 * f + coef
     if cls == "stage":
@@ -71,12 +72,12 @@ def dir_saving(op, ncomp, N, NCO, per_cycle):
                     - bytes_per_launch(op, ncomp, "dir_last", N, NCO, False))
 
 
-def stage_bytes(op, ncomp, N, NCO, coef_var, per_cycle):
+def stage_bytes(op, ncomp, N, NCO, coef_var, per_cycle, word=8):
     """Sum of algorithmic bytes over the stage launches of an STS advance."""
     tot = 0
     for s in per_cycle:
         for k in range(2, int(s) + 1):
-            tot += bytes_per_launch(op, ncomp, "stage", N, NCO, coef_var, stage_k=k)
+            tot += bytes_per_launch(op, ncomp, "stage", N, NCO, coef_var, stage_k=k, word=word)
     return tot
 
 
@@ -229,7 +230,7 @@ def fp32_leg(paradv, torch, dev, cond, visc, reps=3):
     out = {}
     for name, prob, op, nc, T0, scale, expo in (
             ("conduction", cond, "aligned", 1, cond.T0, 1.0, 2.5),
-            ("viscosity", visc, "iso7", 3, None, 1e-3, 0.0)):
+            ("viscosity", visc, visc.op, 3, None, 1e-3, 0.0)):
         res = {}
         ref = {}
         for prec in ("fp64", "fp32"):
@@ -248,6 +249,27 @@ def fp32_leg(paradv, torch, dev, cond, visc, reps=3):
                     st = g.advance_rkl2(dt, 0) if kind == "rkl2" else g.advance_be(dt, 1e-10, 0)
                     if k > 0:
                         times.append(st["ms_total"] / 1e3)
+                if kind == "rkl2" and prec == "fp32":
+                    # one more run with per-class timing: the FP32 PTL pass
+                    # and stage kernels against their FP32 bytes
+                    g.set_options(timing=1)
+                    u.copy_(u0)
+                    g.bind(u)
+                    tst = g.advance_rkl2(dt, 0)
+                    g.set_options()
+                    mr, mt, mp = prob.mesh.shape
+                    N, NCO = mr * mt * mp, (mr + 1) * (mt + 1) * mp
+                    cls_gbs = {}
+                    for cls in ("first", "stage"):
+                        ms = tst["kernel_ms"][cls]
+                        if ms <= 0:
+                            continue
+                        by = (stage_bytes(op, nc, N, NCO, T0 is not None, tst["per_cycle"], word=4)
+                              if cls == "stage" else
+                              tst["kernel_calls"][cls] * bytes_per_launch(op, nc, cls, N, NCO,
+                                                                          T0 is not None, word=4))
+                        cls_gbs[cls] = {"GB_s": round(by / (ms / 1e3) / 1e9, 1),
+                                        "frac": round(by / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 3)}
                 key = f"{kind}_{prec}"
                 res[key] = {"s_per_advance": round(min(times), 4), "cycles": st["cycles"],
                             "stages" if kind == "rkl2" else "pcg_iters":
@@ -257,6 +279,8 @@ def fp32_leg(paradv, torch, dev, cond, visc, reps=3):
                 else:
                     res[key]["rel_err_vs_fp64"] = [round(rel_l2(u[c], ref[kind][c]), 9)
                                                    for c in range(nc)]
+                    if kind == "rkl2":
+                        res[key]["kernels_fp32"] = cls_gbs
                     res[key]["speedup_vs_fp64"] = round(
                         res[f"{kind}_fp64"]["s_per_advance"] / res[key]["s_per_advance"], 3)
             del g
@@ -426,6 +450,38 @@ def bilu0_leg(paradv, inputs, torch, dev, visc, nr, nt, np_, reps=3):
     return out
 
 
+def c1_leg(paradv, inputs, torch, dev, reps=20):
+    """The small scalar heat workload, 32 x 32 x 64 (kappa = T^{5/2},
+    Dirichlet T): one RKL2 advance of s = 10 stages at dt = 24.3 dt_E and one
+    Backward Euler + Jacobi PCG step at the same dt, tol 1e-10.  It fits in
+    the caches and is bound by launch latency, so no roofline is attached;
+    median of `reps` timed repetitions."""
+    prob = inputs.heat_iso(32, 32, 64)
+    g = paradv.Operator.from_problem(prob)
+    dt = 24.3 * g.dt_explicit()
+    u0 = torch.as_tensor(prob.u, device=dev)
+    u = torch.empty_like(u0)
+    out = {"workload": "32x32x64 scalar heat, kappa = T^(5/2), dt = 24.3 dt_E"}
+    N = prob.mesh.ncells
+    for kind in ("rkl2", "be"):
+        if kind == "rkl2":
+            g.set_options(s_override=10, force_odd=0)
+        else:
+            g.set_options()
+        ms, st = [], None
+        for k in range(reps + 2):
+            u.copy_(u0)
+            g.bind(u)
+            st = g.advance_rkl2(dt, 1) if kind == "rkl2" else g.advance_be(dt, 1e-10, 1)
+            if k >= 2:
+                ms.append(st["ms_total"])
+        t = sorted(ms)[len(ms) // 2] / 1e3
+        units = st["s_total"] if kind == "rkl2" else st["iters_total"]
+        out[kind] = {"s_per_advance": round(t, 6), "stages" if kind == "rkl2" else "pcg_iters": units,
+                     "Gpts_s": round(N * units / t / 1e9, 3)}
+    return out
+
+
 def unfloored_leg(paradv, torch, dev, cond, visc, reps=2, max_cycles=20000):
     """RKL2 cycled at the paper's limit without the floor of dt_E (ptl_floor
     = 0) beside the floored form, on the benchmark's fields: cycles, stages
@@ -540,8 +596,8 @@ def main():
     ap.add_argument("--shape", default="151,301,400")
     ap.add_argument("--leg-reps", type=int, default=3,
                     help="timed repetitions of each advance in the block ILU(0) leg")
-    ap.add_argument("--legs", default="fp32,learned,bilu0,rkg2,unfloored,c5",
-                    help="extra legs reported beside the timed step: fp32, learned, bilu0, "
+    ap.add_argument("--legs", default="c1,fp32,learned,bilu0,rkg2,unfloored,c5",
+                    help="extra legs reported beside the timed step: c1, fp32, learned, bilu0, "
                          "rkg2, unfloored, c5, none")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -719,6 +775,9 @@ def main():
         log("block ILU(0) leg")
         out["bilu0_pc"] = bilu0_leg(paradv, inputs, torch, dev, visc, nr, nt, np_,
                                     reps=args.leg_reps)
+    if "c1" in legs:
+        log("32x32x64 leg")
+        out["c1"] = c1_leg(paradv, inputs, torch, dev)
     if "unfloored" in legs:
         log("unfloored limit leg")
         out["rkl2_unfloored_ptl"] = unfloored_leg(paradv, torch, dev, cond, visc)

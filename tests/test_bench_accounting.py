@@ -24,6 +24,8 @@ N, NCO = 1000, 1010
     ("matvec", "iso7", 3, 3 * 16),
     ("update", "iso7", 3, 3 * 24 + 8),                # 80 B per cell
     ("dir", "iso7", 3, 3 * 40 + 8),                   # 128 B per cell
+    ("update", "viscv", 3, 3 * 24 + 8),
+    ("dir", "viscv", 3, 3 * 40 + 8),
     ("init", "iso7", 3, 3 * 32 + 16),                 # u, y0, diag L; r, p, D
     ("dir_last", "iso7", 3, 3 * 24),                  # x, p; x
 ])
@@ -53,3 +55,11 @@ def test_dir_saving():
     per = bench.bytes_per_launch("iso7", 3, "dir", N, NCO, False) - 9 * f
     assert per == 6 * f + 8 * N
     assert bench.dir_saving("iso7", 3, N, NCO, [12, 0, 7, 1]) == 3 * per
+
+
+def test_fp32_bytes():
+    """The FP32 stencil kernels move 4-byte values, corner coefficients
+    included (12 B per corner)."""
+    assert bench.bytes_per_launch("aligned", 1, "first", N, NCO, False, word=4) == 8 * N + 12 * NCO
+    assert bench.bytes_per_launch("viscv", 3, "stage", N, NCO, False, stage_k=5, word=4) == 5 * 12 * N
+    assert bench.stage_bytes("viscv", 3, N, NCO, False, [3], word=4) == 3 * 12 * N + 4 * 12 * N
