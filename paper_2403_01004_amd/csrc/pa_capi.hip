@@ -1331,7 +1331,7 @@ bool nn_bwd_work(pa_ctx* c, size_t pts)
     c->nn_ga = c->nn_gb = c->nn_g1 = nullptr;
     c->nn_wpart = nullptr;
     c->nn_bcap = 0;
-    const size_t wp = (size_t)nn_wgrad_blocks((long)pts) * 16 * 433;
+    const size_t wp = (size_t)nn_wgrad_partials((long)pts) * 16 * 433;
     if (!need(c, c->nn_ga, 2 * 16 * pts) || !need(c, c->nn_gb, 2 * 16 * pts) ||
         !need(c, c->nn_g1, 2 * pts) || !need(c, c->nn_wpart, sizeof(float) * wp))
         return false;

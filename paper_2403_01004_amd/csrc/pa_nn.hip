@@ -90,10 +90,78 @@ struct NNGrid {
     int nr, nt, np, per;
 };
 
+// Tiled convolution.  A workgroup owns a 16 (phi) x 16 (theta) tile of one
+// element and marches a chunk of kConvRch radial levels.  The input planes
+// of the tile with a one-cell halo ring (18 x 18 cells, all channels) sit in
+// a ring of four LDS slots: output level i reads the planes of i - 1, i and
+// i + 1, while the plane of i + 2 is loaded into registers; so each input
+// value is read from memory once per chunk and the 27-point gathers of the
+// implicit GEMM are LDS reads.  Planes and cells outside the element's
+// radial or colatitude range (and outside phi when not periodic) hold zeros.
+// Wave w computes rows 4w .. 4w + 3 of the tile, each row as 16 points x 16
+// output channels on the matrix cores, with K = 27 * CIN (padded to a
+// multiple of 32) taken in the same order as the operand tables: k = tap *
+// CIN + ci, tap = (di + 1) * 9 + (dj + 1) * 3 + (dk + 1).
+constexpr int kConvT = 16;                     // tile edge (cells)
+constexpr int kConvH = kConvT + 2;             // with the halo ring
+constexpr int kConvPlane = kConvH * kConvH;    // 324 cells
+constexpr int kConvRch = 16;                   // levels per workgroup
+
+template <int CIN>
+struct ConvChunk {
+    // one load slot: 8 channels (16 B) of a cell, or one value when CIN == 1
+    static constexpr int per_cell = CIN >= 8 ? CIN / 8 : 1;
+    static constexpr int count = kConvPlane * per_cell;
+    static constexpr int per_thread = (count + 255) / 256;
+};
+
+template <int CIN>
+__device__ __forceinline__ void conv_load_plane(const NNGrid& gd, const __bf16* x, long ebase,
+                                                int lv, int j0, int k0, uint4 (&reg)[ConvChunk<CIN>::per_thread])
+{
+    using C = ConvChunk<CIN>;
+    const bool lv_ok = lv >= 0 && lv < gd.nr;
+#pragma unroll
+    for (int q = 0; q < C::per_thread; ++q) {
+        const int c = threadIdx.x + 256 * q;
+        uint4 v = {0u, 0u, 0u, 0u};
+        if (c < C::count && lv_ok) {
+            const int cell = c / C::per_cell, part = c % C::per_cell;
+            const int j = j0 - 1 + cell / kConvH;
+            int k = k0 - 1 + cell % kConvH;
+            // only k = -1 and k = np are ever a real cell's neighbour
+            bool ok = j >= 0 && j < gd.nt && k <= gd.np;
+            if (k < 0 || k == gd.np) {
+                if (gd.per) k = k < 0 ? gd.np - 1 : 0;
+                else ok = false;
+            }
+            if (ok) {
+                const long p = ((ebase + lv) * gd.nt + j) * gd.np + k;
+                if constexpr (CIN >= 8) v = *(const uint4*)(x + p * CIN + 8 * part);
+                else v.x = (unsigned)*(const unsigned short*)(x + p);
+            }
+        }
+        reg[q] = v;
+    }
+}
+
+template <int CIN>
+__device__ __forceinline__ void conv_store_plane(__bf16* slot, const uint4 (&reg)[ConvChunk<CIN>::per_thread])
+{
+    using C = ConvChunk<CIN>;
+#pragma unroll
+    for (int q = 0; q < C::per_thread; ++q) {
+        const int c = threadIdx.x + 256 * q;
+        if (c < C::count) {
+            if constexpr (CIN >= 8) *(uint4*)(slot + 8 * c) = reg[q];
+            else *(unsigned short*)(slot + c) = (unsigned short)reg[q].x;
+        }
+    }
+}
+
 // EPI 0: + bias, ReLU -> BF16 [p][16];  EPI 1: row 0 -> FP32 [p];
 // EPI 2: times (mask[p][co] > 0) -> BF16 [p][16] (input gradient through ReLU)
-// One wave computes 16 points x 16 output channels; the launch is skipped
-// when *done != 0 (done may be null).
+// The launch is skipped when *done != 0 (done may be null).
 template <int CIN, int EPI>
 __global__ __launch_bounds__(256) void k_conv(NNGrid gd, const int* done, const __bf16* x,
                                               const __bf16* W, const float* bias,
@@ -101,70 +169,112 @@ __global__ __launch_bounds__(256) void k_conv(NNGrid gd, const int* done, const 
 {
     constexpr int KP = ((27 * CIN + 31) / 32) * 32;
     constexpr int NCH = KP / 32;
+    constexpr int SLOT = kConvPlane * CIN;
+    __shared__ __align__(16) __bf16 sh[4 * SLOT];
     if (done && *done) return;
-    const int nr = gd.nr, nt = gd.nt, np = gd.np, per = gd.per;
-    const int lane = threadIdx.x & 63;
-    const long N = (long)gd.nlev * nt * np;
-    const long p0 = ((long)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
-    if (p0 >= N) return;
+    const int nr = gd.nr, nt = gd.nt, np = gd.np;
+    const int ntk = (np + kConvT - 1) / kConvT, ntj = (nt + kConvT - 1) / kConvT;
+    const int nrc = (nr + kConvRch - 1) / kConvRch;
+    int L = blockIdx.x;
+    const int tk = L % ntk;
+    L /= ntk;
+    const int tj = L % ntj;
+    L /= ntj;
+    const int rc = L % nrc, e = L / nrc;
+    const int k0 = tk * kConvT, j0 = tj * kConvT;
+    const int i0 = rc * kConvRch, i1 = min(nr, i0 + kConvRch);
+    const long ebase = (long)e * nr;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int n = lane & 15, g = lane >> 4;
-    long p = p0 + n;
-    const bool pv = p < N;
-    if (!pv) p = N - 1;
-    const int k = (int)(p % np);
-    const long t1 = p / np;
-    const int j = (int)(t1 % nt), I = (int)(t1 / nt), i = I % nr;
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    // this lane's A operands (weights): row n, k = 32 ch + 8 g .. + 7
+    bf16x8 A[NCH];
 #pragma unroll
-    for (int ch = 0; ch < NCH; ++ch) {
-        const bf16x8 a = *(const bf16x8*)(W + n * KP + ch * 32 + 8 * g);
-        bf16x8 b;
-        if constexpr (CIN == 8) {
-            const int t = ch * 4 + g;
-            const long q = t < 27 ? nb_index(I, i, j, k, t, nr, nt, np, per) : -1;
-            b = q >= 0 ? *(const bf16x8*)(x + q * 8) : zero8();
-        } else if constexpr (CIN == 16) {
-            const int t = ch * 2 + (g >> 1);
-            const long q = t < 27 ? nb_index(I, i, j, k, t, nr, nt, np, per) : -1;
-            b = q >= 0 ? *(const bf16x8*)(x + q * 16 + 8 * (g & 1)) : zero8();
-        } else {  // CIN == 1: the lane's eight k are eight taps
+    for (int ch = 0; ch < NCH; ++ch) A[ch] = *(const bf16x8*)(W + n * KP + ch * 32 + 8 * g);
+    uint4 reg[ConvChunk<CIN>::per_thread];
+    conv_load_plane<CIN>(gd, x, ebase, i0 - 1, j0, k0, reg);
+    conv_store_plane<CIN>(sh + ((i0 + 3) & 3) * SLOT, reg);
+    conv_load_plane<CIN>(gd, x, ebase, i0, j0, k0, reg);
+    conv_store_plane<CIN>(sh + ((i0 + 4) & 3) * SLOT, reg);
+    conv_load_plane<CIN>(gd, x, ebase, i0 + 1, j0, k0, reg);
+    for (int lv = i0; lv < i1; ++lv) {
+        conv_store_plane<CIN>(sh + ((lv + 5) & 3) * SLOT, reg);
+        if (lv + 2 <= i1) conv_load_plane<CIN>(gd, x, ebase, lv + 2, j0, k0, reg);
+        __syncthreads();
+        f32x4 acc[4];
 #pragma unroll
-            for (int qq = 0; qq < 8; ++qq) {
-                const int t = 8 * g + qq;
-                const long q = t < 27 ? nb_index(I, i, j, k, t, nr, nt, np, per) : -1;
-                b[qq] = q >= 0 ? x[q] : (__bf16)0.0f;
+        for (int q = 0; q < 4; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = 4 * wv + q;
+                bf16x8 b;
+                if constexpr (CIN >= 8) {
+                    constexpr int TPC = 32 / CIN;         // taps per chunk (2 or 4)
+                    constexpr int LPT = 4 / TPC;          // lane groups per tap
+                    const int t = ch * TPC + g / LPT;
+                    if (t < 27) {
+                        const int di = t / 9 - 1, dj = (t / 3) % 3 - 1, dk = t % 3 - 1;
+                        const __bf16* s = sh + ((lv + 4 + di) & 3) * SLOT;
+                        const int cell = (row + 1 + dj) * kConvH + (n + 1 + dk);
+                        b = *(const bf16x8*)(s + cell * CIN + 8 * (g % LPT));
+                    } else {
+                        b = zero8();
+                    }
+                } else {  // CIN == 1: the lane's eight k are eight taps
+#pragma unroll
+                    for (int qq = 0; qq < 8; ++qq) {
+                        const int t = 8 * g + qq;
+                        if (t < 27) {
+                            const int di = t / 9 - 1, dj = (t / 3) % 3 - 1, dk = t % 3 - 1;
+                            const __bf16* s = sh + ((lv + 4 + di) & 3) * SLOT;
+                            b[qq] = s[(row + 1 + dj) * kConvH + (n + 1 + dk)];
+                        } else {
+                            b[qq] = (__bf16)0.0f;
+                        }
+                    }
+                }
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ch], b, acc[q], 0, 0, 0);
             }
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
-    }
-    if (!pv) return;
-    if constexpr (EPI == 1) {
-        if (g == 0) ((float*)out)[p] = acc[0];
-    } else {
-        __bf16 v4[4];
+        const int k = k0 + n;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int co = 4 * g + r;
-            float v = acc[r];
-            if constexpr (EPI == 0) v = fmaxf(v + bias[co], 0.0f);
-            else v = ((float)mask[p * 16 + co] > 0.0f) ? v : 0.0f;
-            v4[r] = (__bf16)v;
+        for (int q = 0; q < 4; ++q) {
+            const int j = j0 + 4 * wv + q;
+            if (j >= nt || k >= np) continue;
+            const long p = ((ebase + lv) * nt + j) * np + k;
+            if constexpr (EPI == 1) {
+                if (g == 0) ((float*)out)[p] = acc[q][0];
+            } else {
+                __bf16 v4[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int co = 4 * g + r;
+                    float v = acc[q][r];
+                    if constexpr (EPI == 0) v = fmaxf(v + bias[co], 0.0f);
+                    else v = ((float)mask[p * 16 + co] > 0.0f) ? v : 0.0f;
+                    v4[r] = (__bf16)v;
+                }
+                __bf16* o = (__bf16*)out + p * 16 + 4 * g;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) o[r] = v4[r];
+            }
         }
-        __bf16* o = (__bf16*)out + p * 16 + 4 * g;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) o[r] = v4[r];
     }
 }
 
-static int conv_blocks(long N) { return (int)((N + 63) / 64); }
+static int conv_blocks(int nb, int nr, int nt, int np)
+{
+    return ((np + kConvT - 1) / kConvT) * ((nt + kConvT - 1) / kConvT) *
+           ((nr + kConvRch - 1) / kConvRch) * nb;
+}
 
 void launch_nn_conv(int layer, int dir, int nb, int nr, int nt, int np, int per, const int* done,
                     const __bf16* x, const NNWeights& w, const float* theta, const __bf16* mask,
                     void* out, hipStream_t s)
 {
     const NNGrid gd{nb * nr, nr, nt, np, per};
-    const long N = (long)nb * nr * nt * np;
-    const dim3 gr(conv_blocks(N)), bl(256);
+    const dim3 gr(conv_blocks(nb, nr, nt, np)), bl(256);
     if (dir == 0) {  // forward
         if (layer == 1)
             hipLaunchKernelGGL((k_conv<8, 0>), gr, bl, 0, s, gd, done, x, w.f1, theta + NN_OFF_B1,
@@ -189,14 +299,13 @@ void launch_nn_conv(int layer, int dir, int nb, int nr, int nt, int np, int per,
 // kc = t*CIN + ci (< 27*CIN) or the bias column kc = 27*CIN (X = 1).
 // Writes part[block][co][kc] for co < COUT, kc < NKC.
 template <int CIN, int COUT, bool BIAS>
-__global__ __launch_bounds__(256) void k_wgrad(NNGrid gd, const __bf16* X, const __bf16* G,
+__global__ __launch_bounds__(256) void k_wgrad(NNGrid gd, long PB, const __bf16* X, const __bf16* G,
                                                float* part)
 {
     const int nr = gd.nr, nt = gd.nt, np = gd.np, per = gd.per;
     constexpr int NKC = 27 * CIN + (BIAS ? 1 : 0);
     constexpr int NTILE = (NKC + 15) / 16;
     constexpr int TPW = (NTILE + 3) / 4;  // column tiles per wave
-    constexpr int PB = 1024;              // points per block
     const long N = (long)gd.nlev * nt * np;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int n = lane & 15, g = lane >> 4;
@@ -261,7 +370,22 @@ __global__ __launch_bounds__(256) void k_wgrad(NNGrid gd, const __bf16* X, const
     }
 }
 
-// grad[layer offsets] += sum over blocks (fixed order) of the partials
+// The partials are summed in a fixed order in two passes: segment s of
+// kWgradSeg consecutive blocks into row s of part2, then the rows of part2
+// in order into grad[layer offsets].
+constexpr int kWgradBlocks = 2048;  // most blocks of one weight-gradient launch
+constexpr int kWgradSeg = 64;       // blocks per first-pass segment
+
+__global__ void k_wgrad_seg(const float* part, int nblk, int ncol, float* part2)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= ncol) return;
+    const int b0 = blockIdx.y * kWgradSeg, b1 = min(nblk, b0 + kWgradSeg);
+    float s = 0.0f;
+    for (int b = b0; b < b1; ++b) s += part[(size_t)b * ncol + x];
+    part2[(size_t)blockIdx.y * ncol + x] = s;
+}
+
 __global__ void k_wgrad_reduce(const float* part, int nblk, int cout, int cin, int bias,
                                int off_w, int off_b, float* grad)
 {
@@ -279,28 +403,40 @@ __global__ void k_wgrad_reduce(const float* part, int nblk, int cout, int cin, i
     }
 }
 
-int nn_wgrad_blocks(long npoints) { return (int)((npoints + 1023) / 1024); }
+static int wgrad_blocks(long npoints)
+{
+    return (int)std::min<long>(kWgradBlocks, (npoints + 1023) / 1024);
+}
+
+int nn_wgrad_partials(long npoints)
+{
+    const int nblk = wgrad_blocks(npoints);
+    return nblk + (nblk + kWgradSeg - 1) / kWgradSeg;
+}
 
 void launch_nn_wgrad(int layer, int nb, int nr, int nt, int np, int per, const __bf16* X,
                      const __bf16* G, float* part, float* grad, hipStream_t s)
 {
     const NNGrid gd{nb * nr, nr, nt, np, per};
-    const int nblk = nn_wgrad_blocks((long)nb * nr * nt * np);
-    if (layer == 1) {
-        hipLaunchKernelGGL((k_wgrad<8, 16, true>), dim3(nblk), dim3(256), 0, s, gd, X, G, part);
-        hipLaunchKernelGGL(k_wgrad_reduce, dim3((16 * 217 + 255) / 256), dim3(256), 0, s, part, nblk,
-                           16, 8, 1, NN_OFF_W1, NN_OFF_B1, grad);
-    } else if (layer == 2) {
-        hipLaunchKernelGGL((k_wgrad<16, 16, true>), dim3(nblk), dim3(256), 0, s, gd, X, G,
-                           part);
-        hipLaunchKernelGGL(k_wgrad_reduce, dim3((16 * 433 + 255) / 256), dim3(256), 0, s, part, nblk,
-                           16, 16, 1, NN_OFF_W2, NN_OFF_B2, grad);
-    } else {
-        hipLaunchKernelGGL((k_wgrad<16, 1, false>), dim3(nblk), dim3(256), 0, s, gd, X, G,
-                           part);
-        hipLaunchKernelGGL(k_wgrad_reduce, dim3((432 + 255) / 256), dim3(256), 0, s, part, nblk, 1,
-                           16, 0, NN_OFF_W3, 0, grad);
-    }
+    const long N = (long)nb * nr * nt * np;
+    const int nblk = wgrad_blocks(N);
+    // points per block: a multiple of the 32 points one step takes
+    const long PB = ((N + nblk - 1) / nblk + 31) / 32 * 32;
+    const int nseg = (nblk + kWgradSeg - 1) / kWgradSeg;
+    const int cin = layer == 1 ? 8 : 16, cout = layer == 3 ? 1 : 16, bias = layer == 3 ? 0 : 1;
+    const int ncol = cout * (27 * cin + bias);
+    float* part2 = part + (size_t)nblk * ncol;
+    if (layer == 1)
+        hipLaunchKernelGGL((k_wgrad<8, 16, true>), dim3(nblk), dim3(256), 0, s, gd, PB, X, G, part);
+    else if (layer == 2)
+        hipLaunchKernelGGL((k_wgrad<16, 16, true>), dim3(nblk), dim3(256), 0, s, gd, PB, X, G, part);
+    else
+        hipLaunchKernelGGL((k_wgrad<16, 1, false>), dim3(nblk), dim3(256), 0, s, gd, PB, X, G, part);
+    hipLaunchKernelGGL(k_wgrad_seg, dim3((ncol + 255) / 256, nseg), dim3(256), 0, s, part, nblk,
+                       ncol, part2);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((ncol + 255) / 256), dim3(256), 0, s, part2, nseg,
+                       cout, cin, bias, layer == 1 ? NN_OFF_W1 : layer == 2 ? NN_OFF_W2 : NN_OFF_W3,
+                       layer == 1 ? NN_OFF_B1 : layer == 2 ? NN_OFF_B2 : 0, grad);
 }
 
 // ---------------------------------------------------------------- features
