@@ -1331,7 +1331,8 @@ bool nn_bwd_work(pa_ctx* c, size_t pts)
     c->nn_ga = c->nn_gb = c->nn_g1 = nullptr;
     c->nn_wpart = nullptr;
     c->nn_bcap = 0;
-    const size_t wp = (size_t)nn_wgrad_partials((long)pts) * 16 * 433;
+    const int nb = (int)((pts + c->N - 1) / c->N);
+    const size_t wp = (size_t)nn_wgrad_partials(nb, c->d.nr, c->d.nt, c->d.np) * 16 * 433;
     if (!need(c, c->nn_ga, 2 * 16 * pts) || !need(c, c->nn_gb, 2 * 16 * pts) ||
         !need(c, c->nn_g1, 2 * pts) || !need(c, c->nn_wpart, sizeof(float) * wp))
         return false;

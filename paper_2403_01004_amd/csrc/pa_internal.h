@@ -175,8 +175,8 @@ void launch_nn_conv(int layer, int dir, int nb, int nr, int nt, int np, int per,
                     const __bf16* x, const NNWeights& w, const float* theta, const __bf16* mask,
                     void* out, hipStream_t s);
 // grad[layer's weights and bias] += sum_p G[p][co] X[p + tap][ci];
-// part holds nn_wgrad_partials(points) * 16 * 433 floats
-int nn_wgrad_partials(long npoints);
+// part holds nn_wgrad_partials(nb, nr, nt, np) * 16 * 433 floats
+int nn_wgrad_partials(int nb, int nr, int nt, int np);
 void launch_nn_wgrad(int layer, int nb, int nr, int nt, int np, int per, const __bf16* X,
                      const __bf16* G, float* part, float* grad, hipStream_t s);
 void launch_nn_static(const Geo<double>& g, double dt, const double* w, const double* D,

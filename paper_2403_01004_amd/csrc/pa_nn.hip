@@ -297,63 +297,123 @@ void launch_nn_conv(int layer, int dir, int nb, int nr, int nt, int np, int per,
 
 // Partial dW over a block of points: D[co][kc] = sum_p G[p][co] X[p][kc],
 // kc = t*CIN + ci (< 27*CIN) or the bias column kc = 27*CIN (X = 1).
-// Writes part[block][co][kc] for co < COUT, kc < NKC.
+// Tiled like the convolution: a workgroup owns a 16 x 16 tile of one element
+// over kWgradRch radial levels, and a level's 256 points are eight K-chunks
+// of 32 (two tile rows each).  The level's G (no halo) is staged in LDS
+// transposed, [co][point], so a lane's eight points of one channel are one
+// 16-byte read; the input planes (with the halo, three levels) sit in a
+// ring of four slots, channel-planar [ci][cell].  Points outside the mesh
+// carry G = 0.  Wave w accumulates the column tiles w, w + 4, ... over all
+// the workgroup's points and writes part[block][co][kc] for co < COUT,
+// kc < NKC.
+constexpr int kWgradRch = 32;
+
+template <int CIN>
+__device__ __forceinline__ void wgrad_store_plane(__bf16* slot, const uint4 (&reg)[ConvChunk<CIN>::per_thread])
+{
+    using C = ConvChunk<CIN>;
+#pragma unroll
+    for (int q = 0; q < C::per_thread; ++q) {
+        const int c = threadIdx.x + 256 * q;
+        if (c < C::count) {
+            const int cell = c / C::per_cell, c0 = 8 * (c % C::per_cell);
+            const __bf16* v = (const __bf16*)&reg[q];
+#pragma unroll
+            for (int h = 0; h < 8; ++h) slot[(c0 + h) * kConvPlane + cell] = v[h];
+        }
+    }
+}
+
 template <int CIN, int COUT, bool BIAS>
-__global__ __launch_bounds__(256) void k_wgrad(NNGrid gd, long PB, const __bf16* X, const __bf16* G,
+__global__ __launch_bounds__(256) void k_wgrad(NNGrid gd, const __bf16* X, const __bf16* G,
                                                float* part)
 {
-    const int nr = gd.nr, nt = gd.nt, np = gd.np, per = gd.per;
     constexpr int NKC = 27 * CIN + (BIAS ? 1 : 0);
     constexpr int NTILE = (NKC + 15) / 16;
     constexpr int TPW = (NTILE + 3) / 4;  // column tiles per wave
-    const long N = (long)gd.nlev * nt * np;
+    constexpr int SLOT = kConvPlane * CIN;
+    constexpr int GCH = COUT == 16 ? 2 : 1;  // 16-byte chunks of G per point (COUT == 1: one value)
+    __shared__ __align__(16) __bf16 sx[4 * SLOT];
+    __shared__ __align__(16) __bf16 sg[COUT * 256];
+    const int nr = gd.nr, nt = gd.nt, np = gd.np;
+    const int ntk = (np + kConvT - 1) / kConvT, ntj = (nt + kConvT - 1) / kConvT;
+    const int nrc = (nr + kWgradRch - 1) / kWgradRch;
+    int L = blockIdx.x;
+    const int tk = L % ntk;
+    L /= ntk;
+    const int tj = L % ntj;
+    L /= ntj;
+    const int rc = L % nrc, e = L / nrc;
+    const int k0 = tk * kConvT, j0 = tj * kConvT;
+    const int i0 = rc * kWgradRch, i1 = min(nr, i0 + kWgradRch);
+    const long ebase = (long)e * nr;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int n = lane & 15, g = lane >> 4;
     f32x4 acc[TPW];
 #pragma unroll
     for (int q = 0; q < TPW; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const long pbeg = (long)blockIdx.x * PB;
-    for (long pg = pbeg; pg < pbeg + PB && pg < N; pg += 32) {
-        // A = G^T: row co = n, points pg + 8g + q
-        bf16x8 a;
-        long pts[8];
+    uint4 reg[ConvChunk<CIN>::per_thread];
+    conv_load_plane<CIN>(gd, X, ebase, i0 - 1, j0, k0, reg);
+    wgrad_store_plane<CIN>(sx + ((i0 + 3) & 3) * SLOT, reg);
+    conv_load_plane<CIN>(gd, X, ebase, i0, j0, k0, reg);
+    wgrad_store_plane<CIN>(sx + ((i0 + 4) & 3) * SLOT, reg);
+    conv_load_plane<CIN>(gd, X, ebase, i0 + 1, j0, k0, reg);
+    for (int lv = i0; lv < i1; ++lv) {
+        // G of this level's tile points: chunk c of point pt = c / GCH
+        uint4 gr[GCH];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const long p = pg + 8 * g + q;
-            pts[q] = p < N ? p : -1;
-            a[q] = (p < N && n < COUT) ? G[p * COUT + n] : (__bf16)0.0f;
-        }
-        int II[8], ii[8], jj[8], kk[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const long p = pts[q] < 0 ? 0 : pts[q];
-            kk[q] = (int)(p % np);
-            const long t1 = p / np;
-            jj[q] = (int)(t1 % nt);
-            II[q] = (int)(t1 / nt);
-            ii[q] = II[q] % nr;
-        }
-#pragma unroll
-        for (int tq = 0; tq < TPW; ++tq) {
-            const int tile = wv + 4 * tq;
-            if (tile >= NTILE) break;
-            const int kc = tile * 16 + n;
-            bf16x8 b;
-            const int t = kc / CIN, ci = kc % CIN;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                float v = 0.0f;
-                if (pts[q] >= 0) {
-                    if (kc < 27 * CIN) {
-                        const long nbq = nb_index(II[q], ii[q], jj[q], kk[q], t, nr, nt, np, per);
-                        v = nbq >= 0 ? (float)X[nbq * CIN + ci] : 0.0f;
-                    } else if (BIAS && kc == 27 * CIN) {
-                        v = 1.0f;
-                    }
-                }
-                b[q] = (__bf16)v;
+        for (int q = 0; q < GCH; ++q) {
+            const int c = threadIdx.x + 256 * q, pt = c / GCH;
+            const int j = j0 + pt / kConvT, k = k0 + pt % kConvT;
+            uint4 v = {0u, 0u, 0u, 0u};
+            if (j < nt && k < np) {
+                const long p = ((ebase + lv) * nt + j) * np + k;
+                if constexpr (COUT == 16) v = *(const uint4*)(G + p * 16 + 8 * (c % GCH));
+                else v.x = (unsigned)*(const unsigned short*)(G + p);
             }
-            acc[tq] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[tq], 0, 0, 0);
+            gr[q] = v;
+        }
+        __syncthreads();  // the previous level's reads of sg are done
+        wgrad_store_plane<CIN>(sx + ((lv + 5) & 3) * SLOT, reg);
+#pragma unroll
+        for (int q = 0; q < GCH; ++q) {
+            const int c = threadIdx.x + 256 * q, pt = c / GCH;
+            if constexpr (COUT == 16) {
+                const int c0 = 8 * (c % GCH);
+                const __bf16* v = (const __bf16*)&gr[q];
+#pragma unroll
+                for (int h = 0; h < 8; ++h) sg[(c0 + h) * 256 + pt] = v[h];
+            } else {
+                *(unsigned short*)(sg + pt) = (unsigned short)gr[q].x;
+            }
+        }
+        if (lv + 2 <= i1) conv_load_plane<CIN>(gd, X, ebase, lv + 2, j0, k0, reg);
+        __syncthreads();
+#pragma unroll 1
+        for (int ch = 0; ch < 8; ++ch) {
+            // A = G^T: row co = n, points 32 ch + 8 g .. + 7
+            const bf16x8 a = n < COUT ? *(const bf16x8*)(sg + n * 256 + 32 * ch + 8 * g) : zero8();
+            const int row = 2 * ch + (g >> 1), col0 = 8 * (g & 1);
+#pragma unroll
+            for (int tq = 0; tq < TPW; ++tq) {
+                const int tile = wv + 4 * tq;
+                if (tile >= NTILE) break;
+                const int kc = tile * 16 + n;
+                bf16x8 b;
+                if (kc < 27 * CIN) {
+                    const int t = kc / CIN, ci = kc % CIN;
+                    const int di = t / 9 - 1, dj = (t / 3) % 3 - 1, dk = t % 3 - 1;
+                    const __bf16* s = sx + ((lv + 4 + di) & 3) * SLOT + ci * kConvPlane +
+                                      (row + 1 + dj) * kConvH + (col0 + 1 + dk);
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) b[q] = s[q];
+                } else {
+                    const __bf16 one = (BIAS && kc == 27 * CIN) ? (__bf16)1.0f : (__bf16)0.0f;
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) b[q] = one;
+                }
+                acc[tq] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[tq], 0, 0, 0);
+            }
         }
     }
     float* pb = part + (size_t)blockIdx.x * COUT * NKC;
@@ -373,7 +433,6 @@ __global__ __launch_bounds__(256) void k_wgrad(NNGrid gd, long PB, const __bf16*
 // The partials are summed in a fixed order in two passes: segment s of
 // kWgradSeg consecutive blocks into row s of part2, then the rows of part2
 // in order into grad[layer offsets].
-constexpr int kWgradBlocks = 2048;  // most blocks of one weight-gradient launch
 constexpr int kWgradSeg = 64;       // blocks per first-pass segment
 
 __global__ void k_wgrad_seg(const float* part, int nblk, int ncol, float* part2)
@@ -403,14 +462,15 @@ __global__ void k_wgrad_reduce(const float* part, int nblk, int cout, int cin, i
     }
 }
 
-static int wgrad_blocks(long npoints)
+static int wgrad_blocks(int nb, int nr, int nt, int np)
 {
-    return (int)std::min<long>(kWgradBlocks, (npoints + 1023) / 1024);
+    return ((np + kConvT - 1) / kConvT) * ((nt + kConvT - 1) / kConvT) *
+           ((nr + kWgradRch - 1) / kWgradRch) * nb;
 }
 
-int nn_wgrad_partials(long npoints)
+int nn_wgrad_partials(int nb, int nr, int nt, int np)
 {
-    const int nblk = wgrad_blocks(npoints);
+    const int nblk = wgrad_blocks(nb, nr, nt, np);
     return nblk + (nblk + kWgradSeg - 1) / kWgradSeg;
 }
 
@@ -418,20 +478,17 @@ void launch_nn_wgrad(int layer, int nb, int nr, int nt, int np, int per, const _
                      const __bf16* G, float* part, float* grad, hipStream_t s)
 {
     const NNGrid gd{nb * nr, nr, nt, np, per};
-    const long N = (long)nb * nr * nt * np;
-    const int nblk = wgrad_blocks(N);
-    // points per block: a multiple of the 32 points one step takes
-    const long PB = ((N + nblk - 1) / nblk + 31) / 32 * 32;
+    const int nblk = wgrad_blocks(nb, nr, nt, np);
     const int nseg = (nblk + kWgradSeg - 1) / kWgradSeg;
     const int cin = layer == 1 ? 8 : 16, cout = layer == 3 ? 1 : 16, bias = layer == 3 ? 0 : 1;
     const int ncol = cout * (27 * cin + bias);
     float* part2 = part + (size_t)nblk * ncol;
     if (layer == 1)
-        hipLaunchKernelGGL((k_wgrad<8, 16, true>), dim3(nblk), dim3(256), 0, s, gd, PB, X, G, part);
+        hipLaunchKernelGGL((k_wgrad<8, 16, true>), dim3(nblk), dim3(256), 0, s, gd, X, G, part);
     else if (layer == 2)
-        hipLaunchKernelGGL((k_wgrad<16, 16, true>), dim3(nblk), dim3(256), 0, s, gd, PB, X, G, part);
+        hipLaunchKernelGGL((k_wgrad<16, 16, true>), dim3(nblk), dim3(256), 0, s, gd, X, G, part);
     else
-        hipLaunchKernelGGL((k_wgrad<16, 1, false>), dim3(nblk), dim3(256), 0, s, gd, PB, X, G, part);
+        hipLaunchKernelGGL((k_wgrad<16, 1, false>), dim3(nblk), dim3(256), 0, s, gd, X, G, part);
     hipLaunchKernelGGL(k_wgrad_seg, dim3((ncol + 255) / 256, nseg), dim3(256), 0, s, part, nblk,
                        ncol, part2);
     hipLaunchKernelGGL(k_wgrad_reduce, dim3((ncol + 255) / 256), dim3(256), 0, s, part2, nseg,

@@ -275,3 +275,28 @@ def test_corrupted_weights_still_converge(dev, oracle_mod):
     xl, sl, dt = _solve(dev, held, theta, "learned")
     _log("  corrupted: iters", sl["iters_total"], "fallbacks", sl["fallbacks"])
     assert true_residual(o, held, xl, dt) <= 1.001e-10
+
+
+@pytest.mark.timeout(600)
+def test_learned_solve_full_size(dev, oracle_mod):
+    """The transition-region conduction problem at the benchmark's size
+    (151 x 301 x 400): trained on seed 401 with the default recipe, the
+    learned FCG(1) solve of the held-out seed 402 (one BE step of 50 dt_E)
+    reaches the same FP64 true residual as Jacobi PCG, evaluated with the
+    oracle's operator.  The iteration counts are reported, not asserted:
+    the network does not lower them (the measured negative result)."""
+    prob = inputs.transition_region(151, 301, 400, seed=401)
+    g, dt, rep = _train(dev, prob)
+    _log("  full-size training", rep)
+    theta = g.lpc_get_weights()
+    assert np.all(np.isfinite(theta)) and rep["loss_last"] < rep["loss_first"]
+    del g
+    held = inputs.transition_region(151, 301, 400, seed=402)
+    o = oracle_mod.Oracle.from_problem(held)
+    xj, sj, dt = _solve(dev, held, None, "jacobi")
+    xl, sl, _ = _solve(dev, held, theta, "learned")
+    rj, rl = true_residual(o, held, xj, dt), true_residual(o, held, xl, dt)
+    _log("  full-size held-out: iterations jacobi", sj["iters_total"], "learned", sl["iters_total"],
+         "fallbacks", sl["fallbacks"], "true residual", rj, rl)
+    assert sl["status"] == dev.PA_OK and sj["status"] == dev.PA_OK
+    assert rl <= 1.001e-10 and rj <= 1.001e-10
