@@ -273,21 +273,23 @@ class Oracle:
 
     def set_pc(self, pc="jacobi", block=(8, 4, 16)):
         """Preconditioner of the BE solves: point Jacobi (PC1) or block ILU(0)
-        (PC2) on boxes of block = (r, theta, phi) cells (7-point operator)."""
+        (PC2) on boxes of block = (r, theta, phi) cells (7-point and
+        field-aligned operators)."""
         if _load().or_set_pc(self._h, PCS[pc], *[int(b) for b in block]):
-            raise ValueError("block ILU(0) needs the 7-point operator and a positive box")
+            raise ValueError("block ILU(0) needs a scalar operator and a positive box")
 
     def bilu0_csr(self, dt):
         """(rowp, col, m0, lu): the block-diagonal part of M = wV + dt L in CSR
         (columns ascending) and its ILU(0) factors in the same pattern (strict
         lower part: L with unit diagonal implied; diagonal and upper: U)."""
         n = self.nr * self.nt * self.np
+        w = 27 * n  # the field-aligned operator couples 3 x 3 x 3 neighbourhoods
         rowp = np.zeros(n + 1, dtype=np.intc)
-        col = np.zeros(7 * n, dtype=np.intc)
-        m0, lu = np.zeros(7 * n), np.zeros(7 * n)
+        col = np.zeros(w, dtype=np.intc)
+        m0, lu = np.zeros(w), np.zeros(w)
         ip = ctypes.POINTER(ctypes.c_int)
         nnz = _load().or_bilu0_export(self._h, float(dt), rowp.ctypes.data_as(ip),
-                                      col.ctypes.data_as(ip), _ptr(m0), _ptr(lu), 7 * n)
+                                      col.ctypes.data_as(ip), _ptr(m0), _ptr(lu), w)
         if nnz < 0:
             raise ValueError("block ILU(0) export failed (%d)" % nnz)
         return rowp, col[:nnz], m0[:nnz], lu[:nnz]

@@ -839,7 +839,10 @@ static void sts_cycle(or_ctx* o, double* u, double dt, int kind, int s)
  * block-diagonal part of M = wV + dt L (every coupling between cells of
  * different boxes dropped).  The periodic phi coupling between k = np-1 and
  * k = 0 is always dropped, also when both cells lie in one box, so that each
- * box is a plain sub-grid.  Implemented for the 7-point operator. */
+ * box is a plain sub-grid.  Implemented for the 7-point operator and for the
+ * field-aligned operator (whose sparsity is each cell's 3 x 3 x 3
+ * neighbourhood: the cells sharing a corner with it); "the sparsity of M"
+ * is its nonzero entries. */
 
 #define OR_PC_JACOBI 0
 #define OR_PC_BILU0 2
@@ -921,6 +924,88 @@ static int bilu0_assemble(const or_ctx* o, double dt, or_csr* A)
     return 0;
 }
 
+/* Colours of the longitude index for reading the field-aligned operator by
+ * probes: any three cyclically consecutive k get distinct colours. */
+static int kcolours(int np) { return np % 3 == 0 ? 3 : np % 4 == 0 ? 4 : np % 5 == 0 ? 5 : np; }
+
+/* The block-diagonal part of M = wV + dt L for the field-aligned operator,
+ * read from the operator itself: with the cells coloured by (i mod 3,
+ * j mod 3, k mod kcolours(np)), a cell has at most one cell of each colour
+ * in its neighbourhood (phi wrap included), so (L x)_m for x the indicator
+ * of one colour (linear mode, L x = -wV F) is L_mn for the neighbour n of m
+ * of that colour (the diagonal is taken from or_diag, as the Jacobi
+ * preconditioner has it).  Entries are stored in ascending column order;
+ * exact zeros off the diagonal are not part of the sparsity. */
+static int bilu0_assemble_aligned(const or_ctx* oc, double dt, or_csr* A)
+{
+    or_ctx* o = (or_ctx*)oc;   /* the apply uses the context's corner buffer */
+    const int nr = o->nr, nt = o->nt, np = o->np, nk = kcolours(np);
+    const int n = (int)ncell(o);
+    double* Lc = (double*)calloc((size_t)27 * n, sizeof(double));
+    double* x = (double*)malloc((size_t)n * sizeof(double));
+    double* F = (double*)malloc((size_t)n * sizeof(double));
+    for (int ci = 0; ci < 3; ++ci)
+        for (int cj = 0; cj < 3; ++cj)
+            for (int ck = 0; ck < nk; ++ck) {
+#pragma omp parallel for schedule(static)
+                for (int i = 0; i < nr; ++i)
+                    for (int j = 0; j < nt; ++j)
+                        for (int k = 0; k < np; ++k)
+                            x[cell_ix(o, 0, i, j, k)] =
+                                (i % 3 == ci && j % 3 == cj && k % nk == ck) ? 1.0 : 0.0;
+                apply_aligned(o, 0, x, F, 0);
+#pragma omp parallel for schedule(static)
+                for (int i = 0; i < nr; ++i)
+                    for (int j = 0; j < nt; ++j)
+                        for (int k = 0; k < np; ++k) {
+                            const size_t m = cell_ix(o, 0, i, j, k);
+                            const double Lm = -F[m] * wvol(o, i, j, k);
+                            for (int t = 0; t < 27; ++t) {
+                                const int i2 = i + t / 9 - 1, j2 = j + (t / 3) % 3 - 1;
+                                const int k2 = (k + t % 3 - 1 + np) % np;
+                                if (i2 < 0 || i2 >= nr || j2 < 0 || j2 >= nt) continue;
+                                if (i2 % 3 == ci && j2 % 3 == cj && k2 % nk == ck)
+                                    Lc[27 * m + t] = Lm;
+                            }
+                        }
+            }
+    free(x);
+    free(F);
+    double* Ld = (double*)malloc((size_t)n * sizeof(double));
+    or_diag(o, Ld);   /* the diagonal as the Jacobi preconditioner has it */
+    A->n = n;
+    A->rowp = (int*)malloc((size_t)(n + 1) * sizeof(int));
+    A->col = (int*)malloc((size_t)27 * n * sizeof(int));
+    A->m0 = (double*)malloc((size_t)27 * n * sizeof(double));
+    A->lu = (double*)malloc((size_t)27 * n * sizeof(double));
+    A->dpos = (int*)malloc((size_t)n * sizeof(int));
+    int q = 0;
+    for (int i = 0; i < nr; ++i)
+        for (int j = 0; j < nt; ++j)
+            for (int k = 0; k < np; ++k) {
+                const int m = (int)cell_ix(o, 0, i, j, k);
+                A->rowp[m] = q;
+                /* offsets in (di, dj, dk) order are columns in ascending order */
+                for (int t = 0; t < 27; ++t) {
+                    const int i2 = i + t / 9 - 1, j2 = j + (t / 3) % 3 - 1, k2 = k + t % 3 - 1;
+                    if (i2 < 0 || i2 >= nr || j2 < 0 || j2 >= nt || k2 < 0 || k2 >= np) continue;
+                    if (!same_box(o, i, j, k, i2, j2, k2)) continue;
+                    const double v = (t == 13) ? wvol(o, i, j, k) + dt * Ld[m]
+                                               : dt * Lc[27 * (size_t)m + t];
+                    if (t != 13 && v == 0.0) continue;
+                    if (t == 13) A->dpos[m] = q;
+                    A->col[q] = (int)cell_ix(o, 0, i2, j2, k2);
+                    A->m0[q] = v;
+                    A->lu[q] = v;
+                    ++q;
+                }
+            }
+    A->rowp[n] = q;
+    free(Lc);
+    free(Ld);
+    return 0;
+}
+
 /* ILU(0) in place on A->lu, IKJ order: for each row i and each k < i in the
  * row, l_ik = a_ik / u_kk, then a_ij -= l_ik u_kj for the j > k of row k
  * that are in the pattern of row i.  7 (not factorable) on a pivot that is
@@ -952,7 +1037,7 @@ static int bilu0_factor(or_csr* A)
 
 static int bilu0_make(const or_ctx* o, double dt, or_csr* A)
 {
-    int e = bilu0_assemble(o, dt, A);
+    int e = o->op == OR_ALIGNED ? bilu0_assemble_aligned(o, dt, A) : bilu0_assemble(o, dt, A);
     if (!e) e = bilu0_factor(A);
     return e;
 }
@@ -989,7 +1074,7 @@ static void precondition(const or_ctx* o, const or_csr* F, const double* D, cons
 int or_set_pc(or_ctx* o, int pc, int bi, int bj, int bk)
 {
     if (pc == OR_PC_JACOBI) { o->pcond = pc; return 0; }
-    if (pc != OR_PC_BILU0 || o->op != OR_ISO7 || bi < 1 || bj < 1 || bk < 1) return 1;
+    if (pc != OR_PC_BILU0 || o->op == OR_VISCV || bi < 1 || bj < 1 || bk < 1) return 1;
     o->pcond = pc;
     o->pbi = bi; o->pbj = bj; o->pbk = bk;
     return 0;
