@@ -1,8 +1,8 @@
 """The four PTL-cycled advances of the 151 x 301 x 400 benchmark step, run
 exactly as the benchmark runs them (default options, dt = 50 dt_E of each
 operator, tol 1e-10; the viscosity in its vector form), against the oracle
-on the same inputs; and the same
-advances with FP32 stages / FP32 matvecs against the oracle's FP64 result.
+on the same inputs; the same advances with FP32 stages / FP32 matvecs
+against the oracle's FP64 result; and the benchmark's unfloored RKL2 leg.
 
 Bars:
 * STS (Sec. 3.1, App. A): identical cycle schedules (every cycle length to
@@ -208,6 +208,31 @@ def test_rkl2_ptl_cycled(dev, probs, oruns, name):
     uo, so = oracle_for(oruns, name, "rkl2", st, so, dt)
     err = rel_l2(ug, uo)
     _log(f"rkl2 {name}: rel L2 {err:.3e}")
+    assert err <= 1e-12
+
+
+@pytest.mark.parametrize("name", ["conduction", "viscosity"])
+def test_rkl2_unfloored(dev, oracle_mod, probs, oruns, name):
+    """The benchmark's unfloored leg: RKL2 cycled at the paper's limit
+    without the floor of dt_E (ptl_floor = 0), as bench.py runs it, against
+    the oracle replaying the GPU's schedule (every cycle length the oracle's
+    own decision to 1e-12, except where the limit is ill-conditioned: a
+    flattened limiting pair), no cycle floored, fields to 1e-12."""
+    from ptl_follow import replay_unfloored
+    prob = probs[name]
+    g = dev.Operator.from_problem(prob)
+    dt = 50.0 * g.dt_explicit()
+    g.set_options(ptl_floor=0.0, max_cycles=20000)
+    u = g.bind(prob.u)
+    st = g.advance_rkl2(dt, 0)
+    ug = u.cpu().numpy()
+    del g, u
+    _log(f"unfloored rkl2 {name}: cycles {st['cycles']}, stages {st['s_total']}")
+    assert st["floored"] == 0
+    uo, ill = replay_unfloored(oracle_mod, oruns.oracle(name), prob.u, dt, st, log=_log)
+    _log(f"unfloored rkl2 {name}: ill-conditioned cycles {ill}")
+    err = rel_l2(ug, uo)
+    _log(f"unfloored rkl2 {name}: rel L2 {err:.3e}")
     assert err <= 1e-12
 
 

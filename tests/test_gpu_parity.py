@@ -136,6 +136,31 @@ def test_sts_advance(dev, oracle_mod, shape, op, nc, kind):
         assert rel_l2(u.cpu().numpy(), uo) <= REL, (cycles, ratio, s_ovr)
 
 
+@pytest.mark.parametrize("shape", [(9, 10, 13), (17, 24, 40)])
+@pytest.mark.parametrize("op,nc", CASES)
+@pytest.mark.parametrize("kind", ["rkl2", "rkg2"])
+def test_sts_advance_unfloored(dev, oracle_mod, shape, op, nc, kind):
+    """PTL cycling at the paper's limit without the floor of dt_E (ptl_floor
+    = 0; Eqs. (ptl)-(ptl3) as printed), against the oracle replaying the
+    GPU's schedule: every cycle length the oracle's own decision (1e-12)
+    except where the limit is ill-conditioned (a flattened limiting pair),
+    no cycle floored, fields to 1e-12."""
+    from ptl_follow import replay_unfloored
+    _log("sts unfloored", shape, op, nc, kind)
+    prob = problem(op, shape, ncomp=nc)
+    g, o = pair(dev, oracle_mod, prob)
+    dt = 50.0 * o.dt_explicit()
+    g.set_options(ptl_floor=0.0, max_cycles=20000)
+    u = g.bind(prob.u)
+    st = g.advance_sts(dt, 0, sts=kind)
+    _log("  cycles", st["cycles"], "stages", st["s_total"], "dt_ptl_min / dt_E",
+         st["dt_ptl_min"] / o.dt_explicit())
+    assert st["floored"] == 0
+    uo, ill = replay_unfloored(oracle_mod, o, prob.u, dt, st, sts=kind, log=_log)
+    _log("  ill-conditioned cycles", ill)
+    assert rel_l2(u.cpu().numpy(), uo) <= REL
+
+
 def be_true_residual(o, prob, x, dt):
     """||b - M x|| / ||b|| with the oracle's operator: M = V + dt L,
     b = V u^n + dt V F(0)."""
