@@ -90,8 +90,8 @@ class OracleRuns:
             o = self.oracle(name)
             u = self.probs[name].u
             _log(f"oracle: {kind} {name}")
-            if kind == "rkl2":
-                self.res[key] = o.advance_sts(u, dt, 0, "rkl2")
+            if kind in ("rkl2", "rkg2"):
+                self.res[key] = o.advance_sts(u, dt, 0, kind)
             else:
                 self.res[key] = o.advance_be(u, dt, TOL, 0)
         return self.res[key]
@@ -118,7 +118,7 @@ def parted_on_near_tie(o, kind, u0, st, so, dt):
     u = u0
     if c0:
         pre = dg[:c0]
-        u, _ = (o.advance_sts(u0, pre.sum(), 0, "rkl2", replay=pre) if kind == "rkl2"
+        u, _ = (o.advance_sts(u0, pre.sum(), 0, kind, replay=pre) if kind != "be"
                 else o.advance_be(u0, pre.sum(), TOL, 0, replay=pre))
     t_rem = dt - dg[:c0].sum()
     x = t_rem / max(o.ptl(u)[0], o.dt_explicit())
@@ -129,21 +129,23 @@ def follow_gpu(om, o, kind, u0, st):
     """The oracle taking the GPU's decisions cycle by cycle (its cycle
     lengths, and its stage or iteration count per cycle).  Each count that
     differs from the oracle's own must be a genuine near-tie: the stage
-    formula's ceiling argument (sqrt(9 + 16 dt_c/dt_E) - 1)/2 within 1e-12
-    of an integer, or the oracle's residual at the earlier stopping count
-    within 1e-12 of tol (both sides' residuals agree to ~1e-15 of ||b||)."""
+    formula giving the GPU's count for dt_c/dt_E moved by 1e-12 relative
+    (for RKL2 its ceiling argument (sqrt(9 + 16 dt_c/dt_E) - 1)/2 within
+    1e-12 of an integer), or the oracle's residual at the earlier stopping
+    count within 1e-12 of tol (both sides' residuals agree to ~1e-15 of
+    ||b||)."""
     dtE = o.dt_explicit()
     u, flips = u0, 0
     for dtc, n in zip(np.asarray(st["dt_cycle"]), np.asarray(st["per_cycle"])):
         n = int(n)
-        if kind == "rkl2":
-            own = om.sts_stages("rkl2", dtc / dtE)
+        if kind != "be":
+            own = om.sts_stages(kind, dtc / dtE)
             if own != n:
-                x = 0.5 * (math.sqrt(9.0 + 16.0 * dtc / dtE) - 1.0)
-                _log(f"  stage count {n} against the oracle's {own}: argument {x!r}")
-                assert abs(x - round(x)) <= 1e-12 * x, x
+                near = {om.sts_stages(kind, dtc / dtE * (1.0 + e)) for e in (-1e-12, 1e-12)}
+                _log(f"  stage count {n} against the oracle's {own} (counts within 1e-12: {near})")
+                assert n in near, (n, own, dtc / dtE)
                 flips += 1
-            u, _ = o.advance_sts(u, dtc, 1, "rkl2", s_override=n)
+            u, _ = o.advance_sts(u, dtc, 1, kind, s_override=n)
         else:
             uf, sf = o.advance_be(u, dtc, TOL, 1)
             if sf["iters_total"] == n:
@@ -193,21 +195,23 @@ def gpu_advance(dev, prob, kind, prec="fp64"):
     g = dev.Operator.from_problem(prob, prec=prec)
     dt = 50.0 * g.dt_explicit()
     u = g.bind(prob.u)
-    st = g.advance_rkl2(dt, 0) if kind == "rkl2" else g.advance_be(dt, TOL, 0)
+    st = g.advance_sts(dt, 0, sts=kind) if kind != "be" else g.advance_be(dt, TOL, 0)
     out = u.cpu().numpy()
     del g, u
     return out, st, dt
 
 
+@pytest.mark.parametrize("kind", ["rkl2", "rkg2"])
 @pytest.mark.parametrize("name", ["conduction", "viscosity"])
-def test_rkl2_ptl_cycled(dev, probs, oruns, name):
+def test_sts_ptl_cycled(dev, probs, oruns, name, kind):
+    """RKL2 (the timed step) and RKG2 (the benchmark's RKG2-against-BE leg)."""
     prob = probs[name]
-    ug, st, dt = gpu_advance(dev, prob, "rkl2")
-    uo, so = oruns.run(name, "rkl2", dt)
-    _log(f"rkl2 {name}: cycles {st['cycles']}/{so['cycles']}, stages {st['s_total']}/{so['s_total']}")
-    uo, so = oracle_for(oruns, name, "rkl2", st, so, dt)
+    ug, st, dt = gpu_advance(dev, prob, kind)
+    uo, so = oruns.run(name, kind, dt)
+    _log(f"{kind} {name}: cycles {st['cycles']}/{so['cycles']}, stages {st['s_total']}/{so['s_total']}")
+    uo, so = oracle_for(oruns, name, kind, st, so, dt)
     err = rel_l2(ug, uo)
-    _log(f"rkl2 {name}: rel L2 {err:.3e}")
+    _log(f"{kind} {name}: rel L2 {err:.3e}")
     assert err <= 1e-12
 
 
