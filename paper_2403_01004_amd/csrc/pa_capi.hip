@@ -14,8 +14,22 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/paradv.h"
 #include "pa_internal.h"
+
+// A host-side range in rocprofv3's marker trace (--marker-trace): the
+// entry points and each PTL cycle, so a trace shows where the advance's
+// launches were enqueued
+namespace {
+struct Range {
+    explicit Range(const char* name) { roctxRangePush(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range&) = delete;
+    Range& operator=(const Range&) = delete;
+};
+}  // namespace
 
 using namespace pa;
 
@@ -819,6 +833,7 @@ pa_status pa_apply(pa_ctx* c, const double* u, double* F, int32_t affine)
 
 pa_status pa_compute_ptl(pa_ctx* c, double* dt, int64_t* k)
 {
+    Range range("pa_compute_ptl");
     if (!c) return PA_ERR_ARG;
     if (!dt) return fail(c, PA_ERR_ARG, "null output");
     if (!c->have_coef) return fail(c, PA_ERR_STATE, "coefficients not set");
@@ -841,6 +856,7 @@ pa_status pa_compute_ptl(pa_ctx* c, double* dt, int64_t* k)
 
 pa_status pa_compute_ptl_full(pa_ctx* c, double* dt, int64_t* k)
 {
+    Range range("pa_compute_ptl_full");
     if (!c) return PA_ERR_ARG;
     if (!dt) return fail(c, PA_ERR_ARG, "null output");
     if (!c->have_coef) return fail(c, PA_ERR_STATE, "coefficients not set");
@@ -1040,6 +1056,7 @@ pa_status sts_advance(pa_ctx* c, int kind, double dt, int cycles, pa_stats* st, 
     int ncyc = 0;
     pa_status s = PA_OK;
     while (true) {
+        Range cyc("pa sts cycle");
         first_pass<T>(c, u0, y0);
         double dtc;
         int last;
@@ -1061,6 +1078,7 @@ pa_status sts_advance(pa_ctx* c, int kind, double dt, int cycles, pa_stats* st, 
 
 pa_status advance_sts(pa_ctx* c, int kind, double dt, int32_t cycles, pa_stats* user)
 {
+    Range range(kind == PA_STS_RKL2 ? "pa_advance_rkl2" : "pa_advance_rkg2");
     if (!c) return PA_ERR_ARG;
     pa_status s = check_ready(c, dt);
     if (s) return s;
@@ -1534,6 +1552,7 @@ extern "C" {
 
 pa_status pa_advance_be_pcg(pa_ctx* c, double dt, double tol, int32_t cycles, pa_stats* user)
 {
+    Range range("pa_advance_be_pcg");
     if (!c) return PA_ERR_ARG;
     pa_status s = check_ready(c, dt);
     if (s) return s;
@@ -1567,6 +1586,7 @@ pa_status pa_advance_be_pcg(pa_ctx* c, double dt, double tol, int32_t cycles, pa
     double t_rem = dt;
     int ncyc = 0;
     while (true) {
+        Range cyc("pa be cycle");
         first_pass<double>(c, c->u, y0);
         double dtc;
         int last;
@@ -1874,6 +1894,7 @@ pa_status pa_lpc_loss_grad(pa_ctx* c, double dt, int32_t npairs, const double* r
 
 pa_status pa_lpc_train(pa_ctx* c, double dt, const pa_lpc_train_opts* oin, pa_lpc_report* rep)
 {
+    Range range("pa_lpc_train");
     if (!c) return PA_ERR_ARG;
     pa_lpc_train_opts o;
     if (oin) o = *oin;
