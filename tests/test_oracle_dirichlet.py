@@ -132,7 +132,7 @@ def run_checks(oracle_mod):
     return out
 
 
-def verdicts(res):
+def outcomes(res):
     """Which pins a result set passes (the bars of the tests below)."""
     return {
         "linear_iso7": res["linear_iso7"] <= 1e-12,
@@ -199,7 +199,7 @@ def test_planted_closure_mistakes_fail(tmp_path):
         (d / "oracle" / "oracle.c").write_text(src.replace(old, new))
         out = subprocess.run([sys.executable, __file__, str(d)], capture_output=True, text=True,
                              timeout=600, check=True).stdout
-        ok = verdicts(json.loads(out.strip().splitlines()[-1]))
+        ok = outcomes(json.loads(out.strip().splitlines()[-1]))
         assert sum(not v for v in ok.values()) >= 2, (name, ok)
 
 
