@@ -38,6 +38,7 @@ constexpr int HN = HX * HY;              // 340 plane slots
 constexpr int NHALO = HN - TX * TY;      // 84 halo slots
 constexpr int CX = TX + 1, CY = TY + 1;  // corners of a tile plane
 constexpr int NCOR = CX * CY;            // 297
+static_assert(TX * TY == kBlock, "a tile is one workgroup's cells");
 
 __device__ __forceinline__ int xcd_tile()
 {
@@ -1070,8 +1071,9 @@ static void go_iso7(const Geo<T>& g, const KArgs<T>& a, hipStream_t s)
 {
     const int nt = a.nbx * a.nrc * a.nc;
     if (a.rch > RCH_MAX) return;  // the host never asks for longer chunks
-    const dim3 gr(grid_for_tiles(nt)), bl(64 * W7);
+    const dim3 gr(grid_for_tiles(nt));
     if constexpr (iso7_tiled<T>()) {
+        const dim3 bl(kBlock);  // one workgroup per tile
         if (a.coef) {
             if (a.wgt) hipLaunchKernelGGL((k_iso7t<T, MODE, VIRT, true, true>), gr, bl, 0, s, g, a);
             else hipLaunchKernelGGL((k_iso7t<T, MODE, VIRT, true, false>), gr, bl, 0, s, g, a);
@@ -1081,6 +1083,7 @@ static void go_iso7(const Geo<T>& g, const KArgs<T>& a, hipStream_t s)
         }
         return;
     }
+    const dim3 bl(64 * W7);
     if (a.coef) {
         if (a.wgt) hipLaunchKernelGGL((k_iso7<T, MODE, VIRT, true, true>), gr, bl, 0, s, g, a);
         else hipLaunchKernelGGL((k_iso7<T, MODE, VIRT, true, false>), gr, bl, 0, s, g, a);
