@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Gpts/s per stage & s per PTL-cycled advance; HBM roofline %; PCG iters vs Jacobi"
 HBM_PEAK_GBS = 8000.0
+XGROUP = 8                    # PCG iterations per x update of the FP64 point-Jacobi solves (PA_PCG_XGROUP)
 COPY_ELEMS = 1 << 27          # 1 GiB of FP64 read and 1 GiB written
 WORKLOAD = "spherical shell 151x301x400 (18.2M cells): field-aligned conduction + vector viscosity (3 spherical components), PTL-cycled RKL2 and BE+Jacobi-PCG at dt = 50 dt_E"
 
@@ -55,21 +56,29 @@ def bytes_per_launch(op, ncomp, cls, N, NCO, coef_var, stage_k=None, word=8):
     if cls == "update":
         return 3 * f + 8 * N    # r, q, D read; r written
     if cls == "dir":
-        return 5 * f + 8 * N    # r, p, x, D read; p, x written
-    if cls == "dir_last":
-        return 3 * f            # the iteration that stops a solve: x, p read; x written
+        return 3 * f + 8 * N    # r, p, D read; the next direction written
+    if cls == "xgroup":
+        return 2 * f            # x read and written once per group (plus its directions)
     if cls == "init":
         return 4 * f + 16 * N   # u, y0, diag L read; r, p, D written
     return 0
 
 
-def dir_saving(op, ncomp, N, NCO, per_cycle):
-    """Bytes the direction launches of a BE advance move less than
-    iterations x a full launch: the launch of the iteration that stops each
-    solve (every cycle with at least one iteration) only applies x."""
-    nstop = sum(1 for s in per_cycle if int(s) > 0)
-    return nstop * (bytes_per_launch(op, ncomp, "dir", N, NCO, False)
-                    - bytes_per_launch(op, ncomp, "dir_last", N, NCO, False))
+def dir_class_bytes(op, ncomp, N, NCO, per_cycle, group=8):
+    """Bytes of the direction class of an FP64 point-Jacobi BE advance: per
+    solve of n iterations, n - 1 direction launches (the iteration that
+    stops a solve writes no new direction) and the x updates of the groups
+    of `group` iterations (x read and written once per group, each
+    iteration's direction read once)."""
+    f = 8 * N * ncomp
+    tot = 0
+    for n in per_cycle:
+        n = int(n)
+        if n <= 0:
+            continue
+        tot += (n - 1) * bytes_per_launch(op, ncomp, "dir", N, NCO, False)
+        tot += n * f + -(-n // group) * bytes_per_launch(op, ncomp, "xgroup", N, NCO, False)
+    return tot
 
 
 def stage_bytes(op, ncomp, N, NCO, coef_var, per_cycle, word=8):
@@ -208,10 +217,10 @@ def kernel_accounting(s, op, nc, N, NCO, coef_var=False):
                 continue
         if cls == "stage":
             by = stage_bytes(op, nc, N, NCO, coef_var, s["per_cycle"])
+        elif cls == "dir":
+            by = dir_class_bytes(op, nc, N, NCO, s["per_cycle"], XGROUP)
         else:
             by = calls * bytes_per_launch(op, nc, cls, N, NCO, coef_var)
-        if cls == "dir":
-            by -= dir_saving(op, nc, N, NCO, s["per_cycle"])
         out[cls] = [ms, calls, by]
     return out
 

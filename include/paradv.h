@@ -84,6 +84,15 @@ typedef enum { PA_PC_JACOBI = 0, PA_PC_LEARNED = 1, PA_PC_BILU0 = 2 } pa_pc;
 #define PA_BILU0_BJ 4
 #define PA_BILU0_BK 16
 
+/* Backward Euler solves with point Jacobi in FP64 apply the x update of
+ * PA_PCG_XGROUP consecutive PCG iterations together: the group's search
+ * directions stay in their own buffers (PA_PCG_XGROUP - 1 fields of device
+ * memory besides the solve's own, allocated on first use; without them the
+ * solve updates x every iteration), and x is read and written once per
+ * group.  The result is that of one x update per iteration, bit for bit;
+ * the timing class PA_K_DIR counts both kernels (direction, group update). */
+#define PA_PCG_XGROUP 8
+
 #define PA_MAX_LOG 4096
 
 /* Grid and operator description (pa_init).  The face arrays are host

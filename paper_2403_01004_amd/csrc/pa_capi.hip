@@ -157,6 +157,13 @@ struct pa_ctx {
     float* nn_wpart = nullptr;                   // weight-gradient partials
     double* bilu0_ip = nullptr;  // [N] inverse block ILU(0) pivots of the current solve
     int pcg_hint = 0;            // iterations of the last PCG solve (first batch of the next)
+    // deferred x update of the FP64 point-Jacobi solves: the directions of
+    // kXGroup consecutive iterations, x updated once per group
+    bool xg_on = false;          // the current solve defers its x updates
+    double* xg_p = nullptr;      // [kXGroup - 1][NT] directions besides the solve's own
+    double* xg_alpha = nullptr;  // [kXGroup] the group's alphas
+    double* xg_p0 = nullptr;     // the solve's own direction buffer (group slot 0)
+    long long xg_q = 0;          // iterations queued in the current solve
     void* scratch = nullptr;     // this device's `scratch` (pa_compute_ptl_noalloc)
     hipError_t scratch_err = hipSuccess;
 };
@@ -1132,6 +1139,31 @@ pa_status pa_advance_rkg2(pa_ctx* c, double dt, int32_t cycles, pa_stats* st)
 
 namespace {
 
+static_assert(kXGroup == PA_PCG_XGROUP, "x-update group of the header");
+
+// Buffers of the deferred x update, allocated on first use; false when
+// device memory is short (the solve then updates x in place)
+bool xg_ready(pa_ctx* c)
+{
+    if (!c->xg_p) c->xg_p = (double*)dev_alloc(c, sizeof(double) * c->NT * (kXGroup - 1));
+    if (!c->xg_alpha) c->xg_alpha = (double*)dev_alloc(c, sizeof(double) * kXGroup);
+    return c->xg_p && c->xg_alpha;
+}
+
+double* xg_slot(pa_ctx* c, int t)
+{
+    return t == 0 ? c->xg_p0 : c->xg_p + (size_t)(t - 1) * c->NT;
+}
+
+// x += alpha_t p_t over the first `count` slots of the group
+void xg_flush(pa_ctx* c, int count)
+{
+    XSlots sl;
+    for (int t = 0; t < kXGroup; ++t) sl.p[t] = xg_slot(c, t);
+    KScope t(c, PA_K_DIR);
+    launch_pcg_xflush(c->NT, c->u, sl, c->xg_alpha, count, c->stream);
+}
+
 // Queue n PCG iterations (each skipped on the device once the solve is
 // done), point Jacobi or block ILU(0) preconditioned.  PT is the storage
 // type of the search direction and the matvec (double, or float for the
@@ -1153,6 +1185,47 @@ void pcg_queue(pa_ctx* c, double dtc, double* r, PT* p, PT* q, int n)
     double* zb = c->w[0];
     for (int b = 0; b < n; ++b) {
         KArgs<PT> a = base_args<PT>(c, 0, nr);
+        if constexpr (sizeof(PT) == 8) {
+            if (c->xg_on && !bilu0) {
+                // deferred x update: iteration k reads its direction from
+                // group slot k % kXGroup and writes the next one to the
+                // following slot; the group's x update runs after the last
+                // iteration's alpha is known and before its slot is reused
+                const int sl = (int)(c->xg_q % kXGroup);
+                double* pc = xg_slot(c, sl);
+                double* pn = xg_slot(c, (sl + 1) % kXGroup);
+                double* as = c->xg_alpha + sl;
+                a.u = pc;
+                a.out = q;
+                a.affine = 0;
+                a.dt = dtc;
+                a.done = &c->st->done;
+                {
+                    KScope t(c, PA_K_MATVEC);
+                    stencil<PT>(c, kMatvec, false, a);
+                }
+                {
+                    KScope t(c, PA_K_REDUCE);
+                    launch_pcg_alpha(c->part, mt, c->st, c->stream, as);
+                }
+                {
+                    KScope t(c, PA_K_UPDATE);
+                    launch_pcg_update<PT>(c->N, nc, c->Dbuf, nullptr, r, pc, q, c->st, c->part,
+                                          &nparts, c->stream);
+                }
+                {
+                    KScope t(c, PA_K_REDUCE);
+                    launch_pcg_beta(c->part, nparts, c->st, c->stream, as);
+                }
+                if (sl == kXGroup - 1) xg_flush(c, kXGroup);
+                {
+                    KScope t(c, PA_K_DIR);
+                    launch_pcg_dir_next(c->N, nc, c->Dbuf, r, pc, pn, c->st, c->stream);
+                }
+                ++c->xg_q;
+                continue;
+            }
+        }
         a.u = p;
         a.out = q;
         a.affine = 0;
@@ -1211,11 +1284,19 @@ pa_status pcg_loop(pa_ctx* c, double dtc, double* r, PT* p, PT* q)
     int batch = c->opt.pcg_batch;
     if (c->opt.force_iters <= 0 && c->pcg_hint > 0) batch = std::min(batch, c->pcg_hint);
     const int later = std::max(1, c->opt.pcg_batch / 4);
+    // the deferred x updates of a last, incomplete group
+    auto finish_x = [&] {
+        if (c->xg_on && c->xg_q % kXGroup) xg_flush(c, (int)(c->xg_q % kXGroup));
+    };
     while (true) {
         pcg_queue<PT>(c, dtc, r, p, q, batch);
         pa_status s = sync_state(c);
-        if (s) return s;
+        if (s) {
+            finish_x();
+            return s;
+        }
         if (c->hst->done) {
+            finish_x();
             c->pcg_hint = c->hst->iters;
             return PA_OK;
         }
@@ -1628,7 +1709,11 @@ pa_status pa_advance_be_pcg(pa_ctx* c, double dt, double tol, int32_t cycles, pa
                 if (s) break;
                 bilu0_start<double>(c, dtc, r, p);
             }
+            c->xg_on = !bilu0 && xg_ready(c);
+            c->xg_q = 0;
+            c->xg_p0 = p;
             s = pcg_loop<double>(c, dtc, r, p, q);
+            c->xg_on = false;
             if (s) break;
             its = c->hst->iters;
         } else {

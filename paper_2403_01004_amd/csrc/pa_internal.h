@@ -141,18 +141,35 @@ void launch_pcg_resid(size_t N, int nc, const double* b, const double* q, const 
                       double* r, PT* p, double* part, int* nparts, hipStream_t s);
 void launch_pcg_start(const double* part, int n, DevState* st, double tol, int max_iter,
                       int force_iters, int mode, double eta, hipStream_t s);
-void launch_pcg_alpha(const double* part, int n, DevState* st, hipStream_t s);
+// alpha = rho / <p, q>; with aslot, *aslot = 0 first (the iteration's entry
+// in the deferred x update; launch_pcg_beta fills it when the r update ran)
+void launch_pcg_alpha(const double* part, int n, DevState* st, hipStream_t s,
+                      double* aslot = nullptr);
 // r -= alpha q, partials <r, r/D>, <r, r>; also x += alpha p when x is not
 // null (otherwise launch_pcg_dir applies it, reading p once for both)
 template <class PT>
 void launch_pcg_update(size_t N, int nc, const double* D, double* x, double* r, const PT* p,
                        const PT* q, const DevState* st, double* part, int* nparts, hipStream_t s);
-void launch_pcg_beta(const double* part, int n, DevState* st, hipStream_t s);
+void launch_pcg_beta(const double* part, int n, DevState* st, hipStream_t s,
+                     double* aslot = nullptr);
 // x += alpha p (the update left by launch_pcg_update with x null), then
 // p = r/D + beta p unless the solve has stopped
 template <class PT>
 void launch_pcg_dir(size_t N, int nc, const double* D, const double* r, double* x, PT* p,
                     const DevState* st, hipStream_t s);
+// Deferred x update (FP64 point-Jacobi solves): the directions of kXGroup
+// consecutive iterations live in kXGroup buffers; pn = r/D + beta p while the
+// solve goes on, and x += alpha_t p_t for the group's iterations in order
+// (the arithmetic of launch_pcg_dir, applied per group: x is read and
+// written once per group instead of once per iteration)
+constexpr int kXGroup = 8;   // PA_PCG_XGROUP
+struct XSlots {
+    const double* p[kXGroup];
+};
+void launch_pcg_dir_next(size_t N, int nc, const double* D, const double* r, const double* p,
+                         double* pn, const DevState* st, hipStream_t s);
+void launch_pcg_xflush(size_t n, double* x, const XSlots& sl, const double* ahist, int count,
+                       hipStream_t s);
 // face couplings L_{m,nb} for nb = r-, r+, t-, t+, p-, p+ into out[6][N]
 // (zero where the neighbour does not exist) (pa_setup.hip)
 void launch_couplings(const Geo<double>& g, int op, const double* coef, double cs, const double* e,

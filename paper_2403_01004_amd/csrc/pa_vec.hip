@@ -455,10 +455,12 @@ void launch_pcg_start(const double* part, int n, DevState* st, double tol, int m
                        force_iters, mode, eta);
 }
 
-__global__ __launch_bounds__(kRedBlock) void k_pcg_alpha(const double* part, int n, DevState* st)
+__global__ __launch_bounds__(kRedBlock) void k_pcg_alpha(const double* part, int n, DevState* st,
+                                                          double* aslot)
 {
     // first kernel of an iteration to see the state: the previous
-    // iteration's x update has been applied by now
+    // iteration's x update has been applied by now (or recorded)
+    if (aslot && threadIdx.x == 0) *aslot = 0.0;
     if (st->done) {
         if (threadIdx.x == 0) st->xpend = 0;
         return;
@@ -471,9 +473,9 @@ __global__ __launch_bounds__(kRedBlock) void k_pcg_alpha(const double* part, int
     st->alpha = st->rho / pq;
 }
 
-void launch_pcg_alpha(const double* part, int n, DevState* st, hipStream_t s)
+void launch_pcg_alpha(const double* part, int n, DevState* st, hipStream_t s, double* aslot)
 {
-    hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(kRedBlock), 0, s, part, n, st);
+    hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(kRedBlock), 0, s, part, n, st, aslot);
 }
 
 // r -= alpha q, z = r/D, and x += alpha p when XU (otherwise k_pcg_dir
@@ -526,7 +528,8 @@ template void launch_pcg_update<float>(size_t, int, const double*, double*, doub
                                        const float*, const DevState*, double*, int*, hipStream_t);
 
 // stopping test and beta (PCG with rho = <r, z>)
-__global__ __launch_bounds__(kRedBlock) void k_pcg_beta(const double* part, int n, DevState* st)
+__global__ __launch_bounds__(kRedBlock) void k_pcg_beta(const double* part, int n, DevState* st,
+                                                         double* aslot)
 {
     if (st->done) return;
     double sums[2] = {0.0, 0.0};
@@ -535,6 +538,7 @@ __global__ __launch_bounds__(kRedBlock) void k_pcg_beta(const double* part, int 
     if (threadIdx.x != 0) return;
     st->iters += 1;
     st->xpend = 1;   // this iteration's update ran: its x update is due
+    if (aslot) *aslot = st->alpha;
     st->rr = rr;
     if (!isfinite(rr)) { st->status = 6; st->done = 1; return; }
     if (st->force_iters > 0) {
@@ -548,9 +552,9 @@ __global__ __launch_bounds__(kRedBlock) void k_pcg_beta(const double* part, int 
     st->rho = rz;
 }
 
-void launch_pcg_beta(const double* part, int n, DevState* st, hipStream_t s)
+void launch_pcg_beta(const double* part, int n, DevState* st, hipStream_t s, double* aslot)
 {
-    hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(kRedBlock), 0, s, part, n, st);
+    hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(kRedBlock), 0, s, part, n, st, aslot);
 }
 
 // x += alpha p for the iteration whose update just ran (xpend: set by
@@ -591,6 +595,67 @@ template void launch_pcg_dir<double>(size_t, int, const double*, const double*, 
                                      const DevState*, hipStream_t);
 template void launch_pcg_dir<float>(size_t, int, const double*, const double*, double*, float*,
                                     const DevState*, hipStream_t);
+
+// the direction of the next iteration into its own buffer, pn = r/D + beta p,
+// while the solve goes on; the x update is deferred to k_pcg_xflush (the
+// iteration's alpha recorded by k_pcg_beta)
+__global__ __launch_bounds__(kBlock) void k_pcg_dir_next(unsigned N, int nc,
+                                                         const double* __restrict__ Db,
+                                                         const double* __restrict__ r,
+                                                         const double* __restrict__ p,
+                                                         double* __restrict__ pn,
+                                                         const DevState* st)
+{
+    if (!st->xpend || st->done) return;
+    const double beta = st->beta;
+    for (unsigned cell = blockIdx.x * blockDim.x + threadIdx.x; cell < N;
+         cell += gridDim.x * blockDim.x) {
+        const double D = Db[cell];
+        for (int c = 0; c < nc; ++c) {
+            const size_t m = (size_t)c * N + cell;
+            stnt(ldnt(r + m) / D + beta * ldnt(p + m), pn + m);
+        }
+    }
+}
+
+void launch_pcg_dir_next(size_t N, int nc, const double* D, const double* r, const double* p,
+                         double* pn, const DevState* st, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pcg_dir_next, dim3(vec_blocks(N)), dim3(kBlock), 0, s, (unsigned)N, nc, D,
+                       r, p, pn, st);
+}
+
+// x += alpha_t p_t for t = 0 .. count - 1 in that order, the per-iteration
+// update of k_pcg_dir applied for a group of iterations; a zero alpha (an
+// iteration queued after the solve stopped, or one whose r update did not
+// run) leaves x as it is, so its term is skipped
+__global__ __launch_bounds__(kBlock) void k_pcg_xflush(size_t n, double* __restrict__ x, XSlots sl,
+                                                       const double* ahist, int count)
+{
+    double a[kXGroup];
+    bool any = false;
+#pragma unroll
+    for (int t = 0; t < kXGroup; ++t) {
+        a[t] = t < count ? ahist[t] : 0.0;
+        any = any || a[t] != 0.0;
+    }
+    if (!any) return;
+    for (size_t m = (size_t)blockIdx.x * blockDim.x + threadIdx.x; m < n;
+         m += (size_t)gridDim.x * blockDim.x) {
+        double xv = ldnt(x + m);
+#pragma unroll
+        for (int t = 0; t < kXGroup; ++t)
+            if (a[t] != 0.0) xv = xv + a[t] * ldnt(sl.p[t] + m);
+        stnt(xv, x + m);
+    }
+}
+
+void launch_pcg_xflush(size_t n, double* x, const XSlots& sl, const double* ahist, int count,
+                       hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pcg_xflush, dim3(vec_blocks(n)), dim3(kBlock), 0, s, n, x, sl, ahist,
+                       count);
+}
 
 // p = z + beta p while the solve goes on, with z the preconditioned
 // residual stored by a block preconditioner (all components, n = nc * N

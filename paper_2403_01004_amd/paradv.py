@@ -17,6 +17,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libparadv.so")
 PA_MAX_LOG = 4096
+PA_PCG_XGROUP = 8
 
 PA_OK, PA_ERR_ARG, PA_ERR_ALLOC, PA_ERR_HIP, PA_ERR_NOCONV, PA_ERR_BREAKDOWN, \
     PA_ERR_NONFINITE, PA_ERR_STATE, PA_ERR_MAXCYCLES = range(9)

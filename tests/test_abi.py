@@ -66,6 +66,7 @@ def test_header_constants_match_binding(lib):
     assert int(re.search(r"#define PA_LPC_NPARAM (\d+)", txt).group(1)) == lib.PA_LPC_NPARAM
     assert int(re.search(r"PA_NKCLASS = (\d+)", txt).group(1)) == lib.PA_NKCLASS
     assert int(re.search(r"#define PA_MAX_LOG (\d+)", txt).group(1)) == lib.PA_MAX_LOG
+    assert int(re.search(r"#define PA_PCG_XGROUP (\d+)", txt).group(1)) == lib.PA_PCG_XGROUP
     box = tuple(int(re.search(r"#define PA_BILU0_B%s (\d+)" % a, txt).group(1)) for a in "IJK")
     assert box == lib.PA_BILU0_BOX
     pcs = dict((k, int(v)) for k, v in re.findall(r"PA_PC_(\w+) = (\d+)", txt))

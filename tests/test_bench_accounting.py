@@ -19,15 +19,15 @@ N, NCO = 1000, 1010
     ("first", "aligned", 1, 16 + 24 * 1.01),          # u, y0 + e
     ("matvec", "aligned", 1, 16 + 24 * 1.01),         # p, q + e
     ("update", "aligned", 1, 24 + 8),                 # r, q, D; r
-    ("dir", "aligned", 1, 40 + 8),                    # r, p, x, D; p, x
+    ("dir", "aligned", 1, 24 + 8),                    # r, p, D; the next p
     ("first", "iso7", 3, 3 * 16),
     ("matvec", "iso7", 3, 3 * 16),
     ("update", "iso7", 3, 3 * 24 + 8),                # 80 B per cell
-    ("dir", "iso7", 3, 3 * 40 + 8),                   # 128 B per cell
+    ("dir", "iso7", 3, 3 * 24 + 8),                   # 80 B per cell
     ("update", "viscv", 3, 3 * 24 + 8),
-    ("dir", "viscv", 3, 3 * 40 + 8),
+    ("dir", "viscv", 3, 3 * 24 + 8),
     ("init", "iso7", 3, 3 * 32 + 16),                 # u, y0, diag L; r, p, D
-    ("dir_last", "iso7", 3, 3 * 24),                  # x, p; x
+    ("xgroup", "iso7", 3, 3 * 16),                    # x read and written once per group
 ])
 def test_bytes_per_cell(cls, op, nc, per_cell):
     got = bench.bytes_per_launch(op, nc, cls, N, NCO, False) / N
@@ -49,12 +49,17 @@ def test_stage_bytes_per_cycle():
     assert bench.bytes_per_launch("iso7", 1, "matvec", N, NCO, True) == 2 * f + 8 * N
 
 
-def test_dir_saving():
-    """One short direction launch per solve that took iterations."""
-    f = 8 * N
-    per = bench.bytes_per_launch("iso7", 3, "dir", N, NCO, False) - 9 * f
-    assert per == 6 * f + 8 * N
-    assert bench.dir_saving("iso7", 3, N, NCO, [12, 0, 7, 1]) == 3 * per
+def test_dir_class_bytes():
+    """Per solve of n iterations: n - 1 direction launches (the stopping
+    iteration writes no direction), every iteration's direction read once by
+    its group's x update, x read and written once per group of 8."""
+    f = 8 * N * 3
+    d = bench.bytes_per_launch("iso7", 3, "dir", N, NCO, False)
+    assert d == 3 * f + 8 * N
+    want = (11 * d + 12 * f + 2 * 2 * f) + (6 * d + 7 * f + 1 * 2 * f) + (0 * d + 1 * f + 2 * f)
+    assert bench.dir_class_bytes("iso7", 3, N, NCO, [12, 0, 7, 1], 8) == want
+    import paper_2403_01004_amd.paradv as paradv
+    assert bench.XGROUP == paradv.PA_PCG_XGROUP
 
 
 def test_fp32_bytes():
