@@ -1168,9 +1168,11 @@ void xg_flush(pa_ctx* c, int count)
 // done), point Jacobi or block ILU(0) preconditioned.  PT is the storage
 // type of the search direction and the matvec (double, or float for the
 // FP32-matvec inner solves); x, r and all scalars are FP64.  Point Jacobi:
-// matvec, alpha, r update, stopping test, then x += alpha p together with
-// the new direction (p is read once for both; the iteration that stops the
-// solve still applies its x update there).
+// matvec, alpha, r update, stopping test, then the new direction; x +=
+// alpha p either in the same kernel (p is read once for both; the iteration
+// that stops the solve still applies its x update there) or, for FP64
+// solves with the group buffers, deferred: once per kXGroup iterations,
+// from the group's directions kept in their own buffers.
 template <class PT>
 void pcg_queue(pa_ctx* c, double dtc, double* r, PT* p, PT* q, int n)
 {
