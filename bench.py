@@ -38,12 +38,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def bytes_per_launch(op, ncomp, cls, N, NCO, coef_var, stage_k=None, word=8):
+def bytes_per_launch(op, ncomp, cls, N, NCO, coef_var, stage_k=None, word=8, rows=False):
     """Algorithmic HBM bytes of one launch: every array the kernel needs read
     once, every output written once, `word` bytes per value (8: FP64; 4:
     the FP32 stencil and stage kernels).  Field-aligned coefficients are 3
     values per corner; the 7-point operator reads a cell coefficient array
-    only when the coefficient varies."""
+    only when the coefficient varies.  rows: the point-Jacobi diagonal is
+    formed from per-(r, theta) row terms (the advance's `jacobi_rows`), so
+    the PCG kernels read no per-cell D (the row terms, 16 B per row and per
+    phi index, are under 0.1% of a launch and not counted)."""
     coef = 3 * word * NCO if op == "aligned" else (word * N if coef_var else 0)
     f = word * N * ncomp
     if cls == "first":
@@ -53,18 +56,19 @@ def bytes_per_launch(op, ncomp, cls, N, NCO, coef_var, stage_k=None, word=8):
         return (nread + 1) * f + coef
     if cls == "matvec":
         return 2 * f + coef
+    dcell = 0 if rows else 8 * N
     if cls == "update":
-        return 3 * f + 8 * N    # r, q, D read; r written
+        return 3 * f + dcell    # r, q, D read; r written
     if cls == "dir":
-        return 3 * f + 8 * N    # r, p, D read; the next direction written
+        return 3 * f + dcell    # r, p, D read; the next direction written
     if cls == "xgroup":
         return 2 * f            # x read and written once per group (plus its directions)
     if cls == "init":
-        return 4 * f + 16 * N   # u, y0, diag L read; r, p, D written
+        return 4 * f + 8 * N + dcell   # u, y0 (and diag L) read; r, p, D written
     return 0
 
 
-def dir_class_bytes(op, ncomp, N, NCO, per_cycle, group=8):
+def dir_class_bytes(op, ncomp, N, NCO, per_cycle, group=8, rows=False):
     """Bytes of the direction class of an FP64 point-Jacobi BE advance: per
     solve of n iterations, n - 1 direction launches (the iteration that
     stops a solve writes no new direction) and the x updates of the groups
@@ -76,7 +80,7 @@ def dir_class_bytes(op, ncomp, N, NCO, per_cycle, group=8):
         n = int(n)
         if n <= 0:
             continue
-        tot += (n - 1) * bytes_per_launch(op, ncomp, "dir", N, NCO, False)
+        tot += (n - 1) * bytes_per_launch(op, ncomp, "dir", N, NCO, False, rows=rows)
         tot += n * f + -(-n // group) * bytes_per_launch(op, ncomp, "xgroup", N, NCO, False)
     return tot
 
@@ -207,6 +211,7 @@ def kernel_accounting(s, op, nc, N, NCO, coef_var=False):
     after its solve stopped exit at once: one effective launch per
     iteration, all launch time charged to them."""
     out = {}
+    rows = bool(s.get("jacobi_rows", False))
     for cls, ms in s["kernel_ms"].items():
         calls = s["kernel_calls"][cls]
         if calls == 0:
@@ -218,9 +223,9 @@ def kernel_accounting(s, op, nc, N, NCO, coef_var=False):
         if cls == "stage":
             by = stage_bytes(op, nc, N, NCO, coef_var, s["per_cycle"])
         elif cls == "dir":
-            by = dir_class_bytes(op, nc, N, NCO, s["per_cycle"], XGROUP)
+            by = dir_class_bytes(op, nc, N, NCO, s["per_cycle"], XGROUP, rows)
         else:
-            by = calls * bytes_per_launch(op, nc, cls, N, NCO, coef_var)
+            by = calls * bytes_per_launch(op, nc, cls, N, NCO, coef_var, rows=rows)
         out[cls] = [ms, calls, by]
     return out
 

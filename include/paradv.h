@@ -166,6 +166,10 @@ typedef struct {
     int32_t kernel_calls[PA_NKCLASS]; /* with opts.timing: launches per class */
     double dt_cycle[PA_MAX_LOG];   /* length of each cycle */
     int32_t per_cycle[PA_MAX_LOG]; /* stages (STS) or PCG iterations (BE) per cycle */
+    int32_t jacobi_rows;  /* BE with FP64 point-Jacobi PCG: 1 when the diagonal
+                             D = V + dt diag(L) was formed from per-(r, theta) row
+                             terms (7-point operator, constant coefficient, no
+                             weight), so no per-cell D is read in the iterations */
 } pa_stats;
 
 /* Create a context on the current HIP device; all work goes to hip_stream

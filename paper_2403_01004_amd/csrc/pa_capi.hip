@@ -162,6 +162,9 @@ struct pa_ctx {
     bool xg_on = false;          // the current solve defers its x updates
     double* xg_p = nullptr;      // [kXGroup - 1][NT] directions besides the solve's own
     double* xg_alpha = nullptr;  // [kXGroup] the group's alphas
+    bool jd_on = false;          // the current solve forms D from rows (JacD)
+    double* jd_ab = nullptr;     // [nr * nt][2] row terms A, B of D at the solve's step
+    double* jd_G = nullptr;      // [np] gpp_k + gpp_{k+1}
     double* xg_p0 = nullptr;     // the solve's own direction buffer (group slot 0)
     long long xg_q = 0;          // iterations queued in the current solve
     void* scratch = nullptr;     // this device's `scratch` (pa_compute_ptl_noalloc)
@@ -1150,6 +1153,29 @@ bool xg_ready(pa_ctx* c)
     return c->xg_p && c->xg_alpha;
 }
 
+// Row form of the Jacobi diagonal (7-point operator, constant coefficient,
+// no weight), arrays allocated on first use; false when not applicable or
+// device memory is short (D is then read per cell)
+bool jd_ready(pa_ctx* c)
+{
+    if (c->d.op == PA_OP_FIELD_ALIGNED || c->coef_var || c->use_w) return false;
+    if (!c->jd_ab) c->jd_ab = (double*)dev_alloc(c, sizeof(double) * 2 * c->d.nr * c->d.nt);
+    if (!c->jd_G) c->jd_G = (double*)dev_alloc(c, sizeof(double) * c->d.np);
+    return c->jd_ab && c->jd_G;
+}
+
+JacD jd_of(pa_ctx* c)
+{
+    JacD j;
+    if (c->jd_on) {
+        j.ab = c->jd_ab;
+        j.G = c->jd_G;
+        j.vp = c->m64.vp;
+        j.np = (unsigned)c->d.np;
+    }
+    return j;
+}
+
 double* xg_slot(pa_ctx* c, int t)
 {
     return t == 0 ? c->xg_p0 : c->xg_p + (size_t)(t - 1) * c->NT;
@@ -1213,7 +1239,7 @@ void pcg_queue(pa_ctx* c, double dtc, double* r, PT* p, PT* q, int n)
                 {
                     KScope t(c, PA_K_UPDATE);
                     launch_pcg_update<PT>(c->N, nc, c->Dbuf, nullptr, r, pc, q, c->st, c->part,
-                                          &nparts, c->stream);
+                                          &nparts, c->stream, jd_of(c));
                 }
                 {
                     KScope t(c, PA_K_REDUCE);
@@ -1222,7 +1248,8 @@ void pcg_queue(pa_ctx* c, double dtc, double* r, PT* p, PT* q, int n)
                 if (sl == kXGroup - 1) xg_flush(c, kXGroup);
                 {
                     KScope t(c, PA_K_DIR);
-                    launch_pcg_dir_next(c->N, nc, c->Dbuf, r, pc, pn, c->st, c->stream);
+                    launch_pcg_dir_next(c->N, nc, c->Dbuf, r, pc, pn, c->st, c->stream,
+                                        jd_of(c));
                 }
                 ++c->xg_q;
                 continue;
@@ -1694,12 +1721,18 @@ pa_status pa_advance_be_pcg(pa_ctx* c, double dt, double tol, int32_t cycles, pa
             if (s) break;
             st->fallbacks += fb;
         } else if (!c->fp32) {
+            c->jd_on = !bilu0 && jd_ready(c);
+            if (c->jd_on) st->jacobi_rows = 1;
             {
                 KScope t(c, PA_K_INIT);
                 if (any_dir) boundary_data(c, q);
+                if (c->jd_on)
+                    launch_jacobi_rows(g, c->cscale, c->d.bc_in, c->d.bc_out, dtc, c->jd_ab,
+                                       c->jd_G, c->stream);
                 launch_pcg_init<double>(g, nc, dtc, c->use_w ? c->w64 : nullptr, c->u, y0,
                                         any_dir ? q : nullptr, c->diagL,
-                                        c->Dbuf, r, p, nullptr, c->part, &nparts, c->stream);
+                                        c->Dbuf, r, p, nullptr, c->part, &nparts, c->stream,
+                                        jd_of(c));
             }
             {
                 KScope t(c, PA_K_REDUCE);
@@ -1716,6 +1749,7 @@ pa_status pa_advance_be_pcg(pa_ctx* c, double dt, double tol, int32_t cycles, pa
             c->xg_p0 = p;
             s = pcg_loop<double>(c, dtc, r, p, q);
             c->xg_on = false;
+            c->jd_on = false;
             if (s) break;
             its = c->hst->iters;
         } else {

@@ -132,10 +132,27 @@ void launch_argmax(const double* pval, const long long* pidx, int n, long long N
 template <class T>
 void launch_ptl_finalize(const double* pval, const long long* pidx, int n, const T* u, const T* F,
                          int nc, int nr, int nt, int np, DevState* st, hipStream_t s);
+// Point-Jacobi diagonal in row form, D = V + dt diag(L) = vp_k A_ij + B_ij G_k,
+// for the 7-point operator with a constant coefficient and no weight: the
+// metric is separable, so D is two values per (r, theta) row and two per phi
+// index instead of one value per cell.  ab interleaves A, B per row
+// (nr * nt pairs), G_k = gpp_k + gpp_{k+1}; ab null: D is read from the
+// per-cell array.
+struct JacD {
+    const double* ab = nullptr;
+    const double* G = nullptr;
+    const double* vp = nullptr;
+    unsigned np = 0;
+};
+// ab and G at step dt (pa_setup.hip)
+void launch_jacobi_rows(const Geo<double>& g, double cs, int bc_in, int bc_out, double dt,
+                        double* ab, double* G, hipStream_t s);
+// with jd.ab set, D is formed from the rows (and still written to D)
 template <class PT>
 void launch_pcg_init(const Geo<double>& g, int nc, double dt, const double* w, const double* u,
                      const double* y0, const double* hF, const double* diagL, double* D, double* r,
-                     PT* p, double* b, double* part, int* nparts, hipStream_t s);
+                     PT* p, double* b, double* part, int* nparts, hipStream_t s,
+                     const JacD& jd = JacD{});
 template <class PT>
 void launch_pcg_resid(size_t N, int nc, const double* b, const double* q, const double* D,
                       double* r, PT* p, double* part, int* nparts, hipStream_t s);
@@ -149,7 +166,8 @@ void launch_pcg_alpha(const double* part, int n, DevState* st, hipStream_t s,
 // null (otherwise launch_pcg_dir applies it, reading p once for both)
 template <class PT>
 void launch_pcg_update(size_t N, int nc, const double* D, double* x, double* r, const PT* p,
-                       const PT* q, const DevState* st, double* part, int* nparts, hipStream_t s);
+                       const PT* q, const DevState* st, double* part, int* nparts, hipStream_t s,
+                       const JacD& jd = JacD{});
 void launch_pcg_beta(const double* part, int n, DevState* st, hipStream_t s,
                      double* aslot = nullptr);
 // x += alpha p (the update left by launch_pcg_update with x null), then
@@ -167,7 +185,7 @@ struct XSlots {
     const double* p[kXGroup];
 };
 void launch_pcg_dir_next(size_t N, int nc, const double* D, const double* r, const double* p,
-                         double* pn, const DevState* st, hipStream_t s);
+                         double* pn, const DevState* st, hipStream_t s, const JacD& jd = JacD{});
 void launch_pcg_xflush(size_t n, double* x, const XSlots& sl, const double* ahist, int count,
                        hipStream_t s);
 // face couplings L_{m,nb} for nb = r-, r+, t-, t+, p-, p+ into out[6][N]

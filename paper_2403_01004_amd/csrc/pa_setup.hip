@@ -206,6 +206,39 @@ void launch_diag_iso7(const Geo<double>& g, const double* coef, double cs, const
                        part);
 }
 
+// Row form of the BE Jacobi diagonal D = V + dt diag(L) for the 7-point
+// operator with the constant coefficient cs and no weight (the terms of
+// k_diag_iso7 with every face coefficient equal to cs): every term carries
+// either vp_k (cell volume, radial and colatitude faces) or gpp_k, gpp_{k+1}
+// (the two longitude faces), so D = vp_k A_ij + B_ij G_k with
+// A_ij = vr_i vt_j + dt cs (vt_j (gr_lo + gr_hi) + gtr_i (gtt_lo + gtt_hi)),
+// B_ij = dt cs gtr_i gpt_j, G_k = gpp_k + gpp_{k+1}.
+__global__ __launch_bounds__(kBlock) void k_jacobi_rows(Geo<double> g, double cs, int bc_in,
+                                                        int bc_out, double dt, double* ab,
+                                                        double* G)
+{
+    const int nr = g.nr, nt = g.nt, np = g.np;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < np) G[t] = g.gpp[t] + g.gpp[t == np - 1 ? 0 : t + 1];
+    if (t >= nr * nt) return;
+    const int i = t / nt, j = t - i * nt;
+    const double grl = (i > 0 || bc_in == 0) ? g.gr[i] : 0.0;
+    const double grh = (i < nr - 1 || bc_out == 0) ? g.gr[i + 1] : 0.0;
+    const double gtl = j > 0 ? g.gtt[j] : 0.0;
+    const double gth = j < nt - 1 ? g.gtt[j + 1] : 0.0;
+    const double q = cs * (g.vt[j] * (grl + grh) + g.gtr[i] * (gtl + gth));
+    ab[2 * t] = g.vr[i] * g.vt[j] + dt * q;
+    ab[2 * t + 1] = dt * cs * g.gtr[i] * g.gpt[j];
+}
+
+void launch_jacobi_rows(const Geo<double>& g, double cs, int bc_in, int bc_out, double dt,
+                        double* ab, double* G, hipStream_t s)
+{
+    const int n = g.nr * g.nt > g.np ? g.nr * g.nt : g.np;
+    hipLaunchKernelGGL(k_jacobi_rows, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, g, cs,
+                       bc_in, bc_out, dt, ab, G);
+}
+
 void launch_diag_aligned(const Geo<double>& g, const double* e, const double* w, int bc_in,
                          int bc_out, double* diag, double* part, hipStream_t s, int* nparts)
 {

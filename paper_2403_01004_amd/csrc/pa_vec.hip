@@ -24,6 +24,15 @@ __device__ __forceinline__ T ldnt(const T* a) { return __builtin_nontemporal_loa
 template <class T>
 __device__ __forceinline__ void stnt(T v, T* a) { __builtin_nontemporal_store(v, a); }
 
+// Jacobi diagonal of a cell: from the rows (JacD) or the per-cell array.  The
+// row form is one expression, so every kernel forms the same value.
+__device__ __forceinline__ double jac_d(const JacD& jd, const double* Db, unsigned cell)
+{
+    if (!jd.ab) return Db[cell];
+    const unsigned ij = cell / jd.np, k = cell - ij * jd.np;
+    return fma(jd.vp[k], jd.ab[2 * ij], jd.ab[2 * ij + 1] * jd.G[k]);
+}
+
 // K sums of part[q*n .. q*n + n) by one workgroup of kRedBlock threads,
 // results in thread 0.  The K arrays are read in the same loop, so their
 // loads overlap (the stopping test needs two sums, the start of a solve
@@ -335,7 +344,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(Geo<double> g, int nc, doub
                                                      const double* y0,
                                                      const double* hF, const double* dL,
                                                      double* Dout, double* r, PT* p, double* bout,
-                                                     double* part)
+                                                     double* part, JacD jd)
 {
     const int nr = g.nr, np = g.np;
     const unsigned P = (unsigned)g.P, N = (unsigned)nr * P;
@@ -344,7 +353,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(Geo<double> g, int nc, doub
          cell += gridDim.x * blockDim.x) {
         const unsigned i = cell / P, pp = cell - i * P, j = pp / (unsigned)np, k = pp - j * np;
         const double V = g.vr[i] * g.vt[j] * g.vp[k] * (w ? w[cell] : 1.0);  // w V
-        const double D = V + dt * dL[cell];
+        const double D = jd.ab ? jac_d(jd, nullptr, cell) : V + dt * dL[cell];
         Dout[cell] = D;
         const bool bnd = hF && (i == 0 || i == (unsigned)nr - 1);
         for (int c = 0; c < nc; ++c) {
@@ -367,19 +376,21 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(Geo<double> g, int nc, doub
 template <class PT>
 void launch_pcg_init(const Geo<double>& g, int nc, double dt, const double* w, const double* u,
                      const double* y0, const double* hF, const double* diagL, double* D, double* r,
-                     PT* p, double* b, double* part, int* nparts, hipStream_t s)
+                     PT* p, double* b, double* part, int* nparts, hipStream_t s, const JacD& jd)
 {
     const int nb = vec_blocks((size_t)g.nr * g.P);
     *nparts = nb;
     hipLaunchKernelGGL((k_pcg_init<PT>), dim3(nb), dim3(kBlock), 0, s, g, nc, dt, w, u, y0, hF,
-                       diagL, D, r, p, b, part);
+                       diagL, D, r, p, b, part, jd);
 }
 template void launch_pcg_init<double>(const Geo<double>&, int, double, const double*, const double*,
                                       const double*, const double*, const double*, double*,
-                                      double*, double*, double*, double*, int*, hipStream_t);
+                                      double*, double*, double*, double*, int*, hipStream_t,
+                                      const JacD&);
 template void launch_pcg_init<float>(const Geo<double>&, int, double, const double*, const double*,
                                      const double*, const double*, const double*, double*,
-                                     double*, float*, double*, double*, int*, hipStream_t);
+                                     double*, float*, double*, double*, int*, hipStream_t,
+                                     const JacD&);
 
 // Defect correction: r = b - q (q = M x from an FP64 matvec), p = r/D;
 // partials <r,z>, <r,r>, <b,b>.
@@ -488,14 +499,14 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(unsigned N, int nc,
                                                        double* __restrict__ r,
                                                        const PT* __restrict__ p,
                                                        const PT* __restrict__ q,
-                                                       const DevState* st, double* part)
+                                                       const DevState* st, double* part, JacD jd)
 {
     if (st->done) return;
     const double alpha = st->alpha;
     double acc[2] = {0.0, 0.0};
     for (unsigned cell = blockIdx.x * blockDim.x + threadIdx.x; cell < N;
          cell += gridDim.x * blockDim.x) {
-        const double D = Db[cell];
+        const double D = jac_d(jd, Db, cell);
         for (int c = 0; c < nc; ++c) {
             const size_t m = (size_t)c * N + cell;
             if (XU) stnt(ldnt(x + m) + alpha * (double)ldnt(p + m), x + m);
@@ -511,21 +522,24 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(unsigned N, int nc,
 
 template <class PT>
 void launch_pcg_update(size_t N, int nc, const double* D, double* x, double* r, const PT* p,
-                       const PT* q, const DevState* st, double* part, int* nparts, hipStream_t s)
+                       const PT* q, const DevState* st, double* part, int* nparts, hipStream_t s,
+                       const JacD& jd)
 {
     const int nb = vec_blocks(N);
     *nparts = nb;
     if (x)
         hipLaunchKernelGGL((k_pcg_update<PT, true>), dim3(nb), dim3(kBlock), 0, s, (unsigned)N, nc,
-                           D, x, r, p, q, st, part);
+                           D, x, r, p, q, st, part, jd);
     else
         hipLaunchKernelGGL((k_pcg_update<PT, false>), dim3(nb), dim3(kBlock), 0, s, (unsigned)N, nc,
-                           D, x, r, p, q, st, part);
+                           D, x, r, p, q, st, part, jd);
 }
 template void launch_pcg_update<double>(size_t, int, const double*, double*, double*, const double*,
-                                        const double*, const DevState*, double*, int*, hipStream_t);
+                                        const double*, const DevState*, double*, int*, hipStream_t,
+                                        const JacD&);
 template void launch_pcg_update<float>(size_t, int, const double*, double*, double*, const float*,
-                                       const float*, const DevState*, double*, int*, hipStream_t);
+                                       const float*, const DevState*, double*, int*, hipStream_t,
+                                       const JacD&);
 
 // stopping test and beta (PCG with rho = <r, z>)
 __global__ __launch_bounds__(kRedBlock) void k_pcg_beta(const double* part, int n, DevState* st,
@@ -604,13 +618,13 @@ __global__ __launch_bounds__(kBlock) void k_pcg_dir_next(unsigned N, int nc,
                                                          const double* __restrict__ r,
                                                          const double* __restrict__ p,
                                                          double* __restrict__ pn,
-                                                         const DevState* st)
+                                                         const DevState* st, JacD jd)
 {
     if (!st->xpend || st->done) return;
     const double beta = st->beta;
     for (unsigned cell = blockIdx.x * blockDim.x + threadIdx.x; cell < N;
          cell += gridDim.x * blockDim.x) {
-        const double D = Db[cell];
+        const double D = jac_d(jd, Db, cell);
         for (int c = 0; c < nc; ++c) {
             const size_t m = (size_t)c * N + cell;
             stnt(ldnt(r + m) / D + beta * ldnt(p + m), pn + m);
@@ -619,10 +633,10 @@ __global__ __launch_bounds__(kBlock) void k_pcg_dir_next(unsigned N, int nc,
 }
 
 void launch_pcg_dir_next(size_t N, int nc, const double* D, const double* r, const double* p,
-                         double* pn, const DevState* st, hipStream_t s)
+                         double* pn, const DevState* st, hipStream_t s, const JacD& jd)
 {
     hipLaunchKernelGGL(k_pcg_dir_next, dim3(vec_blocks(N)), dim3(kBlock), 0, s, (unsigned)N, nc, D,
-                       r, p, pn, st);
+                       r, p, pn, st, jd);
 }
 
 // x += alpha_t p_t for t = 0 .. count - 1 in that order, the per-iteration

@@ -78,7 +78,8 @@ class pa_stats(ctypes.Structure):
                 ("kernel_ms", ctypes.c_double * PA_NKCLASS),
                 ("kernel_calls", ctypes.c_int32 * PA_NKCLASS),
                 ("dt_cycle", ctypes.c_double * PA_MAX_LOG),
-                ("per_cycle", ctypes.c_int32 * PA_MAX_LOG)]
+                ("per_cycle", ctypes.c_int32 * PA_MAX_LOG),
+                ("jacobi_rows", ctypes.c_int32)]
 
 
 class pa_lpc_train_opts(ctypes.Structure):
@@ -330,7 +331,8 @@ def _stats_dict(s: pa_stats):
                 rel_residual=s.rel_residual, ms_total=s.ms_total,
                 kernel_ms={k: s.kernel_ms[i] for i, k in enumerate(KERNEL_CLASSES)},
                 kernel_calls={k: s.kernel_calls[i] for i, k in enumerate(KERNEL_CLASSES)},
-                dt_cycle=np.array(s.dt_cycle[:n]), per_cycle=np.array(s.per_cycle[:n]))
+                dt_cycle=np.array(s.dt_cycle[:n]), per_cycle=np.array(s.per_cycle[:n]),
+                jacobi_rows=bool(s.jacobi_rows))
 
 
 class Operator:

@@ -68,3 +68,31 @@ def test_fp32_bytes():
     assert bench.bytes_per_launch("aligned", 1, "first", N, NCO, False, word=4) == 8 * N + 12 * NCO
     assert bench.bytes_per_launch("viscv", 3, "stage", N, NCO, False, stage_k=5, word=4) == 5 * 12 * N
     assert bench.stage_bytes("viscv", 3, N, NCO, False, [3], word=4) == 3 * 12 * N + 4 * 12 * N
+
+
+@pytest.mark.parametrize("cls,per_cell", [
+    ("update", 3 * 24),        # r, q; r (D from the row terms)
+    ("dir", 3 * 24),           # r, p; the next p
+    ("init", 3 * 32 + 8),      # u, y0; r, p, D
+])
+def test_bytes_with_row_diagonal(cls, per_cell):
+    """With the point-Jacobi diagonal formed from per-(r, theta) row terms
+    (7-point operator, constant coefficient, no weight) the PCG kernels read
+    no per-cell D, and the start of a solve reads no diag(L)."""
+    got = bench.bytes_per_launch("viscv", 3, cls, N, NCO, False, rows=True) / N
+    assert got == pytest.approx(per_cell, rel=1e-12)
+    f = 8 * N * 3
+    assert bench.dir_class_bytes("viscv", 3, N, NCO, [9], 8, rows=True) == \
+        8 * 3 * f + 9 * f + 2 * 2 * f
+
+
+def test_kernel_accounting_follows_the_flag():
+    """kernel_accounting charges the row form only when the advance reports it."""
+    s = {"kernel_ms": {"update": 1.0, "dir": 1.0, "init": 1.0},
+         "kernel_calls": {"update": 10, "dir": 10, "init": 1},
+         "iters_total": 9, "per_cycle": [9]}
+    plain = bench.kernel_accounting(dict(s, jacobi_rows=False), "viscv", 3, N, NCO)
+    rows = bench.kernel_accounting(dict(s, jacobi_rows=True), "viscv", 3, N, NCO)
+    assert plain["update"][2] - rows["update"][2] == 9 * 8 * N
+    assert plain["dir"][2] - rows["dir"][2] == 8 * 8 * N
+    assert plain["init"][2] - rows["init"][2] == 8 * N
