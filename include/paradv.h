@@ -84,10 +84,11 @@ typedef enum { PA_PC_JACOBI = 0, PA_PC_LEARNED = 1, PA_PC_BILU0 = 2 } pa_pc;
 #define PA_BILU0_BJ 4
 #define PA_BILU0_BK 16
 
-/* Backward Euler solves with point Jacobi in FP64 apply the x update of
+/* Backward Euler solves with point Jacobi (FP64, or FP32 matvecs and
+ * directions) apply the x update of
  * PA_PCG_XGROUP consecutive PCG iterations together: the group's search
  * directions stay in their own buffers (PA_PCG_XGROUP - 1 fields of device
- * memory besides the solve's own, allocated on first use; without them the
+ * memory besides the solve's own, in the direction type, allocated on first use; without them the
  * solve updates x every iteration), and x is read and written once per
  * group.  The result is that of one x update per iteration, bit for bit;
  * the timing class PA_K_DIR counts both kernels (direction, group update). */
@@ -166,7 +167,7 @@ typedef struct {
     int32_t kernel_calls[PA_NKCLASS]; /* with opts.timing: launches per class */
     double dt_cycle[PA_MAX_LOG];   /* length of each cycle */
     int32_t per_cycle[PA_MAX_LOG]; /* stages (STS) or PCG iterations (BE) per cycle */
-    int32_t jacobi_rows;  /* BE with FP64 point-Jacobi PCG: 1 when the diagonal
+    int32_t jacobi_rows;  /* BE with point-Jacobi PCG: 1 when the diagonal
                              D = V + dt diag(L) was formed from per-(r, theta) row
                              terms (7-point operator, constant coefficient, no
                              weight), so no per-cell D is read in the iterations */

@@ -157,15 +157,16 @@ struct pa_ctx {
     float* nn_wpart = nullptr;                   // weight-gradient partials
     double* bilu0_ip = nullptr;  // [N] inverse block ILU(0) pivots of the current solve
     int pcg_hint = 0;            // iterations of the last PCG solve (first batch of the next)
-    // deferred x update of the FP64 point-Jacobi solves: the directions of
+    // deferred x update of the point-Jacobi solves: the directions of
     // kXGroup consecutive iterations, x updated once per group
     bool xg_on = false;          // the current solve defers its x updates
     double* xg_p = nullptr;      // [kXGroup - 1][NT] directions besides the solve's own
+    float* xg_p32 = nullptr;     // the same for the FP32-matvec solves
     double* xg_alpha = nullptr;  // [kXGroup] the group's alphas
     bool jd_on = false;          // the current solve forms D from rows (JacD)
     double* jd_ab = nullptr;     // [nr * nt][2] row terms A, B of D at the solve's step
     double* jd_G = nullptr;      // [np] gpp_k + gpp_{k+1}
-    double* xg_p0 = nullptr;     // the solve's own direction buffer (group slot 0)
+    void* xg_p0 = nullptr;       // the solve's own direction buffer (group slot 0)
     long long xg_q = 0;          // iterations queued in the current solve
     void* scratch = nullptr;     // this device's `scratch` (pa_compute_ptl_noalloc)
     hipError_t scratch_err = hipSuccess;
@@ -1144,13 +1145,23 @@ namespace {
 
 static_assert(kXGroup == PA_PCG_XGROUP, "x-update group of the header");
 
-// Buffers of the deferred x update, allocated on first use; false when
-// device memory is short (the solve then updates x in place)
+// Direction buffers of the deferred x update (PT: the solve's direction
+// type), allocated on first use; false when device memory is short (the
+// solve then updates x in place)
+template <class PT>
+PT*& xg_bufs(pa_ctx* c)
+{
+    if constexpr (sizeof(PT) == 8) return c->xg_p;
+    else return c->xg_p32;
+}
+
+template <class PT>
 bool xg_ready(pa_ctx* c)
 {
-    if (!c->xg_p) c->xg_p = (double*)dev_alloc(c, sizeof(double) * c->NT * (kXGroup - 1));
+    PT*& b = xg_bufs<PT>(c);
+    if (!b) b = (PT*)dev_alloc(c, sizeof(PT) * c->NT * (kXGroup - 1));
     if (!c->xg_alpha) c->xg_alpha = (double*)dev_alloc(c, sizeof(double) * kXGroup);
-    return c->xg_p && c->xg_alpha;
+    return b && c->xg_alpha;
 }
 
 // Row form of the Jacobi diagonal (7-point operator, constant coefficient,
@@ -1176,18 +1187,20 @@ JacD jd_of(pa_ctx* c)
     return j;
 }
 
-double* xg_slot(pa_ctx* c, int t)
+template <class PT>
+PT* xg_slot(pa_ctx* c, int t)
 {
-    return t == 0 ? c->xg_p0 : c->xg_p + (size_t)(t - 1) * c->NT;
+    return t == 0 ? (PT*)c->xg_p0 : xg_bufs<PT>(c) + (size_t)(t - 1) * c->NT;
 }
 
 // x += alpha_t p_t over the first `count` slots of the group
+template <class PT>
 void xg_flush(pa_ctx* c, int count)
 {
-    XSlots sl;
-    for (int t = 0; t < kXGroup; ++t) sl.p[t] = xg_slot(c, t);
+    XSlots<PT> sl;
+    for (int t = 0; t < kXGroup; ++t) sl.p[t] = xg_slot<PT>(c, t);
     KScope t(c, PA_K_DIR);
-    launch_pcg_xflush(c->NT, c->u, sl, c->xg_alpha, count, c->stream);
+    launch_pcg_xflush<PT>(c->NT, c->u, sl, c->xg_alpha, count, c->stream);
 }
 
 // Queue n PCG iterations (each skipped on the device once the solve is
@@ -1196,8 +1209,8 @@ void xg_flush(pa_ctx* c, int count)
 // FP32-matvec inner solves); x, r and all scalars are FP64.  Point Jacobi:
 // matvec, alpha, r update, stopping test, then the new direction; x +=
 // alpha p either in the same kernel (p is read once for both; the iteration
-// that stops the solve still applies its x update there) or, for FP64
-// solves with the group buffers, deferred: once per kXGroup iterations,
+// that stops the solve still applies its x update there) or, when the
+// group buffers could be allocated, deferred: once per kXGroup iterations,
 // from the group's directions kept in their own buffers.
 template <class PT>
 void pcg_queue(pa_ctx* c, double dtc, double* r, PT* p, PT* q, int n)
@@ -1213,47 +1226,45 @@ void pcg_queue(pa_ctx* c, double dtc, double* r, PT* p, PT* q, int n)
     double* zb = c->w[0];
     for (int b = 0; b < n; ++b) {
         KArgs<PT> a = base_args<PT>(c, 0, nr);
-        if constexpr (sizeof(PT) == 8) {
-            if (c->xg_on && !bilu0) {
-                // deferred x update: iteration k reads its direction from
-                // group slot k % kXGroup and writes the next one to the
-                // following slot; the group's x update runs after the last
-                // iteration's alpha is known and before its slot is reused
-                const int sl = (int)(c->xg_q % kXGroup);
-                double* pc = xg_slot(c, sl);
-                double* pn = xg_slot(c, (sl + 1) % kXGroup);
-                double* as = c->xg_alpha + sl;
-                a.u = pc;
-                a.out = q;
-                a.affine = 0;
-                a.dt = dtc;
-                a.done = &c->st->done;
-                {
-                    KScope t(c, PA_K_MATVEC);
-                    stencil<PT>(c, kMatvec, false, a);
-                }
-                {
-                    KScope t(c, PA_K_REDUCE);
-                    launch_pcg_alpha(c->part, mt, c->st, c->stream, as);
-                }
-                {
-                    KScope t(c, PA_K_UPDATE);
-                    launch_pcg_update<PT>(c->N, nc, c->Dbuf, nullptr, r, pc, q, c->st, c->part,
-                                          &nparts, c->stream, jd_of(c));
-                }
-                {
-                    KScope t(c, PA_K_REDUCE);
-                    launch_pcg_beta(c->part, nparts, c->st, c->stream, as);
-                }
-                if (sl == kXGroup - 1) xg_flush(c, kXGroup);
-                {
-                    KScope t(c, PA_K_DIR);
-                    launch_pcg_dir_next(c->N, nc, c->Dbuf, r, pc, pn, c->st, c->stream,
-                                        jd_of(c));
-                }
-                ++c->xg_q;
-                continue;
+        if (c->xg_on && !bilu0) {
+            // deferred x update: iteration k reads its direction from
+            // group slot k % kXGroup and writes the next one to the
+            // following slot; the group's x update runs after the last
+            // iteration's alpha is known and before its slot is reused
+            const int sl = (int)(c->xg_q % kXGroup);
+            PT* pc = xg_slot<PT>(c, sl);
+            PT* pn = xg_slot<PT>(c, (sl + 1) % kXGroup);
+            double* as = c->xg_alpha + sl;
+            a.u = pc;
+            a.out = q;
+            a.affine = 0;
+            a.dt = dtc;
+            a.done = &c->st->done;
+            {
+                KScope t(c, PA_K_MATVEC);
+                stencil<PT>(c, kMatvec, false, a);
             }
+            {
+                KScope t(c, PA_K_REDUCE);
+                launch_pcg_alpha(c->part, mt, c->st, c->stream, as);
+            }
+            {
+                KScope t(c, PA_K_UPDATE);
+                launch_pcg_update<PT>(c->N, nc, c->Dbuf, nullptr, r, pc, q, c->st, c->part,
+                                      &nparts, c->stream, jd_of(c));
+            }
+            {
+                KScope t(c, PA_K_REDUCE);
+                launch_pcg_beta(c->part, nparts, c->st, c->stream, as);
+            }
+            if (sl == kXGroup - 1) xg_flush<PT>(c, kXGroup);
+            {
+                KScope t(c, PA_K_DIR);
+                launch_pcg_dir_next<PT>(c->N, nc, c->Dbuf, r, pc, pn, c->st, c->stream,
+                                        jd_of(c));
+            }
+            ++c->xg_q;
+            continue;
         }
         a.u = p;
         a.out = q;
@@ -1315,7 +1326,7 @@ pa_status pcg_loop(pa_ctx* c, double dtc, double* r, PT* p, PT* q)
     const int later = std::max(1, c->opt.pcg_batch / 4);
     // the deferred x updates of a last, incomplete group
     auto finish_x = [&] {
-        if (c->xg_on && c->xg_q % kXGroup) xg_flush(c, (int)(c->xg_q % kXGroup));
+        if (c->xg_on && c->xg_q % kXGroup) xg_flush<PT>(c, (int)(c->xg_q % kXGroup));
     };
     while (true) {
         pcg_queue<PT>(c, dtc, r, p, q, batch);
@@ -1744,7 +1755,7 @@ pa_status pa_advance_be_pcg(pa_ctx* c, double dt, double tol, int32_t cycles, pa
                 if (s) break;
                 bilu0_start<double>(c, dtc, r, p);
             }
-            c->xg_on = !bilu0 && xg_ready(c);
+            c->xg_on = !bilu0 && xg_ready<double>(c);
             c->xg_q = 0;
             c->xg_p0 = p;
             s = pcg_loop<double>(c, dtc, r, p, q);
@@ -1758,12 +1769,18 @@ pa_status pa_advance_be_pcg(pa_ctx* c, double dt, double tol, int32_t cycles, pa
             double* bvec = p;  // b lives in the FP64 direction buffer
             float* p32 = c->f[0];
             float* q32 = c->f[1];
+            c->jd_on = !bilu0 && jd_ready(c);
+            if (c->jd_on) st->jacobi_rows = 1;
             {
                 KScope t(c, PA_K_INIT);
                 if (any_dir) boundary_data(c, q);
+                if (c->jd_on)
+                    launch_jacobi_rows(g, c->cscale, c->d.bc_in, c->d.bc_out, dtc, c->jd_ab,
+                                       c->jd_G, c->stream);
                 launch_pcg_init<float>(g, nc, dtc, c->use_w ? c->w64 : nullptr, c->u, y0,
                                        any_dir ? q : nullptr, c->diagL,
-                                       c->Dbuf, r, p32, bvec, c->part, &nparts, c->stream);
+                                       c->Dbuf, r, p32, bvec, c->part, &nparts, c->stream,
+                                       jd_of(c));
             }
             if (bilu0) {
                 s = bilu0_factor(c, dtc);
@@ -1779,7 +1796,11 @@ pa_status pa_advance_be_pcg(pa_ctx* c, double dt, double tol, int32_t cycles, pa
                 if (bilu0) bilu0_start<float>(c, dtc, r, p32);
                 s = sync_state(c);
                 if (s || c->hst->done) break;
+                c->xg_on = !bilu0 && xg_ready<float>(c);
+                c->xg_q = 0;
+                c->xg_p0 = p32;
                 s = pcg_loop<float>(c, dtc, r, p32, q32);
+                c->xg_on = false;
                 if (s) break;
                 its += c->hst->iters;
                 ++outer;
@@ -1798,6 +1819,7 @@ pa_status pa_advance_be_pcg(pa_ctx* c, double dt, double tol, int32_t cycles, pa
                                             c->stream);
                 }
             }
+            c->jd_on = false;
             if (s) break;
         }
         if (ncyc < PA_MAX_LOG) { st->dt_cycle[ncyc] = dtc; st->per_cycle[ncyc] = its; }

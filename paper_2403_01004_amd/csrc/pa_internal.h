@@ -175,18 +175,21 @@ void launch_pcg_beta(const double* part, int n, DevState* st, hipStream_t s,
 template <class PT>
 void launch_pcg_dir(size_t N, int nc, const double* D, const double* r, double* x, PT* p,
                     const DevState* st, hipStream_t s);
-// Deferred x update (FP64 point-Jacobi solves): the directions of kXGroup
+// Deferred x update (point-Jacobi solves): the directions of kXGroup
 // consecutive iterations live in kXGroup buffers; pn = r/D + beta p while the
 // solve goes on, and x += alpha_t p_t for the group's iterations in order
 // (the arithmetic of launch_pcg_dir, applied per group: x is read and
 // written once per group instead of once per iteration)
 constexpr int kXGroup = 8;   // PA_PCG_XGROUP
+template <class PT>
 struct XSlots {
-    const double* p[kXGroup];
+    const PT* p[kXGroup];
 };
-void launch_pcg_dir_next(size_t N, int nc, const double* D, const double* r, const double* p,
-                         double* pn, const DevState* st, hipStream_t s, const JacD& jd = JacD{});
-void launch_pcg_xflush(size_t n, double* x, const XSlots& sl, const double* ahist, int count,
+template <class PT>
+void launch_pcg_dir_next(size_t N, int nc, const double* D, const double* r, const PT* p, PT* pn,
+                         const DevState* st, hipStream_t s, const JacD& jd = JacD{});
+template <class PT>
+void launch_pcg_xflush(size_t n, double* x, const XSlots<PT>& sl, const double* ahist, int count,
                        hipStream_t s);
 // face couplings L_{m,nb} for nb = r-, r+, t-, t+, p-, p+ into out[6][N]
 // (zero where the neighbour does not exist) (pa_setup.hip)

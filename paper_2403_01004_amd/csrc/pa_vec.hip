@@ -611,13 +611,14 @@ template void launch_pcg_dir<float>(size_t, int, const double*, const double*, d
                                     const DevState*, hipStream_t);
 
 // the direction of the next iteration into its own buffer, pn = r/D + beta p,
-// while the solve goes on; the x update is deferred to k_pcg_xflush (the
-// iteration's alpha recorded by k_pcg_beta)
+// while the solve goes on (the arithmetic of k_pcg_dir); the x update is
+// deferred to k_pcg_xflush (the iteration's alpha recorded by k_pcg_beta)
+template <class PT>
 __global__ __launch_bounds__(kBlock) void k_pcg_dir_next(unsigned N, int nc,
                                                          const double* __restrict__ Db,
                                                          const double* __restrict__ r,
-                                                         const double* __restrict__ p,
-                                                         double* __restrict__ pn,
+                                                         const PT* __restrict__ p,
+                                                         PT* __restrict__ pn,
                                                          const DevState* st, JacD jd)
 {
     if (!st->xpend || st->done) return;
@@ -627,24 +628,32 @@ __global__ __launch_bounds__(kBlock) void k_pcg_dir_next(unsigned N, int nc,
         const double D = jac_d(jd, Db, cell);
         for (int c = 0; c < nc; ++c) {
             const size_t m = (size_t)c * N + cell;
-            stnt(ldnt(r + m) / D + beta * ldnt(p + m), pn + m);
+            stnt((PT)(ldnt(r + m) / D + beta * (double)ldnt(p + m)), pn + m);
         }
     }
 }
 
-void launch_pcg_dir_next(size_t N, int nc, const double* D, const double* r, const double* p,
-                         double* pn, const DevState* st, hipStream_t s, const JacD& jd)
+template <class PT>
+void launch_pcg_dir_next(size_t N, int nc, const double* D, const double* r, const PT* p, PT* pn,
+                         const DevState* st, hipStream_t s, const JacD& jd)
 {
-    hipLaunchKernelGGL(k_pcg_dir_next, dim3(vec_blocks(N)), dim3(kBlock), 0, s, (unsigned)N, nc, D,
-                       r, p, pn, st, jd);
+    hipLaunchKernelGGL((k_pcg_dir_next<PT>), dim3(vec_blocks(N)), dim3(kBlock), 0, s, (unsigned)N,
+                       nc, D, r, p, pn, st, jd);
 }
+template void launch_pcg_dir_next<double>(size_t, int, const double*, const double*,
+                                          const double*, double*, const DevState*, hipStream_t,
+                                          const JacD&);
+template void launch_pcg_dir_next<float>(size_t, int, const double*, const double*, const float*,
+                                         float*, const DevState*, hipStream_t, const JacD&);
 
 // x += alpha_t p_t for t = 0 .. count - 1 in that order, the per-iteration
 // update of k_pcg_dir applied for a group of iterations; a zero alpha (an
 // iteration queued after the solve stopped, or one whose r update did not
 // run) leaves x as it is, so its term is skipped
-__global__ __launch_bounds__(kBlock) void k_pcg_xflush(size_t n, double* __restrict__ x, XSlots sl,
-                                                       const double* ahist, int count)
+template <class PT>
+__global__ __launch_bounds__(kBlock) void k_pcg_xflush(size_t n, double* __restrict__ x,
+                                                       XSlots<PT> sl, const double* ahist,
+                                                       int count)
 {
     double a[kXGroup];
     bool any = false;
@@ -659,17 +668,22 @@ __global__ __launch_bounds__(kBlock) void k_pcg_xflush(size_t n, double* __restr
         double xv = ldnt(x + m);
 #pragma unroll
         for (int t = 0; t < kXGroup; ++t)
-            if (a[t] != 0.0) xv = xv + a[t] * ldnt(sl.p[t] + m);
+            if (a[t] != 0.0) xv = xv + a[t] * (double)ldnt(sl.p[t] + m);
         stnt(xv, x + m);
     }
 }
 
-void launch_pcg_xflush(size_t n, double* x, const XSlots& sl, const double* ahist, int count,
+template <class PT>
+void launch_pcg_xflush(size_t n, double* x, const XSlots<PT>& sl, const double* ahist, int count,
                        hipStream_t s)
 {
-    hipLaunchKernelGGL(k_pcg_xflush, dim3(vec_blocks(n)), dim3(kBlock), 0, s, n, x, sl, ahist,
+    hipLaunchKernelGGL((k_pcg_xflush<PT>), dim3(vec_blocks(n)), dim3(kBlock), 0, s, n, x, sl, ahist,
                        count);
 }
+template void launch_pcg_xflush<double>(size_t, double*, const XSlots<double>&, const double*, int,
+                                        hipStream_t);
+template void launch_pcg_xflush<float>(size_t, double*, const XSlots<float>&, const double*, int,
+                                       hipStream_t);
 
 // p = z + beta p while the solve goes on, with z the preconditioned
 // residual stored by a block preconditioner (all components, n = nc * N
