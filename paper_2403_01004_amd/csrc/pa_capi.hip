@@ -197,7 +197,12 @@ void* dev_alloc(pa_ctx* c, size_t bytes)
     void* p = nullptr;
     if (bytes == 0) bytes = 16;
     if (c->d.alloc) p = c->d.alloc(bytes, c->d.alloc_user);
-    else if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
+    else if (hipMalloc(&p, bytes) != hipSuccess) {
+        p = nullptr;
+        // the caller reports the failure (or falls back, for the lazy
+        // buffers of a solve): leave no error behind for the launch checks
+        (void)hipGetLastError();
+    }
     if (p) c->allocs.push_back(p);
     return p;
 }

@@ -129,3 +129,31 @@ def test_torch_allocator(dev, name):
     torch.cuda.synchronize()
     assert torch.cuda.memory_allocated() == base
     assert np.array_equal(outs[0], outs[1])
+
+
+def test_be_without_lazy_buffers(dev):
+    """When the deferred x update's direction buffers and the row terms of
+    the Jacobi diagonal cannot be allocated (every allocation after set-up
+    fails), a BE advance still runs: x is updated in place every iteration
+    and D is read per cell.  Its result matches the ordinary run's (same
+    method, D equal up to rounding)."""
+    import torch
+    prob = inputs.viscosity(9, 10, 13, seed=37, vector=True)
+    a = CountingAllocator(torch, 10 ** 6)
+    g = dev.Operator.from_problem(prob, allocator=(a.alloc, a.free))
+    a.ok = a.calls          # every later allocation fails
+    dt = 30.0 * g.dt_explicit()
+    u = g.bind(prob.u)
+    st = g.advance_be(dt, 1e-13, 1)
+    assert a.calls > a.ok   # the lazy allocations were tried
+    assert not st["jacobi_rows"]
+    ref = dev.Operator.from_problem(prob)
+    v = ref.bind(prob.u)
+    sr = ref.advance_be(dt, 1e-13, 1)
+    assert sr["jacobi_rows"]
+    assert abs(st["iters_total"] - sr["iters_total"]) <= 2
+    x, y = u.cpu().numpy(), v.cpu().numpy()
+    assert np.linalg.norm(x - y) <= 1e-12 * np.linalg.norm(y)
+    del g, u, ref, v
+    gc.collect()
+    assert not a.live

@@ -62,7 +62,7 @@ def test_fp32_sts(dev, oracle_mod, kind, shape, sts):
     g.set_options()
 
 
-@pytest.mark.parametrize("kind,shape", CASES[:3])
+@pytest.mark.parametrize("kind,shape", CASES[:3] + [CASES[4]])
 def test_fp32_matvec_be(dev, oracle_mod, kind, shape):
     """BE with FP32 matvecs inside an FP64 defect correction: the FP64 true
     residual of the result, evaluated with the oracle's operator, meets the
@@ -82,6 +82,8 @@ def test_fp32_matvec_be(dev, oracle_mod, kind, shape):
     assert res <= 1.001e-10, res
     assert rel_l2(x, uo) <= 1e-8
     assert st["rel_residual"] <= 1e-10
+    # constant viscosity: the Jacobi diagonal comes from per-(r, theta) row terms
+    assert st["jacobi_rows"] == (kind in ("visc", "viscv"))
     # the inner iterations cost at most a little more than plain FP64 PCG
     assert st["iters_total"] <= 2 * so["iters_total"] + 10
 
