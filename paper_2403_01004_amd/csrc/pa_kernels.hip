@@ -889,10 +889,15 @@ struct ShV {
     T gr[RCH_MAX + 3], gtr[RCH_MAX + 3], vr[RCH_MAX + 3];
 };
 
-// row a of the change of basis for the faces theta-, theta+, phi-, phi+
+// row a of the change of basis for the faces theta-, theta+, phi-, phi+.
+// A colatitude rotation (about phi-hat) leaves the phi component alone and
+// mixes only r and theta, so its row has two entries, on components ta and
+// tb (0 and 1 for a = 0, 1; 2 and 2 with weights 1, 0 for a = 2)
 template <class T>
 struct RowsV {
-    T q[4][3];
+    T t[2][2];
+    T q[2][3];
+    int ta, tb;
 };
 
 template <class T>
@@ -903,10 +908,11 @@ __device__ __forceinline__ RowsV<T> rows_viscv(const Geo<T>& g, int a, int j, in
     // colatitude faces j (neighbour j-1, angle -D_j) and j+1 (angle D_{j+1})
     const T ct[2] = {g.rtf[j], g.rtf[j + 1]};
     const T st[2] = {-g.rtf[nt + 1 + j], g.rtf[nt + 1 + j + 1]};
+    R.ta = a == 2 ? 2 : 0;
+    R.tb = a == 2 ? 2 : 1;
     for (int f = 0; f < 2; ++f) {
-        R.q[f][0] = a == 0 ? ct[f] : a == 1 ? st[f] : T(0);
-        R.q[f][1] = a == 0 ? -st[f] : a == 1 ? ct[f] : T(0);
-        R.q[f][2] = a == 2 ? T(1) : T(0);
+        R.t[f][0] = a == 0 ? ct[f] : a == 1 ? st[f] : T(1);
+        R.t[f][1] = a == 0 ? -st[f] : a == 1 ? ct[f] : T(0);
     }
     // longitude faces k (neighbour k-1, angle -d_k) and kp (angle d_kp)
     const T s = g.rtc[j], c = g.rtc[nt + j];
@@ -914,9 +920,9 @@ __device__ __forceinline__ RowsV<T> rows_viscv(const Geo<T>& g, int a, int j, in
     const T sd[2] = {-g.rpf[np + k], g.rpf[np + kp]};
     for (int f = 0; f < 2; ++f) {
         const T q = qd[f], d = sd[f];
-        R.q[2 + f][0] = a == 0 ? T(1) - s * s * q : a == 1 ? -s * c * q : s * d;
-        R.q[2 + f][1] = a == 0 ? -s * c * q : a == 1 ? T(1) - c * c * q : c * d;
-        R.q[2 + f][2] = a == 0 ? -s * d : a == 1 ? -c * d : T(1) - q;
+        R.q[f][0] = a == 0 ? T(1) - s * s * q : a == 1 ? -s * c * q : s * d;
+        R.q[f][1] = a == 0 ? -s * c * q : a == 1 ? T(1) - c * c * q : c * d;
+        R.q[f][2] = a == 0 ? -s * d : a == 1 ? -c * d : T(1) - q;
     }
     return R;
 }
@@ -950,11 +956,13 @@ __device__ __forceinline__ void stepV(const Geo<T>& g, const KArgs<T>& a, const 
     const T* s0 = sh.su[b][0];
     const T* s1 = sh.su[b][1];
     const T* s2 = sh.su[b][2];
+    const T* sa = sh.su[b][Q.ta];
+    const T* sb = sh.su[b][Q.tb];
     // the in-plane neighbours' vectors in this cell's basis, component comp
-    const T us = Q.q[0][0] * s0[o - HX] + Q.q[0][1] * s1[o - HX] + Q.q[0][2] * s2[o - HX];
-    const T un = Q.q[1][0] * s0[o + HX] + Q.q[1][1] * s1[o + HX] + Q.q[1][2] * s2[o + HX];
-    const T uw = Q.q[2][0] * s0[o - 1] + Q.q[2][1] * s1[o - 1] + Q.q[2][2] * s2[o - 1];
-    const T ue = Q.q[3][0] * s0[o + 1] + Q.q[3][1] * s1[o + 1] + Q.q[3][2] * s2[o + 1];
+    const T us = Q.t[0][0] * sa[o - HX] + Q.t[0][1] * sb[o - HX];
+    const T un = Q.t[1][0] * sa[o + HX] + Q.t[1][1] * sb[o + HX];
+    const T uw = Q.q[0][0] * s0[o - 1] + Q.q[0][1] * s1[o - 1] + Q.q[0][2] * s2[o - 1];
+    const T ue = Q.q[1][0] * s0[o + 1] + Q.q[1][1] * s1[o + 1] + Q.q[1][2] * s2[o + 1];
     const T uc = Rc.x;
     const T cc = CV ? Rc.cx : a.cs;
     T cw = a.cs, ce = a.cs, cs_ = a.cs, cn = a.cs;
