@@ -196,12 +196,17 @@ void* dev_alloc(pa_ctx* c, size_t bytes)
 {
     void* p = nullptr;
     if (bytes == 0) bytes = 16;
-    if (c->d.alloc) p = c->d.alloc(bytes, c->d.alloc_user);
-    else if (hipMalloc(&p, bytes) != hipSuccess) {
-        p = nullptr;
-        // the caller reports the failure (or falls back, for the lazy
-        // buffers of a solve): leave no error behind for the launch checks
-        (void)hipGetLastError();
+    if (c->d.alloc) {
+        p = c->d.alloc(bytes, c->d.alloc_user);
+    } else {
+        const hipError_t before = hipPeekAtLastError();
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            p = nullptr;
+            // the caller reports the failure (or falls back, for the lazy
+            // buffers of a solve): drop the allocation's own error so that
+            // the launch checks do not see it, but keep an earlier one
+            if (before == hipSuccess) (void)hipGetLastError();
+        }
     }
     if (p) c->allocs.push_back(p);
     return p;
