@@ -312,24 +312,29 @@ static int vec_blocks(size_t n)
     return (int)((n + 2 * kBlock - 1) / (2 * kBlock));
 }
 
-// deterministic per-block sums of up to 3 accumulators into part[q*nb + b]
+// deterministic per-block sums of up to 3 accumulators into part[q*nb + b]:
+// every wave's sums go to LDS together, one barrier, then thread 0 adds
+// the waves' values in order (called once per kernel: nothing waits for
+// thread 0 to finish reading the LDS)
 template <int NV>
 __device__ __forceinline__ void block_partials(const double (&v)[NV], double* part)
 {
-    __shared__ double lds[kBlock / 64];
+    __shared__ double lds[NV][kBlock / 64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double x[NV];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) {
-        const double x = wsum(v[q]);
-        __syncthreads();
-        if (lane == 0) lds[w] = x;
-        __syncthreads();
-        if (threadIdx.x == 0) {
+    for (int q = 0; q < NV; ++q) x[q] = wsum(v[q]);
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) lds[q][w] = x[q];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
             double sacc = 0.0;
-            for (int t = 0; t < kBlock / 64; ++t) sacc += lds[t];
+            for (int t = 0; t < kBlock / 64; ++t) sacc += lds[q][t];
             part[(size_t)q * gridDim.x + blockIdx.x] = sacc;
         }
-    }
 }
 
 // Start of a Backward Euler solve, per cell (all components):
