@@ -10,6 +10,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -1320,14 +1321,29 @@ void pcg_queue(pa_ctx* c, double dtc, double* r, PT* p, PT* q, int n)
     }
 }
 
+// Iterations still needed, estimated from the residual decrease so far
+// (the mean contraction of ||r||^2 per iteration carried on to the stopping
+// level); `fallback` when there is nothing to go on
+int pcg_remaining(const DevState* h, int fallback)
+{
+    double target = h->tol * h->tol * h->bb;
+    if (h->mode == 1) target = std::max(target, h->eta * h->eta * h->rr0);
+    if (h->iters <= 0 || !(target > 0.0) || !(h->rr > target) || !(h->rr < h->rr0))
+        return fallback;
+    const double per_iter = std::log(h->rr / h->rr0) / h->iters;   // < 0
+    const double n = std::ceil(std::log(target / h->rr) / per_iter);
+    return n < 1.0 ? 1 : n > 1e6 ? 1000000 : (int)n;
+}
+
 // One PCG solve of M d = r0 from the state queued by launch_pcg_init /
 // launch_pcg_resid + launch_pcg_start: iterations are queued in batches and
-// the host reads the device state after each batch.  The first batch is the iteration count of the previous solve on the
-// context (the solves of a PTL-cycled advance take similar counts), capped
-// at pcg_batch; later batches are a quarter of pcg_batch.  Iterations queued
-// after the solve stopped exit at once but still cost their launches, so
-// a close first guess saves most of them at the price of a few more host
-// checks.
+// the host reads the device state after each batch.  The first batch is the
+// iteration count of the previous solve on the context (the solves of a
+// PTL-cycled advance take similar counts), capped at pcg_batch; a later
+// batch is the estimate of pcg_remaining, capped at pcg_batch.  Iterations
+// queued after the solve stopped exit at once but still cost their
+// launches, and each batch costs a host check; the batching never changes
+// the result.
 template <class PT>
 pa_status pcg_loop(pa_ctx* c, double dtc, double* r, PT* p, PT* q)
 {
@@ -1350,7 +1366,8 @@ pa_status pcg_loop(pa_ctx* c, double dtc, double* r, PT* p, PT* q)
             c->pcg_hint = c->hst->iters;
             return PA_OK;
         }
-        batch = later;
+        batch = c->opt.force_iters > 0 ? later
+                                        : std::min(c->opt.pcg_batch, pcg_remaining(c->hst, later));
     }
 }
 
