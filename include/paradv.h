@@ -131,7 +131,9 @@ typedef struct {
     int32_t force_iters;  /* >0: run exactly this many PCG iterations per solve. default 0 */
     int32_t pcg_batch;    /* most PCG iterations queued between host checks (the first
                              batch of a solve follows the previous solve's count, later
-                             ones are a quarter of this). default 16 */
+                             ones the iterations the residual decrease so far predicts;
+                             a quarter of this under force_iters); results do not
+                             depend on it. default 16 */
     int32_t replay_n;     /* >0: cycle lengths taken from replay_dt (parity replays) */
     const double* replay_dt; /* host, replay_n entries; copied by pa_set_options */
     double ptl_floor;     /* limit used = max(dt_PTL, ptl_floor * dt_E). default 1.0 */
