@@ -523,10 +523,19 @@ __device__ __forceinline__ void stepT(const Geo<T>& g, const KArgs<T>& a, const 
     const T uu = hi ? Rn.x : t.ubu;
     T Lu = Cl * (uc - ul);
     Lu += Cu * (uc - uu);
-    Lu += half * (cc + cs_) * (gtri * t.As) * (uc - us);
-    Lu += half * (cc + cn) * (gtri * t.An) * (uc - un);
-    Lu += half * (cc + cw) * (gtri * t.Aw) * (uc - uw);
-    Lu += half * (cc + ce) * (gtri * t.Ae) * (uc - ue);
+    if constexpr (CV) {
+        Lu += half * (cc + cs_) * (gtri * t.As) * (uc - us);
+        Lu += half * (cc + cn) * (gtri * t.An) * (uc - un);
+        Lu += half * (cc + cw) * (gtri * t.Aw) * (uc - uw);
+        Lu += half * (cc + ce) * (gtri * t.Ae) * (uc - ue);
+    } else {
+        // one coefficient for the four in-plane faces: factored out
+        T inp = t.As * (uc - us);
+        inp += t.An * (uc - un);
+        inp += t.Aw * (uc - uw);
+        inp += t.Ae * (uc - ue);
+        Lu += (a.cs * gtri) * inp;
+    }
     const T V = WT ? sh.vr[il] * t.Ar * Rc.wt : sh.vr[il] * t.Ar;  // (w) V
     if (t.valid && i < i1) epilogue<T, MODE>(a, cb + (size_t)ic * P + tm.own_off, Lu, V, uc, Rc.st, acc);
     um = uc;
@@ -985,10 +994,19 @@ __device__ __forceinline__ void stepV(const Geo<T>& g, const KArgs<T>& a, const 
     const T uu = hi ? Rn.x : t.ubu;
     T Lu = Cl * (uc - ul);
     Lu += Cu * (uc - uu);
-    Lu += half * (cc + cs_) * (gtri * t.As) * (uc - us);
-    Lu += half * (cc + cn) * (gtri * t.An) * (uc - un);
-    Lu += half * (cc + cw) * (gtri * t.Aw) * (uc - uw);
-    Lu += half * (cc + ce) * (gtri * t.Ae) * (uc - ue);
+    if constexpr (CV) {
+        Lu += half * (cc + cs_) * (gtri * t.As) * (uc - us);
+        Lu += half * (cc + cn) * (gtri * t.An) * (uc - un);
+        Lu += half * (cc + cw) * (gtri * t.Aw) * (uc - uw);
+        Lu += half * (cc + ce) * (gtri * t.Ae) * (uc - ue);
+    } else {
+        // one coefficient for the four in-plane faces: factored out
+        T inp = t.As * (uc - us);
+        inp += t.An * (uc - un);
+        inp += t.Aw * (uc - uw);
+        inp += t.Ae * (uc - ue);
+        Lu += (a.cs * gtri) * inp;
+    }
     const T V = WT ? sh.vr[il] * t.Ar * Rc.wt : sh.vr[il] * t.Ar;  // (w) V
     if (t.valid && i < i1 && (a.only_c < 0 || a.only_c == comp))
         epilogue<T, MODE>(a, cb + (size_t)ic * P + tm.own_off, Lu, V, uc, Rc.st, acc);
